@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact all-pairs Jaccard hot path on one MI355X.
+
+One step = jas_encode (stage/validate, sort + dedup, compaction, batches, pack,
+column sums) + jas_gram (packed-tile popcount Gram, row-list pairs, diagonal,
+unions, J) over one synthetic collection that is already resident in HBM.
+Prints one JSON line (see the design doc for every field).
+
+  python bench.py [--steps K] [--warmup W] [--workload paperlike]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(kernel: str) -> str:
+    src = {"radix_scatter": "radix.hip", "radix_hist": "radix.hip", "gram_popc": "gram.hip",
+           "cls_count": "encode.hip", "cls_write": "encode.hip", "pack": "encode.hip",
+           "build_keys": "encode.hip"}.get(kernel)
+    if src is None:
+        return ""
+    h = hashlib.sha256()
+    for f in (src, "device_util.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1911_04200_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
+    """(bound, algorithmic amount per launch, unit, per-unit description) of a kernel."""
+    if kernel == "radix_scatter":
+        return "hbm", 16.0 * N / 1e9, "GB/s", "16 B per key per pass (read 8 + write 8)"
+    if kernel == "radix_hist":
+        return "hbm", 8.0 * N / 1e9, "GB/s", "8 B per key per pass (read)"
+    if kernel == "build_keys":
+        return "hbm", 16.0 * N / 1e9, "GB/s", "16 B per entry (read ID 8 + write key 8)"
+    if kernel == "cls_count":
+        return "hbm", 8.0 * N / 1e9, "GB/s", "8 B per sorted key (read)"
+    if kernel == "cls_write":
+        return ("hbm", (8.0 * N + 4.0 * stats["n_pairs"] + 16.0 * stats["n_shared_rows"]) / 1e9, "GB/s",
+                "8 B per key read + 4 B per shared pair + 16 B per shared row written")
+    if kernel == "pack":
+        ldw = math.ceil(n / 128) * 128
+        return "hbm", 8.0 * stats["n_word_rows"] * ldw / 1e9, "GB/s", "8 B per packed word written"
+    if kernel == "gram_popc":
+        nt = math.ceil(n / 128)
+        wp = stats["n_word_rows"] * (nt * (nt + 1) // 2) * 128 * 128
+        return "alu", 4.0 * wp / 1e12, "TOP/s", "4 VALU lane-ops per 64-bit word pair (2 AND + 2 popcount-add)"
+    return None
+
+
+def cpu_baseline(spec, k: int, seed: int = 5):
+    """The oracle timed on a bounded sample: k sets of the workload, all k(k+1)/2 pairs."""
+    import numpy as np
+
+    import oracle
+    import synth
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(spec.n, size=min(k, spec.n), replace=False))
+    ids, off = synth.generate_samples(spec, idx)
+    t0 = time.perf_counter()
+    s, so = oracle.normalize(ids, off)
+    t1 = time.perf_counter()
+    kk = idx.size
+    iu, ju = np.triu_indices(kk)
+    oracle.pairs_normalized(s, so, s, so, iu, ju)
+    t2 = time.perf_counter()
+    t_set = (t1 - t0) / kk
+    t_pair = (t2 - t1) / iu.size
+    n = spec.n
+    full_pairs = n * (n + 1) // 2
+    projected = full_pairs / (n * t_set + full_pairs * t_pair)
+    return {"value": projected, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": (f"{kk} of the {n} sets ({int(off[-1])} IDs), all {iu.size} pairs: set build "
+                       f"{t1 - t0:.2f} s, pair merges {t2 - t1:.2f} s on {oracle.threads()} threads; value = "
+                       f"n(n+1)/2 / (n * per-set + n(n+1)/2 * per-pair time) for the full n={n}")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="paperlike", choices=["tiny", "paperlike", "precision", "batching"])
+    ap.add_argument("--dmin", type=int, default=0, help="dense_min_degree (0: library default)")
+    ap.add_argument("--upper", action="store_true", help="packed upper-triangle outputs")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="sets in the oracle's timed sample (0: skip)")
+    ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing in the timed region")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1911_04200_amd as jas
+    from paper_1911_04200_amd import jas as cabi
+
+    spec = synth.workload(args.workload)
+    bb = synth.BATCH_BITS[args.workload]
+    n = spec.n
+    off = synth.offsets(spec)
+    N = int(off[-1])
+    log(f"[bench] workload {args.workload}: n={n} U={spec.universe_bits} N={N} ids, batch 2^{bb}")
+    t = time.perf_counter()
+    host = torch.empty(N, dtype=torch.int64, pin_memory=True)
+    ids_np = host.numpy().view(np.uint64)
+    synth.generate(spec, out=ids_np)
+    log(f"[bench] generated in {time.perf_counter() - t:.1f} s")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    ids_d = host.to(dev, non_blocking=False)
+    off_d = torch.from_numpy(off.view(np.int64)).to(dev)
+    del host, ids_np
+    torch.cuda.synchronize()
+    log("[bench] inputs resident in HBM")
+
+    stream = torch.cuda.current_stream()
+    length = n * (n + 1) // 2 if args.upper else n * n
+    B = torch.empty(length, dtype=torch.int32, device=dev)
+    card = torch.empty(n, dtype=torch.int64, device=dev)
+    den = torch.empty(length, dtype=torch.int64, device=dev)
+    J = torch.empty(length, dtype=torch.float64, device=dev)
+    opts = cabi.jas_encode_opts(spec.universe_bits, bb, args.dmin, 0, 0)
+    flags = cabi.JAS_UPPER if args.upper else 0
+
+    def step():
+        db, st = cabi.jas_encode(ids_d, off_d, n, opts, stream)
+        cabi.jas_gram(db, flags, stream, B, card, den, J)
+        db.close()
+        return st
+
+    for w in range(args.warmup):
+        st = step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    if args.timing:
+        cabi.jas_timing_enable(True)
+        cabi.jas_timing_report()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = cabi.jas_timing_report() if args.timing else {}
+    cabi.jas_timing_enable(False)
+    log(f"[bench] {args.steps} timed steps done")
+    sec = (t1 - t0) / args.steps
+    pairs = n * (n + 1) // 2
+    value = pairs / sec
+
+    # the dominant kernel and its roofline
+    roof = None
+    passes = math.ceil(spec.universe_bits / 8)
+    kernels = {name: {"launches": c, "ms_per_step": ms / args.steps, "ms_per_launch": ms / max(c, 1)}
+               for name, (c, ms) in kt.items()}
+    if kt:
+        dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
+        c, ms = kt[dom]
+        alg = algorithmic(dom, st, n, N, passes)
+        if alg:
+            bound, amount, unit, desc = alg
+            avg_s = ms / c / 1e3
+            achieved = amount / avg_s
+            peak = HBM_PEAK_GBS if bound == "hbm" else VALU_PEAK_TOPS
+            traffic = None
+            tf = os.path.join(ROOT, "profiles", "traffic.json")
+            if os.path.exists(tf):
+                rec = json.load(open(tf)).get(f"{dom}:{args.workload}")
+                if rec and rec.get("source_hash") == kernel_source_hash(dom):
+                    traffic = rec.get("bytes_per_launch")
+            roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                    "frac": achieved / peak, "traffic": traffic, "per_launch": desc,
+                    "avg_launch_ms": ms / c}
+    # word-pair rates of the popcount Gram
+    gram_ms = kt.get("gram_popc", (0, 0.0))[1] / max(args.steps, 1)
+    nt = math.ceil(n / 128)
+    executed = st["n_word_rows"] * (nt * (nt + 1) // 2) * 128 * 128
+    extra = {"gram_ms": gram_ms,
+             "G_bit_ANDs_per_s_executed": (64.0 * executed / (gram_ms / 1e3) / 1e9) if gram_ms else None,
+             "G_bit_ANDs_per_s_algorithmic_F": (64.0 * st["word_pairs_F"] / (gram_ms / 1e3) / 1e9) if gram_ms
+             else None,
+             "encode_stats": st, "kernels": kernels}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        log("[bench] timing the oracle on a sample")
+        cpu = cpu_baseline(spec, args.cpu_sample)
+
+    out = {"metric": "sample-pair intersections/s (exact B, C, J of all pairs i <= j)",
+           "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64 keys / i32 counts / f64 J", "data": "synthetic (seeded generator, see DESIGN.md)",
+           "config": {"workload": f"{args.workload}_n{n}_u{spec.universe_bits}", "n": n,
+                      "universe_bits": spec.universe_bits, "batch_rows": f"2^{bb}", "ids": N,
+                      "pairs_per_step": pairs, "layout": "upper" if args.upper else "full",
+                      "dense_min_degree": args.dmin},
+           "roofline": roof, "cpu_baseline": cpu, "detail": extra}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

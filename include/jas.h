@@ -1,0 +1,179 @@
+/*
+ * jas.h -- C ABI of libjas: exact all-pairs Jaccard similarity of n sets on
+ * one AMD MI355X (gfx950), computed as in SimilarityAtScale (arXiv 1911.04200).
+ *
+ * Problem (Sec. II-A, Eq. (1)): n samples X_1..X_n, each a set of integer IDs;
+ * for every pair, J(X_i, X_j) = |X_i cap X_j| / |X_i cup X_j|, and J = 1 when
+ * both sets are empty.  IDs here are 0-based integers in [0, 2^U) (the paper's
+ * "positive integers up to m" relabelled).
+ *
+ * Method (Sec. III-A/B): with the indicator matrix A (a_ki = 1 iff k in X_i),
+ * B = A^T A holds the intersection sizes, C_ij = |X_i| + |X_j| - B_ij the union
+ * sizes and S = B / C the similarities (Eq. (2)).  A is cut into row batches of
+ * m~ = 2^batch_bits IDs (Eq. (3)), zero rows are filtered and the rest compacted
+ * (Eqs. (5), (6)), 64 consecutive rows of a column are packed into one bitmask
+ * word (Sec. III-B), and B accumulates popcount(word_i AND word_j) over words
+ * and batches (Eqs. (4), (7)).
+ *
+ * Conventions shared by every call:
+ *  - Pointers are DEVICE pointers unless a call's flags include JAS_HOST_PTRS.
+ *    The caller owns every input and output buffer.
+ *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream).
+ *    Outputs are valid once that stream has completed; inputs must stay alive
+ *    until then.  Calls may synchronise `hip_stream` where noted.
+ *  - Every call returns a jas_status.  On failure, jas_last_error() gives a
+ *    message (thread-local, valid until this thread's next jas_* call) and the
+ *    contents of output buffers are unspecified.  Argument errors are detected
+ *    on the host before any work is enqueued.  No C++ exception crosses the ABI.
+ *  - Row-major outputs: entry (i, j) of an n x n result is at i*n + j.  The
+ *    packed upper layout (JAS_UPPER) stores row i's entries j >= i back to back:
+ *    (i, j) is at i*n - i*(i-1)/2 + (j - i).
+ */
+#ifndef JAS_H
+#define JAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    JAS_OK = 0,
+    JAS_EINVAL = -1,       /* bad argument (null pointer, bad offsets, ID >= 2^U, ...) */
+    JAS_ENOMEM = -2,       /* device allocation failed or the HBM budget is exceeded */
+    JAS_EOVERFLOW = -3,    /* a set has 2^31 or more distinct IDs (int32 B would overflow) */
+    JAS_EDEVICE = -4,      /* a HIP runtime call failed (message names it) */
+    JAS_EUNSUPPORTED = -6  /* valid request this build does not support (message says why) */
+} jas_status;
+
+/* ---- flags ---------------------------------------------------------------- */
+#define JAS_HOST_PTRS 0x1u      /* set arrays / outputs are host memory */
+#define JAS_KEEP_IDS 0x2u       /* jas_encode: keep the row index needed by jas_query */
+#define JAS_UPPER 0x10u         /* jas_gram: outputs in the packed upper layout (j >= i) */
+#define JAS_FORCE_POPCOUNT 0x20u /* jas_gram: every packed tile on the AND+popcount kernel */
+#define JAS_FORCE_MFMA 0x40u    /* jas_gram: every packed tile on the int8 MFMA kernel */
+
+typedef struct jas_db jas_db; /* opaque, library-owned, device-resident encoding of A */
+
+typedef struct {
+    uint32_t universe_bits;    /* U, 1..63: every ID is < 2^U; U + ceil(log2 n) <= 64 */
+    uint32_t batch_bits;       /* log2 of the row-batch height m~ (Eq. (3)); 0 or >= U: one batch */
+    uint32_t dense_min_degree; /* rows shared by >= this many sets are bit-packed (Sec. III-B);
+                                  rows shared by 2..this-1 sets are kept as plain row lists;
+                                  0 = library default; 2 = pack every shared row */
+    uint32_t flags;            /* JAS_HOST_PTRS, JAS_KEEP_IDS */
+    uint64_t hbm_budget_bytes; /* cap on device memory this call may hold at once; 0 = none */
+} jas_encode_opts;
+
+typedef struct {
+    uint64_t n_ids;         /* N: input entries, repeats included */
+    uint64_t n_pairs;       /* nnz(A): distinct (ID, sample) pairs */
+    uint64_t n_rows;        /* nonzero rows of A (distinct IDs), the filter's support (Eq. (5)) */
+    uint64_t n_shared_rows; /* rows in >= 2 sets (the only rows off-diagonal B depends on) */
+    uint64_t n_packed_rows; /* rows bit-packed (degree >= dense_min_degree) */
+    uint64_t n_list_rows;   /* rows kept as row lists (2 <= degree < dense_min_degree) */
+    uint64_t n_batches;     /* row batches holding at least one packed row */
+    uint64_t n_word_rows;   /* H: 64-row word rows of the packed matrix */
+    uint64_t nnz_words;     /* nonzero packed words */
+    uint64_t word_pairs_F;  /* sum over word rows of z(z+1)/2, z = nonzero words in the row */
+    uint64_t list_pairs;    /* sum over list rows of d(d-1)/2 (pair increments of the list path) */
+    uint64_t device_bytes;  /* device memory the db holds */
+} jas_encode_stats;
+
+/*
+ * jas_encode -- build the encoded indicator matrix of n sets (Sec. III-B,
+ * Eqs. (3)-(6) and the bitmask compression before Eq. (7)).
+ *
+ *  ids      uint64[offsets[n]]: the IDs of sample i are ids[offsets[i] .. offsets[i+1]),
+ *           any order, repeats allowed (a set: repeats are ignored).
+ *  offsets  uint64[n+1]: offsets[0] = 0, non-decreasing.
+ *  n        number of samples, >= 0.
+ *  opts     see jas_encode_opts (required).
+ *  db_out   receives the handle; NULL on failure.  Free with jas_db_free.
+ *  stats    optional (NULL allowed).
+ * Errors: EINVAL (null pointers, offsets[0] != 0, decreasing offsets, an ID >= 2^U,
+ * U out of range), EOVERFLOW (a set with >= 2^31 distinct IDs), ENOMEM, EDEVICE.
+ * Synchronises hip_stream (the sizes of the encoding are data-dependent).
+ * The input arrays are not modified and may be freed after the call returns.
+ */
+jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, const jas_encode_opts *opts,
+                      void *hip_stream, jas_db **db_out, jas_encode_stats *stats);
+
+/*
+ * jas_gram -- the Gram product and the similarity of every pair of encoded
+ * samples: B = A^T A accumulated as in Eqs. (4) and (7), the unions
+ * C_ij = |X_i| + |X_j| - B_ij and J_ij = B_ij / C_ij (Sec. III-A, Eq. (2)).
+ *
+ *  B     int32[n*n] (or n(n+1)/2 with JAS_UPPER): B_ij = |X_i cap X_j|; required.
+ *  card  int64[n]: |X_i|; may be NULL.
+ *  den   int64, same layout as B: C_ij = |X_i cup X_j|; may be NULL.
+ *  J     double, same layout as B: C_ij == 0 ? 1.0 : (double)B_ij / (double)C_ij,
+ *        IEEE binary64 round-to-nearest; may be NULL.
+ *  flags JAS_UPPER, JAS_FORCE_POPCOUNT / JAS_FORCE_MFMA (at most one), JAS_HOST_PTRS.
+ * The result does not depend on flags other than the layout: every tile path
+ * is exact.  Does not synchronise unless JAS_HOST_PTRS is given.
+ */
+jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t *B, int64_t *card, int64_t *den,
+                    double *J);
+
+/*
+ * jas_query -- similarity of nq query sets against every encoded sample:
+ * Eq. (1) with i ranging over the queries and j over the database.
+ *
+ *  q_ids, q_offsets  CSR query sets, as in jas_encode (IDs < 2^U, else EINVAL;
+ *                    repeats ignored).  An ID absent from the database counts
+ *                    toward |Q| only.
+ *  B      int32[nq*n]: |Q_q cap X_j|, row-major; required.
+ *  q_card int64[nq]: |Q_q| (distinct); may be NULL.
+ *  den    int64[nq*n]: |Q_q cup X_j|; may be NULL.
+ *  J      double[nq*n]; may be NULL.
+ * Requires a db encoded with JAS_KEEP_IDS (else EINVAL).  The db is read only:
+ * concurrent jas_query calls on different streams are safe.  Synchronises
+ * hip_stream (query sizes and the ID range check are read back).
+ */
+jas_status jas_query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq,
+                     uint32_t flags, void *hip_stream, int32_t *B, int64_t *q_card, int64_t *den, double *J);
+
+/* Device bytes jas_query allocates for nq queries with n_q_ids entries in total
+ * (for admission control by an HBM budget). */
+uint64_t jas_query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids);
+
+/* Number of samples n of the db (-1 for NULL). */
+int32_t jas_db_size(const jas_db *db);
+
+/* Statistics recorded by jas_encode.  Returns EINVAL for NULL arguments. */
+jas_status jas_db_stats(const jas_db *db, jas_encode_stats *stats);
+
+/* Frees the db and its device memory (synchronises the device first). NULL is a no-op. */
+void jas_db_free(jas_db *db);
+
+/* Message of the last failing jas_* call on this thread ("" if none). */
+const char *jas_last_error(void);
+
+/* Library version string. */
+const char *jas_version(void);
+
+/*
+ * Per-kernel timing (tracing).  While enabled, the library records a HIP event
+ * before and after every kernel it launches, on the stream it launches the
+ * kernel on, and jas_timing_report waits for those events and returns the
+ * elapsed time summed by kernel name.  Process-wide; off by default.
+ */
+typedef struct {
+    const char *name;  /* static string, valid for the life of the library */
+    uint64_t launches;
+    double total_ms;
+} jas_kernel_time;
+
+void jas_timing_enable(int32_t on);
+/* Fills up to cap entries (largest total first), returns the number of kernels
+ * timed since the last reset, and resets the totals.  Synchronises on the
+ * recorded events. */
+int32_t jas_timing_report(jas_kernel_time *out, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JAS_H */

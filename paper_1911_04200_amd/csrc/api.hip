@@ -1,0 +1,288 @@
+// The C entry points of libjas (include/jas.h): argument checks on the host,
+// error capture, host staging for JAS_HOST_PTRS, and the call sequence of
+// each operation.  No exception crosses the ABI.
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <set>
+
+#include "jas_internal.hpp"
+
+namespace jas {
+
+namespace {
+thread_local std::string g_err;
+
+template <class F>
+jas_status guard(F &&f) {
+    g_err.clear();
+    try {
+        f();
+        return JAS_OK;
+    } catch (const Error &e) {
+        g_err = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return JAS_ENOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return JAS_EDEVICE;
+    } catch (...) {
+        g_err = "unknown error";
+        return JAS_EDEVICE;
+    }
+}
+
+std::mutex g_pool_mu;
+std::set<int> g_pool_warm;
+
+__global__ void k_zero_u32(uint32_t *p) { *p = 0; }
+
+// Offsets to the host and validated: offsets[0] = 0, non-decreasing.
+std::vector<uint64_t> host_offsets(const uint64_t *offsets, int32_t n, bool host, hipStream_t s, const char *what) {
+    std::vector<uint64_t> h((size_t)n + 1);
+    if (host) std::memcpy(h.data(), offsets, sizeof(uint64_t) * (n + 1));
+    else {
+        JAS_HIP(hipMemcpyAsync(h.data(), offsets, sizeof(uint64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+    }
+    if (h[0] != 0) fail(JAS_EINVAL, std::string(what) + ": offsets[0] must be 0");
+    for (int32_t i = 0; i < n; ++i)
+        if (h[i + 1] < h[i])
+            fail(JAS_EINVAL, std::string(what) + ": offsets decrease at set " + std::to_string(i));
+    return h;
+}
+
+}  // namespace
+
+void fail(jas_status st, const std::string &msg) { throw Error{st, msg}; }
+
+void check_hip(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? JAS_ENOMEM : JAS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+void check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(JAS_EDEVICE, std::string("launch of ") + what + ": " + hipGetErrorString(e));
+}
+
+void Budget::take(uint64_t bytes, const char *what) {
+    const uint64_t all = held + (other ? other->held : 0);
+    if (limit && all + bytes > limit)
+        fail(JAS_ENOMEM, std::string("HBM budget of ") + std::to_string(limit) + " bytes exceeded by " + what +
+                             " (" + std::to_string(bytes) + " bytes, " + std::to_string(all) + " held)");
+    held += bytes;
+    if (held > peak) peak = held;
+}
+
+// Keep freed stream-ordered memory in the device pool between calls.
+void warm_pool(int device) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_warm.count(device)) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    g_pool_warm.insert(device);
+}
+
+}  // namespace jas
+
+using namespace jas;
+
+extern "C" {
+
+const char *jas_last_error(void) { return g_err.c_str(); }
+
+const char *jas_version(void) { return "jas 0.1 (gfx950)"; }
+
+int32_t jas_db_size(const jas_db *db) { return db ? db->n : -1; }
+
+jas_status jas_db_stats(const jas_db *db, jas_encode_stats *stats) {
+    return guard([&] {
+        if (!db || !stats) fail(JAS_EINVAL, "jas_db_stats: null argument");
+        *stats = db->stats;
+    });
+}
+
+void jas_db_free(jas_db *db) {
+    if (!db) return;
+    int cur = 0;
+    const int dev = db->device;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    delete db;
+    if (cur != dev) (void)hipSetDevice(cur);
+}
+
+jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, const jas_encode_opts *opts,
+                      void *hip_stream, jas_db **db_out, jas_encode_stats *stats) {
+    return guard([&] {
+        if (!db_out) fail(JAS_EINVAL, "jas_encode: db_out is NULL");
+        *db_out = nullptr;
+        if (!opts) fail(JAS_EINVAL, "jas_encode: opts is NULL");
+        if (n < 0) fail(JAS_EINVAL, "jas_encode: n < 0");
+        if (n > 0 && !offsets) fail(JAS_EINVAL, "jas_encode: offsets is NULL");
+        const uint32_t U = opts->universe_bits;
+        if (U < 1 || U > 63) fail(JAS_EINVAL, "jas_encode: universe_bits must be in 1..63");
+        const uint32_t sbits = ceil_log2_u64((uint64_t)std::max<int32_t>(n, 1));
+        if (U + sbits > 64) fail(JAS_EINVAL, "jas_encode: universe_bits + ceil(log2 n) exceeds 64");
+        const bool host = opts->flags & JAS_HOST_PTRS;
+        hipStream_t s = (hipStream_t)hip_stream;
+        // host arrays are validated before the device is touched
+        std::vector<uint64_t> hoff{0};
+        if (host && n > 0) hoff = host_offsets(offsets, n, true, s, "jas_encode");
+        if (host && hoff[n] > 0 && !ids) fail(JAS_EINVAL, "jas_encode: ids is NULL");
+        int dev = 0;
+        JAS_HIP(hipGetDevice(&dev));
+        warm_pool(dev);
+        if (!host && n > 0) hoff = host_offsets(offsets, n, false, s, "jas_encode");
+        const uint64_t N = hoff[n];
+        if (N > 0 && !ids) fail(JAS_EINVAL, "jas_encode: ids is NULL");
+
+        std::unique_ptr<jas_db> db(new jas_db());
+        db->device = dev;
+        db->n = n;
+        db->U = U;
+        db->sbits = sbits;
+        db->batch_bits = (opts->batch_bits == 0 || opts->batch_bits >= U) ? U : opts->batch_bits;
+        db->dmin = opts->dense_min_degree == 0 ? 2u : std::max<uint32_t>(2u, opts->dense_min_degree);
+        db->flags = opts->flags;
+        // one budget for the call: temporaries (tb) and the db's own buffers
+        Budget tb;
+        tb.limit = opts->hbm_budget_bytes;
+        tb.other = &db->budget;
+        db->budget.limit = opts->hbm_budget_bytes;
+        db->budget.other = &tb;
+
+        // inputs on the device
+        DevBuf<uint64_t> ids_d, off_d;
+        const uint64_t *dids = ids, *doff = offsets;
+        if (host) {
+            off_d.alloc(n + 1, s, &tb, true, "offsets copy");
+            JAS_HIP(hipMemcpyAsync(off_d.p, hoff.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, s));
+            doff = off_d.p;
+            if (N > 0) {
+                ids_d.alloc(N, s, &tb, true, "ids copy");
+                JAS_HIP(hipMemcpyAsync(ids_d.p, ids, sizeof(uint64_t) * N, hipMemcpyHostToDevice, s));
+                dids = ids_d.p;
+            }
+        }
+        DevBuf<uint64_t> keys;
+        if (N > 0) {
+            DevBuf<uint64_t> alt;
+            DevBuf<uint32_t> err;
+            keys.alloc(N, s, &tb, true, "sort keys");
+            alt.alloc(N, s, &tb, true, "sort keys (second buffer)");
+            err.alloc(1, s, &tb, true, "error flag");
+            {
+                JAS_TIMED("zero_u32", s);
+                k_zero_u32<<<1, 1, 0, s>>>(err.p);
+            }
+            build_keys(dids, doff, n, N, sbits, U, keys.p, err.p, s);
+            uint32_t herr = 0;
+            JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipStreamSynchronize(s));
+            if (herr) fail(JAS_EINVAL, "jas_encode: an ID is >= 2^universe_bits");
+            ids_d.release();
+            off_d.release();
+            RadixWork rw;
+            radix_sort_u64(keys, alt, N, sbits, sbits + U, rw, s, &tb);
+        }
+        encode_sorted(db.get(), keys.p, N, s, &tb);
+        keys.release();
+        db->budget.limit = 0;
+        db->budget.other = nullptr;
+        JAS_HIP(hipStreamSynchronize(s));
+        db->stats.device_bytes = db->budget.held;
+        if (stats) *stats = db->stats;
+        *db_out = db.release();
+    });
+}
+
+jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t *B, int64_t *card, int64_t *den,
+                    double *J) {
+    return guard([&] {
+        if (!db) fail(JAS_EINVAL, "jas_gram: db is NULL");
+        if (!B && db->n > 0) fail(JAS_EINVAL, "jas_gram: B is NULL");
+        if ((flags & JAS_FORCE_POPCOUNT) && (flags & JAS_FORCE_MFMA))
+            fail(JAS_EINVAL, "jas_gram: JAS_FORCE_POPCOUNT and JAS_FORCE_MFMA are exclusive");
+        hipStream_t s = (hipStream_t)hip_stream;
+        const uint64_t n = (uint64_t)db->n;
+        const uint64_t len = (flags & JAS_UPPER) ? n * (n + 1) / 2 : n * n;
+        if (!(flags & JAS_HOST_PTRS)) {
+            gram(db, flags, s, B, card, den, J);
+            return;
+        }
+        DevBuf<int32_t> dB;
+        DevBuf<int64_t> dC, dD;
+        DevBuf<double> dJ;
+        dB.alloc(len, s, nullptr, true, "B staging");
+        if (card) dC.alloc(n, s, nullptr, true, "card staging");
+        if (den) dD.alloc(len, s, nullptr, true, "den staging");
+        if (J) dJ.alloc(len, s, nullptr, true, "J staging");
+        gram(db, flags & ~JAS_HOST_PTRS, s, dB.p, card ? dC.p : nullptr, den ? dD.p : nullptr, J ? dJ.p : nullptr);
+        JAS_HIP(hipMemcpyAsync(B, dB.p, len * 4, hipMemcpyDeviceToHost, s));
+        if (card) JAS_HIP(hipMemcpyAsync(card, dC.p, n * 8, hipMemcpyDeviceToHost, s));
+        if (den) JAS_HIP(hipMemcpyAsync(den, dD.p, len * 8, hipMemcpyDeviceToHost, s));
+        if (J) JAS_HIP(hipMemcpyAsync(J, dJ.p, len * 8, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+    });
+}
+
+jas_status jas_query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint32_t flags,
+                     void *hip_stream, int32_t *B, int64_t *q_card, int64_t *den, double *J) {
+    return guard([&] {
+        if (!db) fail(JAS_EINVAL, "jas_query: db is NULL");
+        if (!(db->flags & JAS_KEEP_IDS)) fail(JAS_EINVAL, "jas_query: db was encoded without JAS_KEEP_IDS");
+        if (nq < 0) fail(JAS_EINVAL, "jas_query: nq < 0");
+        if (nq > 0 && !q_offsets) fail(JAS_EINVAL, "jas_query: q_offsets is NULL");
+        if (nq > 0 && db->n > 0 && !B) fail(JAS_EINVAL, "jas_query: B is NULL");
+        const uint32_t qbits = ceil_log2_u64((uint64_t)std::max<int32_t>(nq, 1));
+        if (db->U + qbits > 64) fail(JAS_EINVAL, "jas_query: universe_bits + ceil(log2 nq) exceeds 64");
+        hipStream_t s = (hipStream_t)hip_stream;
+        const bool host = flags & JAS_HOST_PTRS;
+        if (nq == 0) return;
+        std::vector<uint64_t> hoff = host_offsets(q_offsets, nq, host, s, "jas_query");
+        const uint64_t NQ = hoff[nq];
+        if (NQ > 0 && !q_ids) fail(JAS_EINVAL, "jas_query: q_ids is NULL");
+        const uint64_t n = (uint64_t)db->n;
+        const uint64_t len = (uint64_t)nq * n;
+        if (!host) {
+            query(db, q_ids, q_offsets, nq, NQ, s, B, q_card, den, J);
+            return;
+        }
+        DevBuf<uint64_t> di, doff;
+        DevBuf<int32_t> dB;
+        DevBuf<int64_t> dC, dD;
+        DevBuf<double> dJ;
+        doff.alloc(nq + 1, s, nullptr, true, "query offsets staging");
+        JAS_HIP(hipMemcpyAsync(doff.p, hoff.data(), 8 * (nq + 1), hipMemcpyHostToDevice, s));
+        di.alloc(std::max<uint64_t>(NQ, 1), s, nullptr, true, "query ids staging");
+        if (NQ) JAS_HIP(hipMemcpyAsync(di.p, q_ids, 8 * NQ, hipMemcpyHostToDevice, s));
+        dB.alloc(std::max<uint64_t>(len, 1), s, nullptr, true, "B staging");
+        if (q_card) dC.alloc(nq, s, nullptr, true, "q_card staging");
+        if (den) dD.alloc(std::max<uint64_t>(len, 1), s, nullptr, true, "den staging");
+        if (J) dJ.alloc(std::max<uint64_t>(len, 1), s, nullptr, true, "J staging");
+        query(db, di.p, doff.p, nq, NQ, s, dB.p, q_card ? dC.p : nullptr, den ? dD.p : nullptr, J ? dJ.p : nullptr);
+        if (len) JAS_HIP(hipMemcpyAsync(B, dB.p, len * 4, hipMemcpyDeviceToHost, s));
+        if (q_card) JAS_HIP(hipMemcpyAsync(q_card, dC.p, 8 * (uint64_t)nq, hipMemcpyDeviceToHost, s));
+        if (den && len) JAS_HIP(hipMemcpyAsync(den, dD.p, len * 8, hipMemcpyDeviceToHost, s));
+        if (J && len) JAS_HIP(hipMemcpyAsync(J, dJ.p, len * 8, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+    });
+}
+
+uint64_t jas_query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids) {
+    if (!db || nq < 0) return 0;
+    return query_workspace_bytes(db, nq, n_q_ids);
+}
+
+}  // extern "C"

@@ -1,0 +1,627 @@
+// Encoding of the indicator matrix A (Sec. III-B).
+//
+// Input: CSR sets.  Keys (id << sbits) | sample are built in CSR order, which
+// is already ascending in `sample`, so a stable sort on the ID bits alone
+// leaves every ID's entries together with samples ascending.
+//
+// After the sort (encode_sorted):
+//   classify   first occurrence of a key = a distinct (ID, sample) pair, i.e. a
+//              nonzero of A (repeats dropped: the (max, x) write of Sec. IV-A);
+//              |X_i| = distinct pairs of sample i (column sums, Eq. (4));
+//              an ID's run of distinct pairs is one nonzero row of A (the
+//              filter of Eq. (5)); rows with >= 2 pairs ("shared") are the
+//              only rows off-diagonal B depends on, because a row with one
+//              nonzero adds only to B_ii = |X_i|.
+//   compaction shared rows are numbered in ID order by a prefix sum (Eq. (6)).
+//   split      rows of degree >= dmin are bit-packed; rows of degree 2..dmin-1
+//              are kept as plain row lists (their outer products are added
+//              pair by pair in the Gram step).
+//   batches    packed rows are grouped by batch l = id >> batch_bits (Eq. (3));
+//              inside a batch, row p (in ID order) is bit p % 64 of word row
+//              p / 64, so words never straddle batches.
+//   pack       one block per word row ORs the bits of its <= 64 rows into an
+//              LDS row of n words and writes it out: W[w][i] is the word of
+//              column i (the bitmask compression preceding Eq. (7)).
+#include <algorithm>
+#include <utility>
+
+#include "device_util.hpp"
+#include "jas_internal.hpp"
+
+namespace jas {
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kWaves = kNT / kWave;
+constexpr int kRounds = 16;
+constexpr uint32_t kTile = kNT * kRounds;  // 4096
+constexpr uint64_t kChunk = 65536;         // elements per classify block
+constexpr int32_t kHistMax = 16384;        // LDS column histogram up to this n
+constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass
+
+enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__ ids,
+                                                     const uint64_t *__restrict__ off, int32_t n, uint64_t N,
+                                                     uint32_t sbits, uint64_t hi_mask, uint64_t *__restrict__ keys,
+                                                     uint32_t *err) {
+    __shared__ int32_t s_lo, s_hi;
+    const uint64_t b0 = (uint64_t)blockIdx.x * kTile;
+    const uint64_t b1 = min(N, b0 + kTile);
+    if (threadIdx.x == 0) {
+        s_lo = find_sample(off, 0, n - 1, b0);
+        s_hi = find_sample(off, s_lo, n - 1, b1 - 1);
+    }
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint64_t t = b0 + threadIdx.x; t < b1; t += kNT) {
+        const int32_t s = find_sample(off, s_lo, s_hi, t);
+        const uint64_t id = ids[t];
+        bad |= (id & hi_mask) != 0;
+        keys[t] = (id << sbits) | (uint64_t)s;
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1u);
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t len, uint64_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Classification of sorted element t (key = K[t]).
+struct Cls {
+    bool first, shared, rowstart, newid;
+};
+
+__device__ __forceinline__ Cls classify(const uint64_t *__restrict__ K, uint64_t N, uint64_t t, uint64_t key,
+                                        uint32_t sbits) {
+    Cls c;
+    const uint64_t id = key >> sbits;
+    const uint64_t prev = t > 0 ? K[t - 1] : ~key;
+    c.first = (t == 0) || prev != key;
+    const bool left = c.first && t > 0 && (prev >> sbits) == id;
+    bool right = false;
+    if (c.first) {
+        uint64_t u = t + 1;
+        while (u < N && K[u] == key) ++u;  // skip repeats of this (ID, sample)
+        right = u < N && (K[u] >> sbits) == id;
+    }
+    c.shared = c.first && (left || right);
+    c.rowstart = c.shared && !left;
+    c.newid = c.first && !left;
+    return c;
+}
+
+__global__ __launch_bounds__(kNT) void k_cls_count(const uint64_t *__restrict__ K, uint64_t N, uint32_t sbits,
+                                                    uint64_t smask, int32_t n, int lds_hist, uint32_t *cD,
+                                                    uint32_t *cS, uint32_t *cR, unsigned long long *card,
+                                                    unsigned long long *st) {
+    extern __shared__ uint32_t hist[];
+    __shared__ uint64_t sh[kWaves];
+    const uint32_t tid = threadIdx.x;
+    if (lds_hist)
+        for (int32_t i = tid; i < n; i += kNT) hist[i] = 0;
+    __syncthreads();
+    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
+    const uint64_t c1 = min(N, c0 + kChunk);
+    uint32_t nD = 0, nS = 0, nR = 0, nI = 0;
+    for (uint64_t t = c0 + tid; t < c1; t += kNT) {
+        const uint64_t key = K[t];
+        const Cls c = classify(K, N, t, key, sbits);
+        if (c.first) {
+            ++nD;
+            const uint32_t s = (uint32_t)(key & smask);
+            if (lds_hist) atomicAdd(&hist[s], 1u);
+            else atomicAdd(&card[s], 1ull);
+        }
+        nS += c.shared;
+        nR += c.rowstart;
+        nI += c.newid;
+    }
+    uint64_t tD, tS, tR, tI;
+    block_excl_scan<kNT>(nD, sh, &tD);
+    block_excl_scan<kNT>(nS, sh, &tS);
+    block_excl_scan<kNT>(nR, sh, &tR);
+    block_excl_scan<kNT>(nI, sh, &tI);
+    if (tid == 0) {
+        cD[blockIdx.x] = (uint32_t)tD;
+        cS[blockIdx.x] = (uint32_t)tS;
+        cR[blockIdx.x] = (uint32_t)tR;
+        atomicAdd(&st[ST_PAIRS], (unsigned long long)tD);
+        atomicAdd(&st[ST_ROWS], (unsigned long long)tI);
+    }
+    if (lds_hist)
+        for (int32_t i = tid; i < n; i += kNT)
+            if (hist[i]) atomicAdd(&card[i], (unsigned long long)hist[i]);
+}
+
+// Ordered compaction of the classified elements of one chunk.
+__global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ K, uint64_t N, uint32_t sbits,
+                                                    uint64_t smask, const uint64_t *oD, const uint64_t *oS,
+                                                    const uint64_t *oR, uint64_t *Dout, uint32_t *Sout,
+                                                    uint64_t *row_id, uint64_t *row_ptr) {
+    __shared__ uint32_t wc[3][kWaves];
+    __shared__ uint64_t run[3];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const uint64_t lt = lanemask_lt();
+    const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
+    const uint64_t c1 = min(N, c0 + kChunk);
+    if (tid == 0) {
+        run[0] = oD[blockIdx.x];
+        run[1] = oS[blockIdx.x];
+        run[2] = oR[blockIdx.x];
+    }
+    for (uint64_t t0 = c0; t0 < c1; t0 += kTile) {
+        __syncthreads();
+        const uint64_t wb = t0 + (uint64_t)w * (kTile / kWaves);
+        uint64_t key[kRounds];
+        uint32_t fD = 0, fS = 0, fR = 0;
+        uint32_t nD = 0, nS = 0, nR = 0;
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            const uint64_t t = wb + (uint64_t)j * kWave + lane;
+            bool d = false, s = false, r = false;
+            key[j] = 0;
+            if (t < c1) {
+                key[j] = K[t];
+                const Cls c = classify(K, N, t, key[j], sbits);
+                d = c.first;
+                s = c.shared;
+                r = c.rowstart;
+            }
+            fD |= (uint32_t)d << j;
+            fS |= (uint32_t)s << j;
+            fR |= (uint32_t)r << j;
+            nD += __popcll(__ballot(d));
+            nS += __popcll(__ballot(s));
+            nR += __popcll(__ballot(r));
+        }
+        if (lane == 0) {
+            wc[0][w] = nD;
+            wc[1][w] = nS;
+            wc[2][w] = nR;
+        }
+        __syncthreads();
+        uint64_t pD = run[0], pS = run[1], pR = run[2];
+        for (uint32_t k = 0; k < w; ++k) {
+            pD += wc[0][k];
+            pS += wc[1][k];
+            pR += wc[2][k];
+        }
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            const bool d = (fD >> j) & 1u, s = (fS >> j) & 1u, r = (fR >> j) & 1u;
+            const uint64_t bd = __ballot(d), bs = __ballot(s), br = __ballot(r);
+            const uint64_t posD = pD + __popcll(bd & lt);
+            const uint64_t posS = pS + __popcll(bs & lt);
+            const uint64_t posR = pR + __popcll(br & lt);
+            if (d && Dout) Dout[posD] = key[j];
+            if (s) Sout[posS] = (uint32_t)(key[j] & smask);
+            if (r) {
+                row_id[posR] = key[j] >> sbits;
+                row_ptr[posR] = posS;
+            }
+            pD += __popcll(bd);
+            pS += __popcll(bs);
+            pR += __popcll(br);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int k = 0; k < kWaves; ++k) {
+                run[0] += wc[0][k];
+                run[1] += wc[1][k];
+                run[2] += wc[2][k];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rows: degree split.
+__global__ void k_row_flags(const uint64_t *row_ptr, uint64_t R, uint32_t dmin, uint32_t *fDense,
+                            uint32_t *fList, unsigned long long *st) {
+    unsigned long long lp = 0;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = row_ptr[r + 1] - row_ptr[r];
+        const bool dense = d >= dmin;
+        fDense[r] = dense;
+        fList[r] = !dense;
+        if (!dense) lp += d * (d - 1) / 2;
+    }
+    if (lp) atomicAdd(&st[ST_LISTPAIRS], lp);
+}
+
+__global__ void k_row_compact(uint64_t R, const uint32_t *fDense, const uint64_t *pDense, const uint64_t *pList,
+                              uint64_t *Drow, uint64_t *Lrow) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
+        if (fDense[r]) Drow[pDense[r]] = r;
+        else Lrow[pList[r]] = r;
+    }
+}
+
+// Batches of packed rows.
+__global__ void k_batch_flag(const uint64_t *Drow, const uint64_t *row_id, uint64_t QD, uint32_t bbits,
+                             uint32_t *bs) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = row_id[Drow[q]] >> bbits;
+        bs[q] = (q == 0) || b != (row_id[Drow[q - 1]] >> bbits);
+    }
+}
+
+__global__ void k_batch_start(const uint32_t *bs, const uint64_t *bpos, uint64_t QD, uint64_t *bq) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x)
+        if (bs[q]) bq[bpos[q]] = q;
+}
+
+__global__ void k_batch_words(const uint64_t *bq, uint64_t nb, uint64_t *nw) {
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x)
+        nw[b] = (bq[b + 1] - bq[b] + 63) / 64;
+}
+
+__global__ void k_word_rows(uint64_t QD, const uint64_t *bpos, const uint64_t *bq, const uint64_t *wbase,
+                            uint64_t *wq0, uint64_t *wq1) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = bpos[q + 1] - 1;  // batch of packed row q
+        const uint64_t p = q - bq[b];        // position inside the batch
+        if ((p & 63) == 0) {
+            const uint64_t w = wbase[b] + p / 64;
+            wq0[w] = q;
+            wq1[w] = min(q + 64, bq[b + 1]);
+        }
+    }
+}
+
+// One block per word row: OR the bits of its rows into LDS, write the row out.
+__global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t ldw, uint64_t H,
+                                               const uint64_t *__restrict__ wq0, const uint64_t *__restrict__ wq1,
+                                               const uint64_t *__restrict__ Drow,
+                                               const uint64_t *__restrict__ row_ptr,
+                                               const uint32_t *__restrict__ S, uint32_t cols,
+                                               unsigned long long *st) {
+    extern __shared__ unsigned long long lw[];
+    __shared__ uint32_t zsh;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+    for (uint64_t w = blockIdx.x; w < H; w += gridDim.x) {
+        const uint64_t q0 = wq0[w], q1 = wq1[w];
+        if (tid == 0) zsh = 0;
+        for (uint64_t c0 = 0; c0 < ldw; c0 += cols) {
+            const uint32_t cn = (uint32_t)min((uint64_t)cols, ldw - c0);
+            for (uint32_t i = tid; i < cn; i += kNT) lw[i] = 0;
+            __syncthreads();
+            for (uint64_t q = q0 + wv; q < q1; q += kWaves) {
+                const unsigned long long bit = 1ull << (q - q0);
+                const uint64_t r = Drow[q];
+                const uint64_t a1 = row_ptr[r + 1];
+                for (uint64_t a = row_ptr[r] + lane; a < a1; a += kWave) {
+                    const uint64_t s = S[a];
+                    if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], bit);
+                }
+            }
+            __syncthreads();
+            uint32_t z = 0;
+            for (uint32_t i = tid; i < cn; i += kNT) {
+                const unsigned long long v = lw[i];
+                W[w * ldw + c0 + i] = v;
+                z += v != 0;
+            }
+            if (z) atomicAdd(&zsh, z);
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const unsigned long long z = zsh;
+            atomicAdd(&st[ST_NNZW], z);
+            atomicAdd(&st[ST_F], z * (z + 1) / 2);
+        }
+        __syncthreads();
+    }
+}
+
+// Row lists: CSR of the rows of degree 2..dmin-1.
+__global__ void k_list_deg(const uint64_t *Lrow, const uint64_t *row_ptr, uint64_t QL, uint64_t *deg) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = Lrow[j];
+        deg[j] = row_ptr[r + 1] - row_ptr[r];
+    }
+}
+
+__global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, const uint32_t *S,
+                              const uint64_t *lptr, uint64_t QL, uint32_t *lsmp) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = Lrow[j];
+        const uint64_t a0 = row_ptr[r], d = row_ptr[r + 1] - a0, o = lptr[j];
+        for (uint64_t k = 0; k < d; ++k) lsmp[o + k] = S[a0 + k];
+    }
+}
+
+// Query index: bucket[b] = first distinct key whose ID has top bits >= b.
+__global__ void k_bucket(const uint64_t *D, uint64_t ND, uint32_t sbits, uint32_t shift, uint64_t nbk,
+                         uint64_t *bucket) {
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= ND; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t bk = t < ND ? ((D[t] >> sbits) >> shift) : nbk;
+        const int64_t prev = t == 0 ? -1 : (int64_t)((D[t - 1] >> sbits) >> shift);
+        for (int64_t b = prev + 1; b <= (int64_t)bk; ++b) bucket[b] = t;
+    }
+}
+
+template <class F>
+void launch_1d(uint64_t work, hipStream_t s, F f) {
+    const uint64_t blocks = std::min<uint64_t>(std::max<uint64_t>(div_up(work, 256), 1), 65536);
+    f((uint32_t)blocks, s);
+}
+
+uint64_t to_host_u64(const uint64_t *dptr, hipStream_t s) {
+    uint64_t v = 0;
+    JAS_HIP(hipMemcpyAsync(&v, dptr, sizeof(v), hipMemcpyDeviceToHost, s));
+    JAS_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+}  // namespace
+
+void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
+                uint64_t *keys, uint32_t *err, hipStream_t s) {
+    if (N == 0) return;
+    const uint64_t hi_mask = U >= 64 ? 0 : ~((uint64_t(1) << U) - 1);
+    const uint64_t blocks = div_up(N, kTile);
+    if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many IDs");
+    {
+        JAS_TIMED("build_keys", s);
+        k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, keys, err);
+    }
+    check_launch("build keys");
+}
+
+void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Budget *tb) {
+    const int32_t n = db->n;
+    const uint32_t sbits = db->sbits;
+    const uint64_t smask = sbits ? ((uint64_t(1) << sbits) - 1) : 0;
+    const bool keep = db->flags & JAS_KEEP_IDS;
+
+    DevBuf<unsigned long long> st;
+    st.alloc(ST_N, s, tb, true, "encode counters");
+    {
+        JAS_TIMED("fill_u64", s);
+        k_fill_u64<<<1, 64, 0, s>>>((uint64_t *)st.p, ST_N, 0);
+    }
+    DevBuf<unsigned long long> cardc;
+    cardc.alloc(std::max<int32_t>(n, 1), s, tb, true, "column sums");
+    {
+        JAS_TIMED("fill_u64", s);
+        k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)cardc.p, (uint64_t)std::max<int32_t>(n, 1), 0);
+    }
+    check_launch("fill");
+
+    // --- classify: counts per chunk, then ordered compaction -----------------
+    const uint64_t nch = div_up(N, kChunk);
+    DevBuf<uint32_t> cnt;
+    DevBuf<uint64_t> offD, offS, offR, stmp;
+    uint64_t NDk = 0, NS = 0, R = 0;
+    DevBuf<uint64_t> Dk, row_id, row_ptr;
+    DevBuf<uint32_t> S;
+    if (N > 0) {
+        cnt.alloc(3 * nch, s, tb, true, "classify counts");
+        const int lds_hist = n <= kHistMax;
+        const size_t shmem = lds_hist ? (size_t)n * sizeof(uint32_t) : 0;
+        {
+            JAS_TIMED("cls_count", s);
+            k_cls_count<<<(uint32_t)nch, kNT, shmem, s>>>(K, N, sbits, smask, n, lds_hist, cnt.p, cnt.p + nch,
+                                                          cnt.p + 2 * nch, cardc.p, st.p);
+        }
+        check_launch("classify count");
+        offD.alloc(nch + 1, s, tb, true, "classify offsets");
+        offS.alloc(nch + 1, s, tb, true, "classify offsets");
+        offR.alloc(nch + 1, s, tb, true, "classify offsets");
+        stmp.alloc(scan_tmp_elems(nch), s, tb, true, "scan scratch");
+        scan_excl_u32(cnt.p, offD.p, nch, stmp.p, s);
+        scan_excl_u32(cnt.p + nch, offS.p, nch, stmp.p, s);
+        scan_excl_u32(cnt.p + 2 * nch, offR.p, nch, stmp.p, s);
+        uint64_t tot[3];
+        JAS_HIP(hipMemcpyAsync(&tot[0], offD.p + nch, 8, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipMemcpyAsync(&tot[1], offS.p + nch, 8, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipMemcpyAsync(&tot[2], offR.p + nch, 8, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+        NDk = tot[0];
+        NS = tot[1];
+        R = tot[2];
+    }
+    // column sums -> |X_i| (int32 B needs every |X_i| < 2^31)
+    db->card.alloc(std::max<int32_t>(n, 1), s, &db->budget, false, "card");
+    if (n > 0) {
+        std::vector<uint64_t> hc(n);
+        JAS_HIP(hipMemcpyAsync(hc.data(), cardc.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < n; ++i)
+            if (hc[i] >= (uint64_t(1) << 31))
+                fail(JAS_EOVERFLOW, "sample " + std::to_string(i) + " has " + std::to_string(hc[i]) +
+                                        " distinct IDs (limit 2^31 - 1)");
+        JAS_HIP(hipMemcpyAsync(db->card.p, cardc.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+    }
+    cardc.release();
+
+    if (N > 0) {
+        if (keep) Dk.alloc(NDk, s, &db->budget, false, "query index keys");
+        S.alloc(NS, s, tb, true, "shared pairs");
+        row_id.alloc(R, s, tb, true, "row ids");
+        row_ptr.alloc(R + 1, s, tb, true, "row pointers");
+        {
+            JAS_TIMED("cls_write", s);
+            k_cls_write<<<(uint32_t)nch, kNT, 0, s>>>(K, N, sbits, smask, offD.p, offS.p, offR.p,
+                                                      keep ? Dk.p : nullptr, S.p, row_id.p, row_ptr.p);
+        }
+        check_launch("classify write");
+        {
+            JAS_TIMED("fill_u64", s);
+            k_fill_u64<<<1, 1, 0, s>>>(row_ptr.p + R, 1, NS);
+        }
+        check_launch("fill");
+    }
+    cnt.release();
+    offD.release();
+    offS.release();
+    offR.release();
+    stmp.release();
+
+    // --- split rows by degree ------------------------------------------------
+    uint64_t QD = 0, QL = 0;
+    DevBuf<uint64_t> Drow, Lrow;
+    if (R > 0) {
+        DevBuf<uint32_t> fDense, fList;
+        DevBuf<uint64_t> pDense, pList, tmp;
+        fDense.alloc(R, s, tb, true, "row flags");
+        fList.alloc(R, s, tb, true, "row flags");
+        launch_1d(R, s, [&](uint32_t b, hipStream_t st_) {
+            {
+                JAS_TIMED("row_flags", st_);
+                k_row_flags<<<b, 256, 0, st_>>>(row_ptr.p, R, db->dmin, fDense.p, fList.p, st.p);
+            }
+        });
+        check_launch("row flags");
+        pDense.alloc(R + 1, s, tb, true, "row scan");
+        pList.alloc(R + 1, s, tb, true, "row scan");
+        tmp.alloc(scan_tmp_elems(R), s, tb, true, "scan scratch");
+        scan_excl_u32(fDense.p, pDense.p, R, tmp.p, s);
+        scan_excl_u32(fList.p, pList.p, R, tmp.p, s);
+        QD = to_host_u64(pDense.p + R, s);
+        QL = R - QD;
+        Drow.alloc(QD, s, tb, true, "packed rows");
+        Lrow.alloc(QL, s, tb, true, "list rows");
+        launch_1d(R, s, [&](uint32_t b, hipStream_t st_) {
+            {
+                JAS_TIMED("row_compact", st_);
+                k_row_compact<<<b, 256, 0, st_>>>(R, fDense.p, pDense.p, pList.p, Drow.p, Lrow.p);
+            }
+        });
+        check_launch("row compact");
+    }
+
+    // --- packed rows: batches, word rows, pack -------------------------------
+    const uint64_t ldw = div_up((uint64_t)std::max<int32_t>(n, 1), 128) * 128;
+    uint64_t nb = 0, H = 0;
+    if (QD > 0) {
+        DevBuf<uint32_t> bs;
+        DevBuf<uint64_t> bpos, bq, nw, wbase, tmp, wq0, wq1;
+        bs.alloc(QD, s, tb, true, "batch flags");
+        const uint32_t bbits = db->batch_bits;
+        launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) {
+            {
+                JAS_TIMED("batch_flag", st_);
+                k_batch_flag<<<b, 256, 0, st_>>>(Drow.p, row_id.p, QD, bbits, bs.p);
+            }
+        });
+        check_launch("batch flags");
+        bpos.alloc(QD + 1, s, tb, true, "batch scan");
+        tmp.alloc(scan_tmp_elems(QD), s, tb, true, "scan scratch");
+        scan_excl_u32(bs.p, bpos.p, QD, tmp.p, s);
+        nb = to_host_u64(bpos.p + QD, s);
+        bq.alloc(nb + 1, s, tb, true, "batch starts");
+        launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_start", st_); k_batch_start<<<b, 256, 0, st_>>>(bs.p, bpos.p, QD, bq.p); } });
+        {
+            JAS_TIMED("fill_u64", s);
+            k_fill_u64<<<1, 1, 0, s>>>(bq.p + nb, 1, QD);
+        }
+        check_launch("batch starts");
+        nw.alloc(nb, s, tb, true, "batch words");
+        launch_1d(nb, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_words", st_); k_batch_words<<<b, 256, 0, st_>>>(bq.p, nb, nw.p); } });
+        check_launch("batch words");
+        wbase.alloc(nb + 1, s, tb, true, "word bases");
+        tmp.release();
+        tmp.alloc(scan_tmp_elems(nb), s, tb, true, "scan scratch");
+        scan_excl_u64(nw.p, wbase.p, nb, tmp.p, s);
+        H = to_host_u64(wbase.p + nb, s);
+        wq0.alloc(H, s, tb, true, "word rows");
+        wq1.alloc(H, s, tb, true, "word rows");
+        launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) {
+            {
+                JAS_TIMED("word_rows", st_);
+                k_word_rows<<<b, 256, 0, st_>>>(QD, bpos.p, bq.p, wbase.p, wq0.p, wq1.p);
+            }
+        });
+        check_launch("word rows");
+        db->W.alloc(H * ldw, s, &db->budget, false, "packed words");
+        const uint32_t cols = (uint32_t)std::min<uint64_t>(ldw, kPackCols);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(H, 1u << 20);
+        {
+            JAS_TIMED("pack", s);
+            k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, wq0.p, wq1.p, Drow.p, row_ptr.p,
+                                                                        S.p, cols, st.p);
+        }
+        check_launch("pack");
+    }
+    db->H = H;
+
+    // --- row lists -----------------------------------------------------------
+    db->n_list = QL;
+    db->list_ptr.alloc(QL + 1, s, &db->budget, false, "row list pointers");
+    if (QL > 0) {
+        DevBuf<uint64_t> deg, tmp;
+        deg.alloc(QL, s, tb, true, "row list degrees");
+        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("list_deg", st_); k_list_deg<<<b, 256, 0, st_>>>(Lrow.p, row_ptr.p, QL, deg.p); } });
+        check_launch("list degrees");
+        tmp.alloc(scan_tmp_elems(QL), s, tb, true, "scan scratch");
+        scan_excl_u64(deg.p, db->list_ptr.p, QL, tmp.p, s);
+        db->list_nnz = to_host_u64(db->list_ptr.p + QL, s);
+        db->list_smp.alloc(db->list_nnz, s, &db->budget, false, "row list samples");
+        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
+            {
+                JAS_TIMED("list_gather", st_);
+                k_list_gather<<<b, 256, 0, st_>>>(Lrow.p, row_ptr.p, S.p, db->list_ptr.p, QL, db->list_smp.p);
+            }
+        });
+        check_launch("list gather");
+    } else {
+        {
+            JAS_TIMED("fill_u64", s);
+            k_fill_u64<<<1, 1, 0, s>>>(db->list_ptr.p, 1, 0);
+        }
+        db->list_nnz = 0;
+        db->list_smp.alloc(1, s, &db->budget, false, "row list samples");
+    }
+
+    // --- query index -----------------------------------------------------------
+    if (keep) {
+        db->n_keys = NDk;
+        uint32_t ib = ceil_log2_u64(div_up(std::max<uint64_t>(NDk, 1), 32));
+        ib = std::max<uint32_t>(1, std::min<uint32_t>(ib, std::min<uint32_t>(db->U, 26)));
+        db->ibits = ib;
+        const uint64_t nbk = uint64_t(1) << ib;
+        db->bucket.alloc(nbk + 1, s, &db->budget, false, "query buckets");
+        if (NDk == 0) {
+            {
+                JAS_TIMED("fill_u64", s);
+                k_fill_u64<<<64, 256, 0, s>>>(db->bucket.p, nbk + 1, 0);
+            }
+            db->keys.alloc(1, s, &db->budget, false, "query index keys");
+        } else {
+            launch_1d(NDk + 1, s, [&](uint32_t b, hipStream_t st_) {
+                {
+                    JAS_TIMED("bucket", st_);
+                    k_bucket<<<b, 256, 0, st_>>>(Dk.p, NDk, sbits, db->U - ib, nbk, db->bucket.p);
+                }
+            });
+            db->keys = std::move(Dk);
+        }
+        check_launch("query buckets");
+    }
+
+    // --- stats -----------------------------------------------------------------
+    uint64_t hst[ST_N];
+    JAS_HIP(hipMemcpyAsync(hst, st.p, sizeof(hst), hipMemcpyDeviceToHost, s));
+    JAS_HIP(hipStreamSynchronize(s));
+    jas_encode_stats &o = db->stats;
+    o.n_ids = N;
+    o.n_pairs = hst[ST_PAIRS];
+    o.n_rows = hst[ST_ROWS];
+    o.n_shared_rows = R;
+    o.n_packed_rows = QD;
+    o.n_list_rows = QL;
+    o.n_batches = nb;
+    o.n_word_rows = H;
+    o.nnz_words = hst[ST_NNZW];
+    o.word_pairs_F = hst[ST_F];
+    o.list_pairs = hst[ST_LISTPAIRS];
+    o.device_bytes = db->budget.held;
+}
+
+}  // namespace jas

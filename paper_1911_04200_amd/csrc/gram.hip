@@ -1,0 +1,217 @@
+// Gram product B = A^T A on the encoding, and the similarity (Sec. III-A/B).
+//
+// Packed rows (Eq. (7)):  B_ij += sum_w popcount(W[w][i] & W[w][j]), summed
+//   over every word row of every batch (Eq. (4)).  The upper triangle of
+//   128 x 128 column tiles is computed; word rows are split into K ranges so
+//   the grid fills the chip, and each block adds its tile into B with integer
+//   atomics (exact and order independent).
+// Row lists: a row shared by d = 2..dmin-1 sets adds 1 to B_ij for each of its
+//   d(d-1)/2 pairs i < j (its outer product a_k a_k^T, unpacked).
+// Diagonal: B_ii = |X_i| (column sums, Eq. (4)).
+// Finalize: C_ij = |X_i| + |X_j| - B_ij, J_ij = B_ij / C_ij, J = 1 if C_ij = 0
+//   (Sec. II-A, Eq. (2)); IEEE binary64 division, round to nearest.
+#include <algorithm>
+#include <vector>
+
+#include "device_util.hpp"
+#include "jas_internal.hpp"
+
+namespace jas {
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kT = 128;   // column tile
+constexpr int kKC = 16;   // word rows per LDS stage
+
+__global__ void k_fill_i32(int32_t *p, uint64_t len, int32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Thread (ty, tx) of a 16 x 16 grid owns rows 32c + 2ty + e and columns
+// 32c + 2tx + e (c = 0..3, e = 0..1) of the 128 x 128 tile: every LDS read is
+// a 16-byte load, consecutive lanes read consecutive 16-byte pieces.
+__global__ __launch_bounds__(kNT) void k_gram_popc(const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H,
+                                                    uint64_t kper, uint32_t nt, uint32_t n,
+                                                    int32_t *__restrict__ B, int upper) {
+    __shared__ ulonglong2 As[kKC][kT / 2];
+    __shared__ ulonglong2 Bs[kKC][kT / 2];
+    // blockIdx.x enumerates the tile pairs I <= J row by row
+    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    while (p >= rowlen) {
+        p -= rowlen;
+        ++I;
+        --rowlen;
+    }
+    const uint32_t Jt = I + p;
+    const uint32_t I0 = I * kT, J0 = Jt * kT;
+    const uint64_t k0 = (uint64_t)blockIdx.y * kper;
+    const uint64_t k1 = min(H, k0 + kper);
+    if (k0 >= k1) return;
+    const uint32_t tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const bool diag = I == Jt;
+
+    uint32_t acc[8][8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+        for (int y = 0; y < 8; ++y) acc[x][y] = 0;
+
+    // global -> register staging: 4 x 16 B per matrix per thread
+    ulonglong2 ra[4], rb[4];
+    auto gload = [&](uint64_t kb) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t idx = tid + kNT * m;      // 0..1023
+            const uint32_t kk = idx >> 6, cp = idx & 63;
+            const uint64_t k = kb + kk;
+            if (k < k1) {
+                ra[m] = *reinterpret_cast<const ulonglong2 *>(W + k * ldw + I0 + 2 * cp);
+                rb[m] = diag ? ra[m] : *reinterpret_cast<const ulonglong2 *>(W + k * ldw + J0 + 2 * cp);
+            } else {
+                ra[m] = make_ulonglong2(0, 0);
+                rb[m] = make_ulonglong2(0, 0);
+            }
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t idx = tid + kNT * m;
+            As[idx >> 6][idx & 63] = ra[m];
+            Bs[idx >> 6][idx & 63] = rb[m];
+        }
+    };
+
+    gload(k0);
+    for (uint64_t kb = k0; kb < k1; kb += kKC) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (kb + kKC < k1) gload(kb + kKC);
+#pragma unroll 4
+        for (int kk = 0; kk < kKC; ++kk) {
+            uint64_t a[8], b[8];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const ulonglong2 va = As[kk][16 * c + ty];
+                const ulonglong2 vb = Bs[kk][16 * c + tx];
+                a[2 * c] = va.x;
+                a[2 * c + 1] = va.y;
+                b[2 * c] = vb.x;
+                b[2 * c + 1] = vb.y;
+            }
+#pragma unroll
+            for (int x = 0; x < 8; ++x)
+#pragma unroll
+                for (int y = 0; y < 8; ++y) {
+                    const uint64_t v = a[x] & b[y];
+                    acc[x][y] += __popc((uint32_t)v) + __popc((uint32_t)(v >> 32));
+                }
+        }
+    }
+    // epilogue: add the strict upper part of the tile into B
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const uint32_t i = I0 + 32 * (x >> 1) + 2 * ty + (x & 1);
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+            const uint32_t j = J0 + 32 * (y >> 1) + 2 * tx + (y & 1);
+            if (acc[x][y] && i < j && j < n) atomicAdd(B + out_index(i, j, n, upper), (int32_t)acc[x][y]);
+        }
+    }
+}
+
+// Row lists: one thread per row, every pair of its (ascending) samples.
+__global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls, uint64_t nl,
+                             uint32_t n, int32_t *__restrict__ B, int upper) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nl; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a0 = lp[r], a1 = lp[r + 1];
+        for (uint64_t a = a0; a < a1; ++a) {
+            const uint32_t i = ls[a];
+            for (uint64_t b = a + 1; b < a1; ++b) atomicAdd(B + out_index(i, ls[b], n, upper), 1);
+        }
+    }
+}
+
+// Diagonal, mirror (full layout), unions and J.
+__global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ card, uint32_t n, int upper,
+                           uint32_t jblocks, int64_t *__restrict__ den, double *__restrict__ J) {
+    const uint32_t i = blockIdx.x / jblocks;
+    const uint32_t j = (blockIdx.x % jblocks) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (upper && j < i) return;
+    uint64_t pos;
+    int64_t b;
+    if (i == j) {
+        pos = out_index(i, i, n, upper);
+        b = card[i];
+        B[pos] = (int32_t)b;
+    } else if (i < j) {
+        pos = out_index(i, j, n, upper);
+        b = B[pos];
+    } else {
+        pos = (uint64_t)i * n + j;
+        b = B[(uint64_t)j * n + i];
+        B[pos] = (int32_t)b;
+    }
+    const int64_t c = card[i] + card[j] - b;
+    if (den) den[pos] = c;
+    if (J) J[pos] = c == 0 ? 1.0 : (double)b / (double)c;
+}
+
+}  // namespace
+
+void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J) {
+    const uint32_t n = (uint32_t)db->n;
+    const bool upper = flags & JAS_UPPER;
+    const uint64_t len = upper ? (uint64_t)n * (n + 1) / 2 : (uint64_t)n * n;
+    if (n == 0) return;
+    {
+        JAS_TIMED("fill_i32", s);
+        k_fill_i32<<<(uint32_t)std::min<uint64_t>(div_up(len, 256), 65536), 256, 0, s>>>(B, len, 0);
+    }
+    check_launch("zero B");
+    if (db->H > 0 && n >= 2) {
+        const uint32_t nt = (uint32_t)div_up(n, kT);
+        const uint64_t np = (uint64_t)nt * (nt + 1) / 2;
+        // K split: enough blocks to fill 256 CUs several times over
+        const uint64_t want = 2048;
+        uint64_t splits = std::max<uint64_t>(1, div_up(want, np));
+        uint64_t kper = div_up(db->H, splits);
+        kper = std::max<uint64_t>(kper, 64);
+        kper = div_up(kper, kKC) * kKC;
+        splits = div_up(db->H, kper);
+        if (splits > 65535) {
+            splits = 65535;
+            kper = div_up(div_up(db->H, splits), kKC) * kKC;
+            splits = div_up(db->H, kper);
+        }
+        const uint64_t ldw = div_up(n, 128) * 128;
+        dim3 grid((uint32_t)np, (uint32_t)splits);
+        {
+            JAS_TIMED("gram_popc", s);
+            k_gram_popc<<<grid, kNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+        }
+        check_launch("gram popcount");
+    }
+    if (db->n_list > 0) {
+        const uint64_t blocks = std::min<uint64_t>(div_up(db->n_list, 256), 65536);
+        {
+            JAS_TIMED("list_pairs", s);
+            k_list_pairs<<<(uint32_t)blocks, 256, 0, s>>>(db->list_ptr.p, db->list_smp.p, db->n_list, n, B, upper);
+        }
+        check_launch("row list pairs");
+    }
+    const uint32_t jb = (uint32_t)div_up(n, 256);
+    const uint64_t fb = (uint64_t)n * jb;
+    if (fb > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "n too large for finalize grid");
+    {
+        JAS_TIMED("finalize", s);
+        k_finalize<<<(uint32_t)fb, 256, 0, s>>>(B, db->card.p, n, upper, jb, den, J);
+    }
+    check_launch("finalize");
+    if (card) JAS_HIP(hipMemcpyAsync(card, db->card.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace jas

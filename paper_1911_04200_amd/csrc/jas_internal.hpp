@@ -1,0 +1,176 @@
+// Internal declarations of libjas (HIP, gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "jas.h"
+
+namespace jas {
+
+// ---------------------------------------------------------------------------
+// Errors: every failure inside the library throws jas::Error; the C entry
+// points catch it and turn it into a status plus a thread-local message.
+struct Error {
+    jas_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(jas_status st, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define JAS_HIP(call) ::jas::check_hip((call), #call)
+
+// Kernel launch check (launch errors surface on the next runtime call).
+void check_launch(const char *what);
+
+// Scoped per-kernel timer: while timing is enabled (jas_timing_enable), records
+// HIP events around the launch made in its scope.  Use via JAS_TIMED.
+class KernelTimer {
+   public:
+    KernelTimer(const char *name, hipStream_t s);
+    ~KernelTimer();
+
+   private:
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+bool timing_on();
+#define JAS_CAT2(a, b) a##b
+#define JAS_CAT(a, b) JAS_CAT2(a, b)
+#define JAS_TIMED(name, stream) ::jas::KernelTimer JAS_CAT(jas_timer_, __LINE__)(name, stream)
+
+// ---------------------------------------------------------------------------
+// Device memory.  Temporaries use the stream-ordered allocator (hipMallocAsync
+// on the call's stream, memory pool kept warm), long-lived buffers of a db use
+// plain hipMalloc.  Budget accounting covers both.
+struct Budget {
+    uint64_t limit = 0;  // 0 = none
+    uint64_t held = 0;
+    uint64_t peak = 0;
+    Budget *other = nullptr;  // a second account that shares the limit
+    void take(uint64_t bytes, const char *what);
+    void give(uint64_t bytes) { held -= bytes; }
+};
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    hipStream_t s = nullptr;
+    Budget *budget = nullptr;
+    bool async = true;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; s = o.s; budget = o.budget; async = o.async;
+            o.p = nullptr; o.n = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count, hipStream_t stream, Budget *b, bool stream_ordered, const char *what) {
+        release();
+        s = stream; budget = b; async = stream_ordered; n = count;
+        const size_t bytes = (count ? count : 1) * sizeof(T);
+        if (budget) budget->take(bytes, what);
+        hipError_t e = async ? hipMallocAsync((void **)&p, bytes, s) : hipMalloc((void **)&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (budget) budget->give(bytes);
+            p = nullptr; n = 0;
+            fail(JAS_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes for " + what +
+                                 " failed: " + hipGetErrorString(e));
+        }
+    }
+    void release() {
+        if (p) {
+            if (async) (void)hipFreeAsync(p, s);
+            else (void)hipFree(p);
+            if (budget) budget->give((n ? n : 1) * sizeof(T));
+        }
+        p = nullptr; n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+void warm_pool(int device);
+
+// ---------------------------------------------------------------------------
+// The encoded database (jas_db).
+}  // namespace jas
+
+struct jas_db {
+    int device = 0;
+    int32_t n = 0;
+    uint32_t U = 0, sbits = 0, batch_bits = 0, dmin = 0, flags = 0;
+    jas_encode_stats stats{};
+    jas::Budget budget;  // db-owned memory
+    // |X_i|
+    jas::DevBuf<int64_t> card;
+    // packed part: W[H][n] 64-bit words, word row w holds bits of up to 64 rows
+    uint64_t H = 0;
+    jas::DevBuf<uint64_t> W;
+    // row-list part: rows of degree 2..dmin-1, CSR over samples (ascending)
+    uint64_t n_list = 0, list_nnz = 0;
+    jas::DevBuf<uint64_t> list_ptr;   // n_list + 1
+    jas::DevBuf<uint32_t> list_smp;   // list_nnz
+    // query index (JAS_KEEP_IDS): distinct keys (id << sbits | sample) in ascending
+    // order and a table of their start by the top `ibits` bits of the ID.
+    uint64_t n_keys = 0;
+    uint32_t ibits = 0;
+    jas::DevBuf<uint64_t> keys;
+    jas::DevBuf<uint64_t> bucket;     // (1 << ibits) + 1 entries
+};
+
+namespace jas {
+
+// ---------------------------------------------------------------------------
+// Device primitives (each in its own translation unit).
+
+// out[i] = sum_{k<i} in[k] for i in [0, len]; out has len + 1 entries (out[len] = total).
+// tmp: scratch from scan_tmp_elems(len).
+size_t scan_tmp_elems(size_t len);
+void scan_excl_u32(const uint32_t *in, uint64_t *out, size_t len, uint64_t *tmp, hipStream_t s);
+void scan_excl_u64(const uint64_t *in, uint64_t *out, size_t len, uint64_t *tmp, hipStream_t s);
+
+// LSD radix sort of 64-bit keys on bits [lo_bit, hi_bit), stable.  Result in
+// *keys (buffers may be swapped with alt).  Each pass: histogram, scan, scatter.
+struct RadixWork {
+    DevBuf<uint32_t> counts;
+    DevBuf<uint64_t> offs, tmp;
+};
+void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
+                    RadixWork &w, hipStream_t s, Budget *b);
+uint64_t radix_work_bytes(uint64_t N);
+
+// Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U.
+void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
+                uint64_t *keys, uint32_t *err, hipStream_t s);
+
+// Encoding after the sort (see encode.hip).
+void encode_sorted(jas_db *db, const uint64_t *keys, uint64_t N, hipStream_t s, Budget *tmpb);
+
+// Gram and finalize (see gram.hip).
+void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J);
+
+// Query (see query.hip).
+void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint64_t NQ,
+           hipStream_t s, int32_t *B, int64_t *q_card, int64_t *den, double *J);
+uint64_t query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids);
+
+inline uint32_t ceil_log2_u64(uint64_t v) {
+    uint32_t b = 0;
+    while (b < 64 && (uint64_t(1) << b) < v) ++b;
+    return b;
+}
+inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+}  // namespace jas

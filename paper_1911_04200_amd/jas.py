@@ -1,0 +1,213 @@
+"""ctypes binding of libjas (include/jas.h): argument marshalling only.
+
+Every function keeps the C name and order of arguments.  Device buffers are
+torch tensors (their ``data_ptr()``), host buffers numpy arrays (with
+JAS_HOST_PTRS); ``stream`` is a ``torch.cuda.Stream`` or None for torch's
+current stream.  A non-OK status raises :class:`JasError`.  All computation
+happens in the HIP library; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libjas.so")
+
+JAS_OK, JAS_EINVAL, JAS_ENOMEM, JAS_EOVERFLOW, JAS_EDEVICE, JAS_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+JAS_HOST_PTRS = 0x1
+JAS_KEEP_IDS = 0x2
+JAS_UPPER = 0x10
+JAS_FORCE_POPCOUNT = 0x20
+JAS_FORCE_MFMA = 0x40
+
+STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERFLOW", -4: "JAS_EDEVICE",
+                -6: "JAS_EUNSUPPORTED"}
+
+# Every symbol include/jas.h declares.
+EXPORTS = sorted(["jas_encode", "jas_gram", "jas_query", "jas_query_workspace_bytes", "jas_db_size", "jas_db_stats",
+                  "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable", "jas_timing_report"])
+
+
+class JasError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class jas_encode_opts(ctypes.Structure):
+    _fields_ = [("universe_bits", ctypes.c_uint32), ("batch_bits", ctypes.c_uint32),
+                ("dense_min_degree", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class jas_encode_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in
+                ["n_ids", "n_pairs", "n_rows", "n_shared_rows", "n_packed_rows", "n_list_rows", "n_batches",
+                 "n_word_rows", "nnz_words", "word_pairs_F", "list_pairs", "device_bytes"]]
+
+    def to_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class jas_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libjas.so (building it first if it is not there)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        from . import build as _build
+        _build.build(force=False)
+    if not os.path.exists(path):
+        raise ImportError(f"libjas.so not found at {path}; run paper_1911_04200_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, u32, i32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64
+    lib.jas_encode.argtypes = [vp, vp, i32, ctypes.POINTER(jas_encode_opts), vp, ctypes.POINTER(vp),
+                               ctypes.POINTER(jas_encode_stats)]
+    lib.jas_encode.restype = ctypes.c_int
+    lib.jas_gram.argtypes = [vp, u32, vp, vp, vp, vp, vp]
+    lib.jas_gram.restype = ctypes.c_int
+    lib.jas_query.argtypes = [vp, vp, vp, i32, u32, vp, vp, vp, vp, vp]
+    lib.jas_query.restype = ctypes.c_int
+    lib.jas_query_workspace_bytes.argtypes = [vp, i32, u64]
+    lib.jas_query_workspace_bytes.restype = u64
+    lib.jas_db_size.argtypes = [vp]
+    lib.jas_db_size.restype = i32
+    lib.jas_db_stats.argtypes = [vp, ctypes.POINTER(jas_encode_stats)]
+    lib.jas_db_stats.restype = ctypes.c_int
+    lib.jas_db_free.argtypes = [vp]
+    lib.jas_db_free.restype = None
+    lib.jas_last_error.restype = ctypes.c_char_p
+    lib.jas_version.restype = ctypes.c_char_p
+    lib.jas_timing_enable.argtypes = [i32]
+    lib.jas_timing_enable.restype = None
+    lib.jas_timing_report.argtypes = [ctypes.POINTER(jas_kernel_time), i32]
+    lib.jas_timing_report.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != JAS_OK:
+        raise JasError(status, load().jas_last_error().decode())
+
+
+def _ptr(x):
+    """Raw address of a torch tensor, numpy array or int (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data if x.size else None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr() if x.numel() else None
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Db:
+    """Owns a jas_db handle; frees it with jas_db_free."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    @property
+    def n(self) -> int:
+        return jas_db_size(self)
+
+    def close(self):
+        if self.handle:
+            load().jas_db_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _h(db):
+    return db.handle if isinstance(db, Db) else db
+
+
+def jas_encode(ids, offsets, n: int, opts: jas_encode_opts, stream=None):
+    """jas_encode: returns (Db, stats dict)."""
+    lib = load()
+    out = ctypes.c_void_p()
+    st = jas_encode_stats()
+    s = None if (opts.flags & JAS_HOST_PTRS and stream is None) else _stream(stream)
+    _check(lib.jas_encode(_ptr(ids), _ptr(offsets), n, ctypes.byref(opts), s, ctypes.byref(out), ctypes.byref(st)))
+    return Db(out.value), st.to_dict()
+
+
+def jas_gram(db, flags: int, stream, B, card=None, den=None, J=None):
+    lib = load()
+    s = None if (flags & JAS_HOST_PTRS and stream is None) else _stream(stream)
+    _check(lib.jas_gram(_h(db), flags, s, _ptr(B), _ptr(card), _ptr(den), _ptr(J)))
+
+
+def jas_query(db, q_ids, q_offsets, nq: int, flags: int, stream, B, q_card=None, den=None, J=None):
+    lib = load()
+    s = None if (flags & JAS_HOST_PTRS and stream is None) else _stream(stream)
+    _check(lib.jas_query(_h(db), _ptr(q_ids), _ptr(q_offsets), nq, flags, s, _ptr(B), _ptr(q_card), _ptr(den),
+                         _ptr(J)))
+
+
+def jas_query_workspace_bytes(db, nq: int, n_q_ids: int) -> int:
+    return int(load().jas_query_workspace_bytes(_h(db), nq, n_q_ids))
+
+
+def jas_db_size(db) -> int:
+    return int(load().jas_db_size(_h(db)))
+
+
+def jas_db_stats(db) -> dict:
+    st = jas_encode_stats()
+    _check(load().jas_db_stats(_h(db), ctypes.byref(st)))
+    return st.to_dict()
+
+
+def jas_db_free(db):
+    if isinstance(db, Db):
+        db.close()
+    else:
+        load().jas_db_free(db)
+
+
+def jas_last_error() -> str:
+    return load().jas_last_error().decode()
+
+
+def jas_version() -> str:
+    return load().jas_version().decode()
+
+
+def jas_timing_enable(on: bool = True):
+    load().jas_timing_enable(1 if on else 0)
+
+
+def jas_timing_report(cap: int = 64) -> dict:
+    """{kernel name: (launches, total ms)} since the last report; resets the totals."""
+    arr = (jas_kernel_time * cap)()
+    k = load().jas_timing_report(arr, cap)
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(k, cap))}

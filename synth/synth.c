@@ -78,10 +78,9 @@ static inline uint32_t ceil_log2(uint64_t v)
     return b;
 }
 
-/* Bijection on [0, size) by cycle walking a bijection on [0, 2^ceil(log2 size)). */
-static inline uint64_t perm_range(uint64_t x, uint64_t size, uint64_t k0, uint64_t k1)
+/* Bijection on [0, size) by cycle walking a bijection on [0, 2^b), b = ceil(log2 size). */
+static inline uint64_t perm_range(uint64_t x, uint64_t size, uint32_t b, uint64_t k0, uint64_t k1)
 {
-    const uint32_t b = ceil_log2(size);
     if (b == 0) return 0;
     uint64_t y = perm_bits(x, b, k0, k1);
     while (y >= size) y = perm_bits(y, b, k0, k1);
@@ -171,8 +170,9 @@ static void fill_one(const synth_spec *sp, int32_t i, uint64_t *dst)
         const uint64_t start = sp->pool_start[p.cluster], size = sp->pool_size[p.cluster];
         const uint64_t k0 = stream_key(sp->sample_seed, TAG_POOLPERM, 2 * (uint64_t)i);
         const uint64_t k1 = stream_key(sp->sample_seed, TAG_POOLPERM, 2 * (uint64_t)i + 1);
+        const uint32_t b = ceil_log2(size);
         for (uint64_t t = 0; t < p.pool_part; ++t) {
-            const uint64_t g = start + perm_range(t, size, k0, k1);
+            const uint64_t g = start + perm_range(t, size, b, k0, k1);
             dst[t] = perm_bits(g, U, idk0, idk1);
         }
     }

@@ -1,0 +1,87 @@
+"""The C ABI library: symbols and host-side argument checks (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1911_04200_amd import jas
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "jas.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(jas_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = jas.load()
+    names = declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), f"{name} missing from libjas.so"
+    assert sorted(jas.EXPORTS) == names
+
+
+def test_version():
+    assert "gfx950" in jas.jas_version()
+
+
+def _opts(U=24, flags=jas.JAS_HOST_PTRS, **kw):
+    return jas.jas_encode_opts(U, kw.get("batch_bits", 0), kw.get("dmin", 0), flags, kw.get("budget", 0))
+
+
+@pytest.mark.parametrize("offsets,msg", [([1, 3], "offsets[0]"), ([0, 3, 2], "decrease")])
+def test_encode_rejects_bad_host_offsets(offsets, msg):
+    ids = np.arange(3, dtype=np.uint64)
+    with pytest.raises(jas.JasError) as e:
+        jas.jas_encode(ids, np.array(offsets, dtype=np.uint64), len(offsets) - 1, _opts())
+    assert e.value.status == jas.JAS_EINVAL and msg in e.value.message
+
+
+@pytest.mark.parametrize("U", [0, 64, 100])
+def test_encode_rejects_universe_bits(U):
+    ids = np.arange(3, dtype=np.uint64)
+    with pytest.raises(jas.JasError) as e:
+        jas.jas_encode(ids, np.array([0, 3], dtype=np.uint64), 1, _opts(U=U))
+    assert e.value.status == jas.JAS_EINVAL
+
+
+def test_encode_rejects_key_overflow():
+    # 2^20 sets need 20 sample bits: U = 50 leaves no room in a 64-bit key
+    n = 1 << 20
+    off = np.zeros(n + 1, dtype=np.uint64)
+    with pytest.raises(jas.JasError) as e:
+        jas.jas_encode(np.zeros(1, np.uint64), off, n, _opts(U=50))
+    assert e.value.status == jas.JAS_EINVAL and "exceeds 64" in e.value.message
+
+
+def test_null_arguments():
+    lib = jas.load()
+    st = jas.jas_encode_stats()
+    assert lib.jas_encode(None, None, 1, None, None, None, ctypes.byref(st)) == jas.JAS_EINVAL
+    out = ctypes.c_void_p()
+    assert lib.jas_encode(None, None, 1, None, None, ctypes.byref(out), None) == jas.JAS_EINVAL
+    assert "opts" in jas.jas_last_error()
+    o = _opts()
+    assert lib.jas_encode(None, None, -1, ctypes.byref(o), None, ctypes.byref(out), None) == jas.JAS_EINVAL
+    assert lib.jas_encode(None, None, 2, ctypes.byref(o), None, ctypes.byref(out), None) == jas.JAS_EINVAL
+    assert lib.jas_gram(None, 0, None, None, None, None, None) == jas.JAS_EINVAL
+    assert lib.jas_query(None, None, None, 1, 0, None, None, None, None, None) == jas.JAS_EINVAL
+    assert lib.jas_db_size(None) == -1
+    assert lib.jas_db_stats(None, ctypes.byref(st)) == jas.JAS_EINVAL
+    assert lib.jas_query_workspace_bytes(None, 1, 10) == 0
+    lib.jas_db_free(None)
+
+
+def test_error_message_is_thread_local_and_reset():
+    lib = jas.load()
+    assert lib.jas_gram(None, 0, None, None, None, None, None) == jas.JAS_EINVAL
+    assert jas.jas_last_error() != ""
+    st = jas.jas_encode_stats()
+    # a call that fails differently replaces the message
+    assert lib.jas_db_stats(None, ctypes.byref(st)) == jas.JAS_EINVAL
+    assert "jas_db_stats" in jas.jas_last_error()

@@ -1,0 +1,256 @@
+"""HIP path vs the CPU oracle, element by element (needs a gfx950 GPU).
+
+B and the unions are compared as integers, J bit for bit (binary64), |X_i|
+exactly.  Sizes here finish in seconds on the oracle and still span several
+128-column tiles, many row batches and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1911_04200_amd as jas  # noqa: E402
+from paper_1911_04200_amd import jas as cabi  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def gpu_all_pairs(ids, off, U, batch_bits=0, dmin=0, upper=False, flags=0):
+    db, st = jas.encode(dev(ids), dev(off), universe_bits=U, batch_bits=batch_bits, dense_min_degree=dmin)
+    out = jas.gram(db, upper=upper, flags=flags)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    db.close()
+    return res, st
+
+
+def assert_matches(res, ref, upper=False):
+    n = ref["card"].size
+    assert np.array_equal(res["card"], ref["card"]), "|X_i|"
+    if upper:
+        iu = np.triu_indices(n)
+        want = {"B": ref["inter"][iu], "den": ref["union"][iu], "J": ref["J"][iu]}
+    else:
+        want = {"B": ref["inter"], "den": ref["union"], "J": ref["J"]}
+    bad = np.argwhere(res["B"] != want["B"])
+    assert bad.size == 0, f"B differs at {bad[:5].tolist()}"
+    assert np.array_equal(res["den"], want["den"]), "unions differ"
+    assert np.array_equal(res["J"].view(np.uint64), want["J"].view(np.uint64)), "J differs"
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    spec = synth.workload("tiny")
+    ids, off = synth.generate(spec)
+    return spec, ids, off, oracle.all_pairs(ids, off)
+
+
+# (batch_bits, dense_min_degree, upper): one batch .. 2^20 batches, every row packed .. no row packed
+VARIANTS = [(24, 0, False), (24, 0, True), (16, 2, False), (10, 3, False), (4, 5, True), (24, 1000, False),
+            (12, 8, False), (20, 4, True)]
+
+
+@pytest.mark.parametrize("bb,dmin,upper", VARIANTS)
+def test_tiny_workload(tiny, bb, dmin, upper):
+    spec, ids, off, ref = tiny
+    res, st = gpu_all_pairs(ids, off, spec.universe_bits, bb, dmin, upper)
+    assert_matches(res, ref, upper)
+    assert st["n_ids"] == ids.size
+    assert st["n_pairs"] == int(ref["card"].sum())
+
+
+SCALED = {
+    # structure of each workload at sizes the oracle finishes in seconds
+    "paperlike": dict(n=300, size_scale=0.004, pool_scale=0.004),
+    "precision": dict(n=257, size_scale=0.01, pool_scale=0.01),
+    "batching": dict(n=400, size_scale=0.004, pool_scale=0.004),
+    "serving_db": dict(n=200, size_scale=0.01, pool_scale=0.005),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SCALED))
+@pytest.mark.parametrize("dmin", [0, 6])
+def test_scaled_workloads(name, dmin):
+    spec = synth.scaled(synth.workload(name), **SCALED[name])
+    ids, off = synth.generate(spec)
+    ref = oracle.all_pairs(ids, off)
+    res, st = gpu_all_pairs(ids, off, spec.universe_bits, synth.BATCH_BITS[name], dmin, upper=(dmin == 6))
+    assert_matches(res, ref, upper=(dmin == 6))
+    assert st["n_packed_rows"] + st["n_list_rows"] == st["n_shared_rows"] > 0
+    if dmin == 0:
+        assert st["n_packed_rows"] == st["n_shared_rows"]
+    else:
+        assert st["n_list_rows"] > 0
+
+
+def test_duplicates_and_empty_sets():
+    spec = synth.scaled(synth.workload("tiny"), n=40, dup_rate=0.3)
+    ids, off = synth.generate(spec)
+    # make sets 3, 17 and 39 empty and set 20 a copy of set 5
+    sets = [ids[int(off[i]):int(off[i + 1])] for i in range(40)]
+    sets[3] = sets[17] = sets[39] = np.zeros(0, np.uint64)
+    sets[20] = sets[5].copy()
+    off2 = np.zeros(41, np.uint64)
+    off2[1:] = np.cumsum([s.size for s in sets])
+    ids2 = np.concatenate(sets)
+    ref = oracle.all_pairs(ids2, off2)
+    for dmin in (0, 4):
+        res, _ = gpu_all_pairs(ids2, off2, 24, 14, dmin)
+        assert_matches(res, ref)
+    assert res["J"][3, 17] == 1.0 and res["J"][3, 5] == 0.0 and res["J"][5, 20] == 1.0
+
+
+@pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 255, 257])
+def test_tile_edges(n):
+    rng = np.random.default_rng(n)
+    core = rng.choice(1 << 20, 3000, replace=False).astype(np.uint64)
+    sets = [np.concatenate([rng.choice(core, int(rng.integers(0, 2000)), replace=False),
+                            rng.integers(0, 1 << 20, int(rng.integers(0, 300))).astype(np.uint64)])
+            for _ in range(n)]
+    off = np.zeros(n + 1, np.uint64)
+    off[1:] = np.cumsum([s.size for s in sets])
+    ids = np.concatenate(sets) if n else np.zeros(0, np.uint64)
+    ref = oracle.all_pairs(ids, off)
+    res, _ = gpu_all_pairs(ids, off, 20, 12, 0)
+    assert_matches(res, ref)
+    res, _ = gpu_all_pairs(ids, off, 20, 0, 0, upper=True)
+    assert_matches(res, ref, upper=True)
+
+
+def test_all_sets_empty():
+    off = np.zeros(6, np.uint64)
+    ids = np.zeros(0, np.uint64)
+    db, st = jas.encode(dev(np.zeros(1, np.uint64))[:0], dev(off), universe_bits=16)
+    out = jas.gram(db)
+    torch.cuda.synchronize()
+    assert st["n_pairs"] == 0
+    assert np.all(out["B"].cpu().numpy() == 0)
+    assert np.all(out["J"].cpu().numpy() == 1.0)
+    assert np.all(out["den"].cpu().numpy() == 0)
+    db.close()
+    ref = oracle.all_pairs(ids, off)
+    assert np.all(ref["J"] == 1.0)
+
+
+def test_zero_sets():
+    db, st = jas.encode(dev(np.zeros(1, np.uint64))[:0], dev(np.zeros(1, np.uint64)), universe_bits=16)
+    assert db.n == 0
+    out = jas.gram(db)
+    assert out["B"].numel() == 0
+    db.close()
+
+
+@pytest.mark.parametrize("U,n", [(63, 2), (62, 3), (1, 3), (2, 5), (40, 1024)])
+def test_universe_extremes(U, n):
+    rng = np.random.default_rng(U * 1000 + n)
+    top = (1 << U) - 1
+    base = np.array([top, top - 1, 0, top // 2, top // 3], dtype=np.uint64)[: min(5, 1 << U)]
+    sets = [np.unique(np.concatenate([rng.choice(base, int(rng.integers(0, base.size + 1))),
+                                      rng.integers(0, top, 3, dtype=np.uint64, endpoint=True)]))
+            for _ in range(n)]
+    off = np.zeros(n + 1, np.uint64)
+    off[1:] = np.cumsum([s.size for s in sets])
+    ids = np.concatenate(sets)
+    ref = oracle.all_pairs(ids, off)
+    res, _ = gpu_all_pairs(ids, off, U, 0, 0)
+    assert_matches(res, ref)
+
+
+def test_id_outside_universe_is_rejected():
+    ids = np.array([1, 2, 1 << 20], dtype=np.uint64)
+    with pytest.raises(jas.JasError) as e:
+        jas.encode(dev(ids), dev(np.array([0, 3], np.uint64)), universe_bits=20)
+    assert e.value.status == cabi.JAS_EINVAL
+
+
+def test_budget_is_enforced():
+    spec = synth.workload("tiny")
+    ids, off = synth.generate(spec)
+    with pytest.raises(jas.JasError) as e:
+        jas.encode(dev(ids), dev(off), universe_bits=24, hbm_budget_bytes=1 << 20)
+    assert e.value.status == cabi.JAS_ENOMEM
+
+
+def test_host_pointers_match_device_path(tiny):
+    spec, ids, off, ref = tiny
+    opts = cabi.jas_encode_opts(24, 16, 0, cabi.JAS_HOST_PTRS, 0)
+    db, st = cabi.jas_encode(ids, off, 32, opts)
+    B = np.empty((32, 32), np.int32)
+    card = np.empty(32, np.int64)
+    den = np.empty((32, 32), np.int64)
+    J = np.empty((32, 32), np.float64)
+    cabi.jas_gram(db, cabi.JAS_HOST_PTRS, None, B, card, den, J)
+    db.close()
+    assert_matches({"B": B, "card": card, "den": den, "J": J}, ref)
+
+
+def test_repeat_runs_are_identical():
+    spec = synth.scaled(synth.workload("precision"), n=300, size_scale=0.01, pool_scale=0.01)
+    ids, off = synth.generate(spec)
+    db, _ = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, dense_min_degree=4)
+    a = jas.gram(db)["B"].cpu().numpy()
+    b = jas.gram(db)["B"].cpu().numpy()
+    db.close()
+    assert np.array_equal(a, b)
+
+
+# --- query path -------------------------------------------------------------
+def test_query_matches_oracle():
+    spec = synth.scaled(synth.workload("serving_db"), n=150, size_scale=0.01, pool_scale=0.005)
+    ids, off = synth.generate(spec)
+    db, _ = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, batch_bits=26, keep_ids=True,
+                       dense_min_degree=5)
+    qspec = synth.scaled(synth.query_spec(spec, 0, 9), size_scale=0.01)
+    qi, qo = synth.generate(qspec)
+    # add DB sets 0 and 7, an empty set, and a set with repeats and IDs absent from the DB
+    extra = [ids[int(off[0]):int(off[1])], ids[int(off[7]):int(off[8])], np.zeros(0, np.uint64),
+             np.array([5, 5, 5, (1 << 36) - 1, 123456789], np.uint64)]
+    sets = [qi[int(qo[i]):int(qo[i + 1])] for i in range(9)] + extra
+    qoff = np.zeros(len(sets) + 1, np.uint64)
+    qoff[1:] = np.cumsum([s.size for s in sets])
+    qids = np.concatenate(sets)
+    ref = oracle.cross(qids, qoff, ids, off)
+    out = jas.query(db, dev(qids), dev(qoff))
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    db.close()
+    assert np.array_equal(res["q_card"], ref["q_card"])
+    assert np.array_equal(res["B"], ref["inter"])
+    assert np.array_equal(res["den"], ref["union"])
+    assert np.array_equal(res["J"].view(np.uint64), ref["J"].view(np.uint64))
+
+
+def test_query_row_equals_gram_row():
+    spec = synth.scaled(synth.workload("batching"), n=120, size_scale=0.004, pool_scale=0.004)
+    ids, off = synth.generate(spec)
+    db, _ = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, batch_bits=26, keep_ids=True)
+    g = jas.gram(db)
+    rows = [3, 50, 119]
+    qs = [ids[int(off[i]):int(off[i + 1])] for i in rows]
+    qoff = np.zeros(4, np.uint64)
+    qoff[1:] = np.cumsum([s.size for s in qs])
+    out = jas.query(db, dev(np.concatenate(qs)), dev(qoff))
+    torch.cuda.synchronize()
+    assert torch.equal(out["B"], g["B"][rows])
+    assert torch.equal(out["J"], g["J"][rows])
+    db.close()
+
+
+def test_query_requires_index_and_rejects_bad_ids():
+    spec = synth.workload("tiny")
+    ids, off = synth.generate(spec)
+    db, _ = jas.encode(dev(ids), dev(off), universe_bits=24)
+    with pytest.raises(jas.JasError):
+        jas.query(db, dev(ids[:10]), dev(np.array([0, 10], np.uint64)))
+    db.close()
+    db, _ = jas.encode(dev(ids), dev(off), universe_bits=24, keep_ids=True)
+    with pytest.raises(jas.JasError) as e:
+        jas.query(db, dev(np.array([1 << 24], np.uint64)), dev(np.array([0, 1], np.uint64)))
+    assert e.value.status == cabi.JAS_EINVAL
+    db.close()
