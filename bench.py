@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
+MFMA_I8_PEAK_TOPS = 5000.0     # dense int8 MFMA, TOP/s
 
 
 def log(msg):
@@ -57,6 +58,10 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
     if kernel == "pack":
         ldw = math.ceil(n / 128) * 128
         return "hbm", 8.0 * stats["n_word_rows"] * ldw / 1e9, "GB/s", "8 B per packed word written"
+    if kernel == "gram_mfma":
+        nt = math.ceil(n / 128)
+        macs = stats["n_word_rows"] * 64 * (nt * (nt + 1) // 2) * 128 * 128
+        return "mfma", 2.0 * macs / 1e12, "TOP/s", "2 int8 ops per bit pair of every packed word pair (MACs x 2)"
     if kernel == "gram_popc":
         nt = math.ceil(n / 128)
         wp = stats["n_word_rows"] * (nt * (nt + 1) // 2) * 128 * 128
@@ -99,6 +104,7 @@ def main():
     ap.add_argument("--workload", default="paperlike", choices=["tiny", "paperlike", "precision", "batching"])
     ap.add_argument("--dmin", type=int, default=0, help="dense_min_degree (0: library default)")
     ap.add_argument("--upper", action="store_true", help="packed upper-triangle outputs")
+    ap.add_argument("--path", default="auto", choices=["auto", "popcount", "mfma"], help="Gram path for packed tiles")
     ap.add_argument("--cpu-sample", type=int, default=64, help="sets in the oracle's timed sample (0: skip)")
     ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing in the timed region")
     args = ap.parse_args()
@@ -142,6 +148,7 @@ def main():
     J = torch.empty(length, dtype=torch.float64, device=dev)
     opts = cabi.jas_encode_opts(spec.universe_bits, bb, args.dmin, 0, 0)
     flags = cabi.JAS_UPPER if args.upper else 0
+    flags |= {"auto": 0, "popcount": cabi.JAS_FORCE_POPCOUNT, "mfma": cabi.JAS_FORCE_MFMA}[args.path]
 
     def step():
         db, st = cabi.jas_encode(ids_d, off_d, n, opts, stream)
@@ -173,7 +180,10 @@ def main():
     roof = None
     passes = math.ceil(spec.universe_bits / 8)
     kernels = {name: {"launches": c, "ms_per_step": ms / args.steps, "ms_per_launch": ms / max(c, 1)}
-               for name, (c, ms) in kt.items()}
+               for name, (c, ms) in kt.items() if not name.startswith("host:")}
+    host_phases = {name[5:]: {"calls": c, "ms_per_step": ms / args.steps}
+                   for name, (c, ms) in kt.items() if name.startswith("host:")}
+    kt = {k: v for k, v in kt.items() if not k.startswith("host:")}
     if kt:
         dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
         c, ms = kt[dom]
@@ -182,7 +192,7 @@ def main():
             bound, amount, unit, desc = alg
             avg_s = ms / c / 1e3
             achieved = amount / avg_s
-            peak = HBM_PEAK_GBS if bound == "hbm" else VALU_PEAK_TOPS
+            peak = {"hbm": HBM_PEAK_GBS, "alu": VALU_PEAK_TOPS, "mfma": MFMA_I8_PEAK_TOPS}[bound]
             traffic = None
             tf = os.path.join(ROOT, "profiles", "traffic.json")
             if os.path.exists(tf):
@@ -193,14 +203,14 @@ def main():
                     "frac": achieved / peak, "traffic": traffic, "per_launch": desc,
                     "avg_launch_ms": ms / c}
     # word-pair rates of the popcount Gram
-    gram_ms = kt.get("gram_popc", (0, 0.0))[1] / max(args.steps, 1)
+    gram_ms = (kt.get("gram_popc", (0, 0.0))[1] + kt.get("gram_mfma", (0, 0.0))[1]) / max(args.steps, 1)
     nt = math.ceil(n / 128)
     executed = st["n_word_rows"] * (nt * (nt + 1) // 2) * 128 * 128
     extra = {"gram_ms": gram_ms,
              "G_bit_ANDs_per_s_executed": (64.0 * executed / (gram_ms / 1e3) / 1e9) if gram_ms else None,
              "G_bit_ANDs_per_s_algorithmic_F": (64.0 * st["word_pairs_F"] / (gram_ms / 1e3) / 1e9) if gram_ms
              else None,
-             "encode_stats": st, "kernels": kernels}
+             "encode_stats": st, "kernels": kernels, "host_phases": host_phases}
 
     cpu = None
     if args.cpu_sample > 0:

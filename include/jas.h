@@ -154,6 +154,12 @@ const char *jas_last_error(void);
 /* Library version string. */
 const char *jas_version(void);
 
+/* Device memory: the library keeps freed device buffers for reuse by later
+ * calls (ordered across streams by events), so repeated calls of the same size
+ * allocate nothing.  jas_trim synchronises the device and returns every cached
+ * buffer to it.  Buffers held by live dbs are not affected. */
+void jas_trim(void);
+
 /*
  * Per-kernel timing (tracing).  While enabled, the library records a HIP event
  * before and after every kernel it launches, on the stream it launches the

@@ -34,9 +34,6 @@ jas_status guard(F &&f) {
     }
 }
 
-std::mutex g_pool_mu;
-std::set<int> g_pool_warm;
-
 __global__ void k_zero_u32(uint32_t *p) { *p = 0; }
 
 // Offsets to the host and validated: offsets[0] = 0, non-decreasing.
@@ -79,19 +76,6 @@ void Budget::take(uint64_t bytes, const char *what) {
     if (held > peak) peak = held;
 }
 
-// Keep freed stream-ordered memory in the device pool between calls.
-void warm_pool(int device) {
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (g_pool_warm.count(device)) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-        uint64_t thr = ~0ull;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    (void)hipGetLastError();
-    g_pool_warm.insert(device);
-}
-
 }  // namespace jas
 
 using namespace jas;
@@ -117,13 +101,20 @@ void jas_db_free(jas_db *db) {
     const int dev = db->device;
     (void)hipGetDevice(&cur);
     if (cur != dev) (void)hipSetDevice(dev);
-    (void)hipDeviceSynchronize();
-    delete db;
+    {
+        JAS_HOST_TIMED("db_free_sync");
+        (void)hipDeviceSynchronize();
+    }
+    {
+        JAS_HOST_TIMED("db_free");
+        delete db;
+    }
     if (cur != dev) (void)hipSetDevice(cur);
 }
 
 jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, const jas_encode_opts *opts,
                       void *hip_stream, jas_db **db_out, jas_encode_stats *stats) {
+    JAS_HOST_TIMED("jas_encode");
     return guard([&] {
         if (!db_out) fail(JAS_EINVAL, "jas_encode: db_out is NULL");
         *db_out = nullptr;
@@ -142,7 +133,6 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
         if (host && hoff[n] > 0 && !ids) fail(JAS_EINVAL, "jas_encode: ids is NULL");
         int dev = 0;
         JAS_HIP(hipGetDevice(&dev));
-        warm_pool(dev);
         if (!host && n > 0) hoff = host_offsets(offsets, n, false, s, "jas_encode");
         const uint64_t N = hoff[n];
         if (N > 0 && !ids) fail(JAS_EINVAL, "jas_encode: ids is NULL");
@@ -194,9 +184,16 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
             ids_d.release();
             off_d.release();
             RadixWork rw;
+            JAS_HOST_TIMED("sort_enqueue");
             radix_sort_u64(keys, alt, N, sbits, sbits + U, rw, s, &tb);
         }
-        encode_sorted(db.get(), keys.p, N, s, &tb);
+        try {
+            encode_sorted(db.get(), keys.p, N, s, &tb);
+        } catch (...) {
+            // the db's buffers return to the cache as idle: let their kernels finish first
+            (void)hipStreamSynchronize(s);
+            throw;
+        }
         keys.release();
         db->budget.limit = 0;
         db->budget.other = nullptr;
@@ -218,6 +215,7 @@ jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t 
         const uint64_t n = (uint64_t)db->n;
         const uint64_t len = (flags & JAS_UPPER) ? n * (n + 1) / 2 : n * n;
         if (!(flags & JAS_HOST_PTRS)) {
+            JAS_HOST_TIMED("jas_gram");
             gram(db, flags, s, B, card, den, J);
             return;
         }

@@ -220,9 +220,10 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // Rows: degree split.
-__global__ void k_row_flags(const uint64_t *row_ptr, uint64_t R, uint32_t dmin, uint32_t *fDense,
-                            uint32_t *fList, unsigned long long *st) {
-    unsigned long long lp = 0;
+__global__ __launch_bounds__(kNT) void k_row_flags(const uint64_t *row_ptr, uint64_t R, uint32_t dmin,
+                                                    uint32_t *fDense, uint32_t *fList, unsigned long long *st) {
+    __shared__ uint64_t sh[kWaves];
+    uint64_t lp = 0;
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t d = row_ptr[r + 1] - row_ptr[r];
         const bool dense = d >= dmin;
@@ -230,7 +231,9 @@ __global__ void k_row_flags(const uint64_t *row_ptr, uint64_t R, uint32_t dmin, 
         fList[r] = !dense;
         if (!dense) lp += d * (d - 1) / 2;
     }
-    if (lp) atomicAdd(&st[ST_LISTPAIRS], lp);
+    uint64_t tot;
+    block_excl_scan<kNT>(lp, sh, &tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(&st[ST_LISTPAIRS], (unsigned long long)tot);
 }
 
 __global__ void k_row_compact(uint64_t R, const uint32_t *fDense, const uint64_t *pDense, const uint64_t *pList,
@@ -273,7 +276,10 @@ __global__ void k_word_rows(uint64_t QD, const uint64_t *bpos, const uint64_t *b
     }
 }
 
-// One block per word row: OR the bits of its rows into LDS, write the row out.
+// One block per word row: OR the bits of its <= 64 rows into an LDS row of
+// words and write it out.  Wave 0 loads the rows' list starts and degrees and
+// scans them, then all threads walk the word row's (row, sample) pairs in
+// parallel (consecutive threads read consecutive samples of a row).
 __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t ldw, uint64_t H,
                                                const uint64_t *__restrict__ wq0, const uint64_t *__restrict__ wq1,
                                                const uint64_t *__restrict__ Drow,
@@ -281,23 +287,41 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
                                                const uint32_t *__restrict__ S, uint32_t cols,
                                                unsigned long long *st) {
     extern __shared__ unsigned long long lw[];
+    __shared__ uint64_t rstart[kWave + 1];  // exclusive prefix of the rows' degrees
+    __shared__ uint64_t rbase[kWave];       // first pair of each row in S
     __shared__ uint32_t zsh;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    unsigned long long nnz_acc = 0, f_acc = 0;  // this block's totals (thread 0)
     for (uint64_t w = blockIdx.x; w < H; w += gridDim.x) {
-        const uint64_t q0 = wq0[w], q1 = wq1[w];
+        if (tid < kWave) {
+            const uint64_t q0 = wq0[w], q1 = wq1[w];
+            uint64_t base = 0, deg = 0;
+            if (q0 + lane < q1) {
+                const uint64_t r = Drow[q0 + lane];
+                base = row_ptr[r];
+                deg = row_ptr[r + 1] - base;
+            }
+            const uint64_t inc = wave_incl_scan(deg);
+            rstart[lane + 1] = inc;
+            if (lane == 0) rstart[0] = 0;
+            rbase[lane] = base;
+        }
         if (tid == 0) zsh = 0;
         for (uint64_t c0 = 0; c0 < ldw; c0 += cols) {
             const uint32_t cn = (uint32_t)min((uint64_t)cols, ldw - c0);
             for (uint32_t i = tid; i < cn; i += kNT) lw[i] = 0;
             __syncthreads();
-            for (uint64_t q = q0 + wv; q < q1; q += kWaves) {
-                const unsigned long long bit = 1ull << (q - q0);
-                const uint64_t r = Drow[q];
-                const uint64_t a1 = row_ptr[r + 1];
-                for (uint64_t a = row_ptr[r] + lane; a < a1; a += kWave) {
-                    const uint64_t s = S[a];
-                    if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], bit);
+            const uint64_t P = rstart[kWave];
+            for (uint64_t p = tid; p < P; p += kNT) {
+                // row t of the word: largest t with rstart[t] <= p
+                uint32_t lo = 0, hi = kWave - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (rstart[mid] <= p) lo = mid;
+                    else hi = mid - 1;
                 }
+                const uint64_t s = S[rbase[lo] + (p - rstart[lo])];
+                if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], 1ull << lo);
             }
             __syncthreads();
             uint32_t z = 0;
@@ -311,10 +335,14 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
         }
         if (tid == 0) {
             const unsigned long long z = zsh;
-            atomicAdd(&st[ST_NNZW], z);
-            atomicAdd(&st[ST_F], z * (z + 1) / 2);
+            nnz_acc += z;
+            f_acc += z * (z + 1) / 2;
         }
         __syncthreads();
+    }
+    if (tid == 0 && nnz_acc) {
+        atomicAdd(&st[ST_NNZW], nnz_acc);
+        atomicAdd(&st[ST_F], f_acc);
     }
 }
 
@@ -352,6 +380,7 @@ void launch_1d(uint64_t work, hipStream_t s, F f) {
 }
 
 uint64_t to_host_u64(const uint64_t *dptr, hipStream_t s) {
+    JAS_HOST_TIMED("readback_sync");
     uint64_t v = 0;
     JAS_HIP(hipMemcpyAsync(&v, dptr, sizeof(v), hipMemcpyDeviceToHost, s));
     JAS_HIP(hipStreamSynchronize(s));
@@ -541,7 +570,7 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         check_launch("word rows");
         db->W.alloc(H * ldw, s, &db->budget, false, "packed words");
         const uint32_t cols = (uint32_t)std::min<uint64_t>(ldw, kPackCols);
-        const uint32_t grid = (uint32_t)std::min<uint64_t>(H, 1u << 20);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(H, 4096);
         {
             JAS_TIMED("pack", s);
             k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, wq0.p, wq1.p, Drow.p, row_ptr.p,

@@ -122,6 +122,103 @@ __global__ __launch_bounds__(kNT) void k_gram_popc(const uint64_t *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// int8 MFMA form of the same product.  Each bit of a packed word becomes a
+// 0/1 byte in registers (never in memory) and V_MFMA_I32_32X32X32_I8 sums
+// the byte products in int32: sum_k a_ki a_kj over the 32 bits of a half
+// word, exact (every partial sum is a count <= 2^31).  The K order inside
+// the instruction does not matter: lane group g (lanes 32g..32g+31) feeds
+// bits 16g..16g+15 of the half word for both operands, so every bit pairs
+// with itself.
+// Block = 2 waves over a 128 x 128 tile; wave c owns columns 64c..64c+63,
+// i.e. 4 x 2 MFMA tiles of 32 x 32 (128 int32 accumulators per lane).
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ v4i bits16_to_bytes(uint32_t x) {
+    // byte b of the result = bit b of x (0 or 1)
+    v4i r;
+    r[0] = (int)(((x & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[1] = (int)((((x >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[2] = (int)((((x >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[3] = (int)((((x >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+    return r;
+}
+
+constexpr int kMfmaNT = 128;
+
+__global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gram_mfma(const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H,
+                                                        uint64_t kper, uint32_t nt, uint32_t n,
+                                                        int32_t *__restrict__ B, int upper) {
+    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    while (p >= rowlen) {
+        p -= rowlen;
+        ++I;
+        --rowlen;
+    }
+    const uint32_t Jt = I + p;
+    const uint64_t k0 = (uint64_t)blockIdx.y * kper;
+    const uint64_t k1 = min(H, k0 + kper);
+    if (k0 >= k1) return;
+    const uint32_t lane = threadIdx.x & 63, wc = threadIdx.x >> 6;
+    const uint32_t lm = lane & 31, lg = lane >> 5;
+    const uint32_t I0 = I * kT, J0 = Jt * kT + 64 * wc;
+    // in a diagonal tile the wave's 128 x 64 block has rows >= its first column only partly
+    v16i acc[4][2];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0;
+
+    const uint64_t *pa = W + I0 + lm;
+    const uint64_t *pb = W + J0 + lm;
+    uint64_t a[4], b[2];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) a[x] = pa[k0 * ldw + 32 * x];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) b[y] = pb[k0 * ldw + 32 * y];
+    for (uint64_t k = k0; k < k1; ++k) {
+        uint64_t na[4], nb[2];
+        const uint64_t kn = (k + 1 < k1) ? k + 1 : k;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) na[x] = pa[kn * ldw + 32 * x];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) nb[y] = pb[kn * ldw + 32 * y];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t sh = 32 * h + 16 * lg;
+            v4i va[4], vb[2];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) va[x] = bits16_to_bytes((uint32_t)(a[x] >> sh) & 0xFFFFu);
+#pragma unroll
+            for (int y = 0; y < 2; ++y) vb[y] = bits16_to_bytes((uint32_t)(b[y] >> sh) & 0xFFFFu);
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(va[x], vb[y], acc[x][y], 0, 0, 0);
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x) a[x] = na[x];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) b[y] = nb[y];
+    }
+    // accumulator r of lane (lg, lm) holds row 8*(r/4) + 4*lg + r%4, column lm of each 32 x 32 tile
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t i = I0 + 32 * x + 8 * (r >> 2) + 4 * lg + (r & 3);
+                const uint32_t j = J0 + 32 * y + lm;
+                const int32_t v = acc[x][y][r];
+                if (v && i < j && j < n) atomicAdd(B + out_index(i, j, n, upper), v);
+            }
+}
+
 // Row lists: one thread per row, every pair of its (ascending) samples.
 __global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls, uint64_t nl,
                              uint32_t n, int32_t *__restrict__ B, int upper) {
@@ -189,11 +286,14 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         }
         const uint64_t ldw = div_up(n, 128) * 128;
         dim3 grid((uint32_t)np, (uint32_t)splits);
-        {
+        if (flags & JAS_FORCE_POPCOUNT) {
             JAS_TIMED("gram_popc", s);
             k_gram_popc<<<grid, kNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+        } else {
+            JAS_TIMED("gram_mfma", s);
+            k_gram_mfma<<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
         }
-        check_launch("gram popcount");
+        check_launch("gram");
     }
     if (db->n_list > 0) {
         const uint64_t blocks = std::min<uint64_t>(div_up(db->n_list, 256), 65536);

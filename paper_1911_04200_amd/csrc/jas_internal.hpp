@@ -39,14 +39,31 @@ class KernelTimer {
     hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 bool timing_on();
+// Scoped host-side timer (wall clock), reported as "host:<name>" beside the kernels.
+class HostTimer {
+   public:
+    explicit HostTimer(const char *name);
+    ~HostTimer();
+
+   private:
+    const char *name_;
+    double t0_ = -1.0;
+};
+#define JAS_HOST_TIMED(name) ::jas::HostTimer JAS_CAT(jas_htimer_, __LINE__)(name)
 #define JAS_CAT2(a, b) a##b
 #define JAS_CAT(a, b) JAS_CAT2(a, b)
 #define JAS_TIMED(name, stream) ::jas::KernelTimer JAS_CAT(jas_timer_, __LINE__)(name, stream)
 
 // ---------------------------------------------------------------------------
-// Device memory.  Temporaries use the stream-ordered allocator (hipMallocAsync
-// on the call's stream, memory pool kept warm), long-lived buffers of a db use
-// plain hipMalloc.  Budget accounting covers both.
+// Device memory.  Every buffer comes from the library's cache (memory.hip):
+// blocks are reused across calls and streams (ordered by events), so steady
+// state calls make no hipMalloc/hipFree.  Budget accounting is per call.
+void *cache_alloc(size_t bytes, hipStream_t s, const char *what);
+// synced: the caller has synchronised every stream that used the block.
+void cache_free(void *p, bool synced);
+void cache_trim();
+uint64_t cache_bytes();
+
 struct Budget {
     uint64_t limit = 0;  // 0 = none
     uint64_t held = 0;
@@ -60,9 +77,8 @@ template <class T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
-    hipStream_t s = nullptr;
     Budget *budget = nullptr;
-    bool async = true;
+    bool owned_by_db = false;  // freed by jas_db_free after a device synchronisation
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -70,30 +86,31 @@ struct DevBuf {
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; n = o.n; s = o.s; budget = o.budget; async = o.async;
+            p = o.p; n = o.n; budget = o.budget; owned_by_db = o.owned_by_db;
             o.p = nullptr; o.n = 0;
         }
         return *this;
     }
     ~DevBuf() { release(); }
-    void alloc(size_t count, hipStream_t stream, Budget *b, bool stream_ordered, const char *what) {
+    // db_owned = false: a temporary of the call (stream-ordered reuse);
+    // db_owned = true: part of a jas_db.
+    void alloc(size_t count, hipStream_t stream, Budget *b, bool temporary, const char *what) {
         release();
-        s = stream; budget = b; async = stream_ordered; n = count;
         const size_t bytes = (count ? count : 1) * sizeof(T);
-        if (budget) budget->take(bytes, what);
-        hipError_t e = async ? hipMallocAsync((void **)&p, bytes, s) : hipMalloc((void **)&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            if (budget) budget->give(bytes);
-            p = nullptr; n = 0;
-            fail(JAS_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes for " + what +
-                                 " failed: " + hipGetErrorString(e));
+        if (b) b->take(bytes, what);
+        try {
+            p = static_cast<T *>(cache_alloc(bytes, stream, what));
+        } catch (...) {
+            if (b) b->give(bytes);
+            throw;
         }
+        n = count;
+        budget = b;
+        owned_by_db = !temporary;
     }
     void release() {
         if (p) {
-            if (async) (void)hipFreeAsync(p, s);
-            else (void)hipFree(p);
+            cache_free(p, owned_by_db);
             if (budget) budget->give((n ? n : 1) * sizeof(T));
         }
         p = nullptr; n = 0;
@@ -101,7 +118,7 @@ struct DevBuf {
     size_t bytes() const { return n * sizeof(T); }
 };
 
-void warm_pool(int device);
+
 
 // ---------------------------------------------------------------------------
 // The encoded database (jas_db).

@@ -1,5 +1,6 @@
 // Per-kernel timing with HIP events (jas_timing_enable / jas_timing_report).
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <string>
@@ -40,6 +41,23 @@ KernelTimer::~KernelTimer() {
     (void)hipEventRecord(b_, s_);
     std::lock_guard<std::mutex> lk(g_mu);
     g_pending.push_back({name_, a_, b_});
+}
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+HostTimer::HostTimer(const char *name) : name_(name) {
+    if (g_on) t0_ = now_ms();
+}
+
+HostTimer::~HostTimer() {
+    if (t0_ < 0) return;
+    const double dt = now_ms() - t0_;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto &e = g_acc[std::string("host:") + name_];
+    e.first += 1;
+    e.second += dt;
 }
 
 }  // namespace jas

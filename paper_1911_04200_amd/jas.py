@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
 
 # Every symbol include/jas.h declares.
 EXPORTS = sorted(["jas_encode", "jas_gram", "jas_query", "jas_query_workspace_bytes", "jas_db_size", "jas_db_stats",
-                  "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable", "jas_timing_report"])
+                  "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable", "jas_timing_report", "jas_trim"])
 
 
 class JasError(RuntimeError):
@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.jas_db_free.restype = None
     lib.jas_last_error.restype = ctypes.c_char_p
     lib.jas_version.restype = ctypes.c_char_p
+    lib.jas_trim.argtypes = []
+    lib.jas_trim.restype = None
     lib.jas_timing_enable.argtypes = [i32]
     lib.jas_timing_enable.restype = None
     lib.jas_timing_report.argtypes = [ctypes.POINTER(jas_kernel_time), i32]
@@ -211,3 +213,7 @@ def jas_timing_report(cap: int = 64) -> dict:
     arr = (jas_kernel_time * cap)()
     k = load().jas_timing_report(arr, cap)
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(k, cap))}
+
+
+def jas_trim():
+    load().jas_trim()

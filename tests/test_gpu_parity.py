@@ -57,9 +57,11 @@ VARIANTS = [(24, 0, False), (24, 0, True), (16, 2, False), (10, 3, False), (4, 5
 
 
 @pytest.mark.parametrize("bb,dmin,upper", VARIANTS)
-def test_tiny_workload(tiny, bb, dmin, upper):
+@pytest.mark.parametrize("path", ["popcount", "mfma"])
+def test_tiny_workload(tiny, bb, dmin, upper, path):
     spec, ids, off, ref = tiny
-    res, st = gpu_all_pairs(ids, off, spec.universe_bits, bb, dmin, upper)
+    flags = cabi.JAS_FORCE_POPCOUNT if path == "popcount" else cabi.JAS_FORCE_MFMA
+    res, st = gpu_all_pairs(ids, off, spec.universe_bits, bb, dmin, upper, flags)
     assert_matches(res, ref, upper)
     assert st["n_ids"] == ids.size
     assert st["n_pairs"] == int(ref["card"].sum())
@@ -107,7 +109,9 @@ def test_duplicates_and_empty_sets():
 
 
 @pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 255, 257])
-def test_tile_edges(n):
+@pytest.mark.parametrize("path", ["popcount", "mfma"])
+def test_tile_edges(n, path):
+    flags = cabi.JAS_FORCE_POPCOUNT if path == "popcount" else cabi.JAS_FORCE_MFMA
     rng = np.random.default_rng(n)
     core = rng.choice(1 << 20, 3000, replace=False).astype(np.uint64)
     sets = [np.concatenate([rng.choice(core, int(rng.integers(0, 2000)), replace=False),
@@ -117,9 +121,9 @@ def test_tile_edges(n):
     off[1:] = np.cumsum([s.size for s in sets])
     ids = np.concatenate(sets) if n else np.zeros(0, np.uint64)
     ref = oracle.all_pairs(ids, off)
-    res, _ = gpu_all_pairs(ids, off, 20, 12, 0)
+    res, _ = gpu_all_pairs(ids, off, 20, 12, 0, flags=flags)
     assert_matches(res, ref)
-    res, _ = gpu_all_pairs(ids, off, 20, 0, 0, upper=True)
+    res, _ = gpu_all_pairs(ids, off, 20, 0, 0, upper=True, flags=flags)
     assert_matches(res, ref, upper=True)
 
 
@@ -190,12 +194,31 @@ def test_host_pointers_match_device_path(tiny):
     assert_matches({"B": B, "card": card, "den": den, "J": J}, ref)
 
 
+@pytest.mark.parametrize("name", ["precision", "paperlike"])
+def test_mfma_equals_popcount_on_dense_tiles(name):
+    spec = synth.scaled(synth.workload(name), n=384, size_scale=0.01, pool_scale=0.01)
+    ids, off = synth.generate(spec)
+    db, st = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, batch_bits=synth.BATCH_BITS[name])
+    a = jas.gram(db, flags=cabi.JAS_FORCE_POPCOUNT)
+    b = jas.gram(db, flags=cabi.JAS_FORCE_MFMA)
+    c = jas.gram(db)
+    torch.cuda.synchronize()
+    assert st["n_word_rows"] > 0
+    assert torch.equal(a["B"], b["B"]) and torch.equal(a["B"], c["B"])
+    assert torch.equal(a["J"], b["J"])
+    db.close()
+    ref = oracle.all_pairs(ids, off)
+    assert_matches({k: v.cpu().numpy() for k, v in b.items()}, ref)
+
+
 def test_repeat_runs_are_identical():
     spec = synth.scaled(synth.workload("precision"), n=300, size_scale=0.01, pool_scale=0.01)
     ids, off = synth.generate(spec)
     db, _ = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, dense_min_degree=4)
     a = jas.gram(db)["B"].cpu().numpy()
     b = jas.gram(db)["B"].cpu().numpy()
+    c = jas.gram(db, flags=cabi.JAS_FORCE_POPCOUNT)["B"].cpu().numpy()
+    assert np.array_equal(a, c)
     db.close()
     assert np.array_equal(a, b)
 
