@@ -61,7 +61,8 @@ typedef struct {
     uint32_t batch_bits;       /* log2 of the row-batch height m~ (Eq. (3)); 0 or >= U: one batch */
     uint32_t dense_min_degree; /* rows shared by >= this many sets are bit-packed (Sec. III-B);
                                   rows shared by 2..this-1 sets are kept as plain row lists;
-                                  0 = library default; 2 = pack every shared row */
+                                  0 = chosen by the library from the row degree histogram
+                                  (cost model of the two Gram paths); 2 = pack every shared row */
     uint32_t flags;            /* JAS_HOST_PTRS, JAS_KEEP_IDS */
     uint64_t hbm_budget_bytes; /* cap on device memory this call may hold at once; 0 = none */
 } jas_encode_opts;
@@ -79,6 +80,7 @@ typedef struct {
     uint64_t word_pairs_F;  /* sum over word rows of z(z+1)/2, z = nonzero words in the row */
     uint64_t list_pairs;    /* sum over list rows of d(d-1)/2 (pair increments of the list path) */
     uint64_t device_bytes;  /* device memory the db holds */
+    uint64_t dense_min_degree; /* the threshold used (chosen by the library when opts asked for 0) */
 } jas_encode_stats;
 
 /*

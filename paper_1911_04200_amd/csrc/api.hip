@@ -143,7 +143,7 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
         db->U = U;
         db->sbits = sbits;
         db->batch_bits = (opts->batch_bits == 0 || opts->batch_bits >= U) ? U : opts->batch_bits;
-        db->dmin = opts->dense_min_degree == 0 ? 2u : std::max<uint32_t>(2u, opts->dense_min_degree);
+        db->dmin = opts->dense_min_degree == 0 ? 0u : std::max<uint32_t>(2u, opts->dense_min_degree);
         db->flags = opts->flags;
         // one budget for the call: temporaries (tb) and the db's own buffers
         Budget tb;

@@ -219,6 +219,24 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Row degree histogram (degrees are <= n): input of the degree threshold choice.
+__global__ __launch_bounds__(kNT) void k_deg_hist(const uint64_t *row_ptr, uint64_t R, uint32_t nb,
+                                                   int lds, unsigned long long *hist) {
+    extern __shared__ uint32_t h[];
+    if (lds)
+        for (uint32_t i = threadIdx.x; i < nb; i += kNT) h[i] = 0;
+    __syncthreads();
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = min(row_ptr[r + 1] - row_ptr[r], (uint64_t)(nb - 1));
+        if (lds) atomicAdd(&h[d], 1u);
+        else atomicAdd(&hist[d], 1ull);
+    }
+    __syncthreads();
+    if (lds)
+        for (uint32_t i = threadIdx.x; i < nb; i += kNT)
+            if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
 // Rows: degree split.
 __global__ __launch_bounds__(kNT) void k_row_flags(const uint64_t *row_ptr, uint64_t R, uint32_t dmin,
                                                     uint32_t *fDense, uint32_t *fList, unsigned long long *st) {
@@ -495,6 +513,35 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
     // --- split rows by degree ------------------------------------------------
     uint64_t QD = 0, QL = 0;
     DevBuf<uint64_t> Drow, Lrow;
+    if (R > 0 && db->dmin == 0) {
+        // choose the degree threshold from the row degree histogram
+        JAS_HOST_TIMED("choose_dmin");
+        const uint32_t nb = (uint32_t)n + 2;
+        DevBuf<unsigned long long> hist;
+        hist.alloc(nb, s, tb, true, "degree histogram");
+        k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)hist.p, nb, 0);
+        const int lds = nb <= 16384;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(div_up(R, 256), 2048);
+        {
+            JAS_TIMED("deg_hist", s);
+            k_deg_hist<<<blocks, kNT, lds ? nb * sizeof(uint32_t) : 0, s>>>(row_ptr.p, R, nb, lds, hist.p);
+        }
+        check_launch("degree histogram");
+        std::vector<uint64_t> hh(nb);
+        JAS_HIP(hipMemcpyAsync(hh.data(), hist.p, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = 0;
+        }
+        uint64_t cap = free_b ? (uint64_t)free_b / 2 : ~0ull;
+        if (tb->limit) cap = std::min<uint64_t>(cap, tb->limit / 2);
+        const uint32_t bb = db->batch_bits, U = db->U;
+        const uint64_t nbatches = (U - bb >= 63) ? ~0ull : (uint64_t(1) << (U - bb));
+        db->dmin = choose_dense_min_degree(hh, (uint32_t)n, nbatches, cap);
+    }
+    db->stats.dense_min_degree = db->dmin;
     if (R > 0) {
         DevBuf<uint32_t> fDense, fList;
         DevBuf<uint64_t> pDense, pList, tmp;

@@ -175,6 +175,11 @@ void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_
 // Encoding after the sort (see encode.hip).
 void encode_sorted(jas_db *db, const uint64_t *keys, uint64_t N, hipStream_t s, Budget *tmpb);
 
+// Degree threshold: rows of degree >= the result are bit-packed, 2..result-1
+// kept as row lists; minimises the modelled Gram time (see tune.hip).
+uint32_t choose_dense_min_degree(const std::vector<uint64_t> &deg_hist, uint32_t n, uint64_t nbatches,
+                                 uint64_t max_packed_bytes);
+
 // Gram and finalize (see gram.hip).
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J);
 

@@ -47,7 +47,7 @@ class jas_encode_opts(ctypes.Structure):
 class jas_encode_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in
                 ["n_ids", "n_pairs", "n_rows", "n_shared_rows", "n_packed_rows", "n_list_rows", "n_batches",
-                 "n_word_rows", "nnz_words", "word_pairs_F", "list_pairs", "device_bytes"]]
+                 "n_word_rows", "nnz_words", "word_pairs_F", "list_pairs", "device_bytes", "dense_min_degree"]]
 
     def to_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

@@ -77,7 +77,7 @@ SCALED = {
 
 
 @pytest.mark.parametrize("name", sorted(SCALED))
-@pytest.mark.parametrize("dmin", [0, 6])
+@pytest.mark.parametrize("dmin", [0, 2, 6])
 def test_scaled_workloads(name, dmin):
     spec = synth.scaled(synth.workload(name), **SCALED[name])
     ids, off = synth.generate(spec)
@@ -85,10 +85,12 @@ def test_scaled_workloads(name, dmin):
     res, st = gpu_all_pairs(ids, off, spec.universe_bits, synth.BATCH_BITS[name], dmin, upper=(dmin == 6))
     assert_matches(res, ref, upper=(dmin == 6))
     assert st["n_packed_rows"] + st["n_list_rows"] == st["n_shared_rows"] > 0
-    if dmin == 0:
+    if dmin == 2:
         assert st["n_packed_rows"] == st["n_shared_rows"]
-    else:
+    elif dmin == 6:
         assert st["n_list_rows"] > 0
+    else:
+        assert st["dense_min_degree"] >= 2
 
 
 def test_duplicates_and_empty_sets():
