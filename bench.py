@@ -58,6 +58,10 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
     if kernel == "pack":
         ldw = math.ceil(n / 128) * 128
         return "hbm", 8.0 * stats["n_word_rows"] * ldw / 1e9, "GB/s", "8 B per packed word written"
+    if kernel == "list_pairs":
+        lp, rows = stats["list_pairs"], stats["n_list_rows"]
+        return ("hbm", (8.0 * lp + 4.0 * (2 * lp / max(rows, 1) + 1) * rows + 8.0 * rows) / 1e9, "GB/s",
+                "8 B per pair increment (4-byte counter read + write) + 4 B per list entry + 8 B per row pointer")
     if kernel == "gram_mfma":
         nt = math.ceil(n / 128)
         macs = stats["n_word_rows"] * 64 * (nt * (nt + 1) // 2) * 128 * 128
@@ -96,6 +100,58 @@ def cpu_baseline(spec, k: int, seed: int = 5):
                        f"n(n+1)/2 / (n * per-set + n(n+1)/2 * per-pair time) for the full n={n}")}
 
 
+def run_serving(n_requests: int, n_saturation: int, seed: int = 1):
+    """Resident serving database (n=8192, U=36, 3.2e9 IDs); Poisson request stream at
+    0.7 x the saturation rate measured by a closed pre-run; continuous batching over 4 slots
+    within an 8 GiB HBM budget."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1911_04200_amd import jas as cabi
+    from paper_1911_04200_amd import serve
+
+    spec = synth.workload("serving_db")
+    off = synth.offsets(spec)
+    N = int(off[-1])
+    log(f"[serving] database n={spec.n} U={spec.universe_bits} N={N} ids")
+    host = torch.empty(N, dtype=torch.int64, pin_memory=True)
+    synth.generate(spec, out=host.numpy().view(np.uint64))
+    ids_d = host.cuda()
+    off_d = torch.from_numpy(off.view(np.int64)).cuda()
+    del host
+    torch.cuda.synchronize()
+    opts = cabi.jas_encode_opts(spec.universe_bits, synth.BATCH_BITS["serving_db"], 0, cabi.JAS_KEEP_IDS, 0)
+    t = time.perf_counter()
+    db, st = cabi.jas_encode(ids_d, off_d, spec.n, opts, None)
+    enc_s = time.perf_counter() - t
+    del ids_d
+    torch.cuda.synchronize()
+    log(f"[serving] encoded in {enc_s:.2f} s; generating requests")
+    warm = serve.make_requests(spec, 8, seed=seed * 1000 + 1, first_id=100000)
+    sat = serve.make_requests(spec, n_saturation, seed=seed * 1000 + 2, first_id=200000)
+    reqs = serve.make_requests(spec, n_requests, seed=seed * 1000 + 3, first_id=300000)
+    server = serve.Server(db, slots=4, budget_bytes=8 << 30, max_batch_sets=64)
+    server.run(warm)
+    t = time.perf_counter()
+    server.run(sat)
+    sat_rate = len(sat) / (time.perf_counter() - t)
+    rate = 0.7 * sat_rate
+    arrivals = serve.poisson_arrivals(len(reqs), rate, seed)
+    log(f"[serving] saturation {sat_rate:.1f} req/s; Poisson stream at {rate:.1f} req/s")
+    t = time.perf_counter()
+    server.run(reqs, arrivals)
+    wall = time.perf_counter() - t
+    out = serve.summarize(reqs, spec.n, wall)
+    out.update({"workload": f"serving_n{spec.n}_u{spec.universe_bits}", "db_ids": N,
+                "db_encode_s": enc_s, "db_device_bytes": st["device_bytes"], "saturation_requests_per_s": sat_rate,
+                "offered_requests_per_s": rate, "slots": 4, "hbm_budget_bytes": 8 << 30, "max_batch_sets": 64,
+                "latency": "completion - Poisson arrival (host arrays in and out, queueing included)"})
+    db.close()
+    cabi.jas_trim()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +163,9 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "popcount", "mfma"], help="Gram path for packed tiles")
     ap.add_argument("--cpu-sample", type=int, default=64, help="sets in the oracle's timed sample (0: skip)")
     ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing in the timed region")
+    ap.add_argument("--serving-requests", type=int, default=160,
+                    help="requests in the timed Poisson serving run (0: no serving run)")
+    ap.add_argument("--serving-saturation", type=int, default=48, help="requests in the closed saturation run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -141,6 +200,8 @@ def main():
     log("[bench] inputs resident in HBM")
 
     stream = torch.cuda.current_stream()
+    if args.workload == "batching":
+        args.upper = True  # the batching form returns the upper triangle only
     length = n * (n + 1) // 2 if args.upper else n * n
     B = torch.empty(length, dtype=torch.int32, device=dev)
     card = torch.empty(n, dtype=torch.int64, device=dev)
@@ -212,6 +273,15 @@ def main():
              else None,
              "encode_stats": st, "kernels": kernels, "host_phases": host_phases}
 
+    del ids_d, B, den, J
+    cabi.jas_trim()
+    serving = None
+    if args.serving_requests > 0:
+        try:
+            serving = run_serving(args.serving_requests, args.serving_saturation)
+        except Exception as e:  # reported, not fatal to the all-pairs line
+            serving = {"error": repr(e)}
+
     cpu = None
     if args.cpu_sample > 0:
         log("[bench] timing the oracle on a sample")
@@ -225,7 +295,7 @@ def main():
                       "universe_bits": spec.universe_bits, "batch_rows": f"2^{bb}", "ids": N,
                       "pairs_per_step": pairs, "layout": "upper" if args.upper else "full",
                       "dense_min_degree": args.dmin},
-           "roofline": roof, "cpu_baseline": cpu, "detail": extra}
+           "roofline": roof, "cpu_baseline": cpu, "serving": serving, "detail": extra}
     print(json.dumps(out), flush=True)
 
 

@@ -149,7 +149,7 @@ class Db:
 
 
 def _h(db):
-    return db.handle if isinstance(db, Db) else db
+    return getattr(db, "handle", db)
 
 
 def jas_encode(ids, offsets, n: int, opts: jas_encode_opts, stream=None):
