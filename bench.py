@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=160,
                     help="requests in the timed Poisson serving run (0: no serving run)")
     ap.add_argument("--serving-saturation", type=int, default=48, help="requests in the closed saturation run")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied device-to-device before the steps: a plain copy of known size that scales "
+                         "the HBM byte counters of a profiler run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -198,6 +201,14 @@ def main():
     del host, ids_np
     torch.cuda.synchronize()
     log("[bench] inputs resident in HBM")
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration} MiB done")
+        del src, dst
 
     stream = torch.cuda.current_stream()
     if args.workload == "batching":
