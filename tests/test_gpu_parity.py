@@ -279,3 +279,36 @@ def test_query_requires_index_and_rejects_bad_ids():
         jas.query(db, dev(np.array([1 << 24], np.uint64)), dev(np.array([0, 1], np.uint64)))
     assert e.value.status == cabi.JAS_EINVAL
     db.close()
+
+
+def test_gram_captured_in_a_graph_replays_exactly():
+    spec = synth.scaled(synth.workload("paperlike"), n=200, size_scale=0.004, pool_scale=0.004)
+    ids, off = synth.generate(spec)
+    db, st = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, batch_bits=26, dense_min_degree=4)
+    assert st["n_list_rows"] > 0 and st["n_packed_rows"] > 0
+    eager = jas.gram(db)
+    torch.cuda.synchronize()
+    n = spec.n
+    B = torch.full((n, n), -7, dtype=torch.int32, device="cuda")
+    card = torch.empty(n, dtype=torch.int64, device="cuda")
+    den = torch.empty((n, n), dtype=torch.int64, device="cuda")
+    J = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        cabi.jas_gram(db, 0, side, B, card, den, J)  # warm the path outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        cabi.jas_gram(db, 0, torch.cuda.current_stream(), B, card, den, J)
+    for rep in range(3):
+        B.fill_(-1)
+        J.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(B, eager["B"]), f"replay {rep}"
+        assert torch.equal(J, eager["J"]) and torch.equal(den, eager["den"]) and torch.equal(card, eager["card"])
+        _ = (eager["B"].float() * 2).sum().item()  # eager work between replays
+    db.close()
