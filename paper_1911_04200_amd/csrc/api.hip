@@ -176,16 +176,17 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
                 JAS_TIMED("zero_u32", s);
                 k_zero_u32<<<1, 1, 0, s>>>(err.p);
             }
-            build_keys(dids, doff, n, N, sbits, U, keys.p, err.p, s);
+            RadixWork rw;
+            radix_prepare(rw, N, s, &tb);
+            build_keys(dids, doff, n, N, sbits, U, keys.p, err.p, rw.counts.p, s);
             uint32_t herr = 0;
             JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
             if (herr) fail(JAS_EINVAL, "jas_encode: an ID is >= 2^universe_bits");
             ids_d.release();
             off_d.release();
-            RadixWork rw;
             JAS_HOST_TIMED("sort_enqueue");
-            radix_sort_u64(keys, alt, N, sbits, sbits + U, rw, s, &tb);
+            radix_sort_u64(keys, alt, N, sbits, sbits + U, rw, s, &tb, /*first_counts_ready=*/true);
         }
         try {
             encode_sorted(db.get(), keys.p, N, s, &tb);

@@ -42,26 +42,42 @@ constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass
 enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
 
 // ---------------------------------------------------------------------------
+// Keys of one radix chunk (kChunk entries) per block; also the chunk's
+// histogram of the first radix digit (bits sbits .. sbits+7 of the key), so
+// the first sort pass needs no histogram pass of its own.
 __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__ ids,
                                                      const uint64_t *__restrict__ off, int32_t n, uint64_t N,
-                                                     uint32_t sbits, uint64_t hi_mask, uint64_t *__restrict__ keys,
-                                                     uint32_t *err) {
+                                                     uint32_t sbits, uint64_t hi_mask, uint32_t dmask,
+                                                     uint64_t *__restrict__ keys, uint32_t *err,
+                                                     uint32_t *__restrict__ counts, uint32_t nchunks) {
     __shared__ int32_t s_lo, s_hi;
-    const uint64_t b0 = (uint64_t)blockIdx.x * kTile;
-    const uint64_t b1 = min(N, b0 + kTile);
-    if (threadIdx.x == 0) {
+    __shared__ uint32_t h[kWaves][256];
+    const uint32_t tid = threadIdx.x, w = tid / kWave;
+    const uint64_t b0 = (uint64_t)blockIdx.x * kChunk;
+    const uint64_t b1 = min(N, b0 + kChunk);
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) h[k][tid] = 0;
+    if (tid == 0) {
         s_lo = find_sample(off, 0, n - 1, b0);
         s_hi = find_sample(off, s_lo, n - 1, b1 - 1);
     }
     __syncthreads();
     uint32_t bad = 0;
-    for (uint64_t t = b0 + threadIdx.x; t < b1; t += kNT) {
-        const int32_t s = find_sample(off, s_lo, s_hi, t);
+    int32_t lo = s_lo;
+    for (uint64_t t = b0 + tid; t < b1; t += kNT) {
+        lo = find_sample(off, lo, s_hi, t);  // t only grows, so the search range only shrinks
         const uint64_t id = ids[t];
         bad |= (id & hi_mask) != 0;
-        keys[t] = (id << sbits) | (uint64_t)s;
+        const uint64_t key = (id << sbits) | (uint64_t)lo;
+        keys[t] = key;
+        atomicAdd(&h[w][(uint32_t)(key >> sbits) & dmask], 1u);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1u);
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) c += h[k][tid];
+    counts[(uint64_t)tid * nchunks + blockIdx.x] = c;
 }
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t len, uint64_t v) {
@@ -70,23 +86,52 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t len, uint64_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// Classification of sorted element t (key = K[t]).
+// Classification of the sorted keys.  A block owns a chunk of kChunk keys and
+// walks it in tiles of kTile; each tile is staged in LDS with one key of halo
+// on each side, so the neighbours that decide an element come from LDS.
+//   first    K[t] != K[t-1]: the first copy of a distinct (ID, sample) pair;
+//   left     the previous distinct pair has the same ID (not the row's first);
+//   right    the next distinct pair (after any copies of K[t]) has the same ID;
+//   shared   first && (left || right): the row has >= 2 distinct pairs;
+//   rowstart shared && !left;  newid = first && !left (one per nonzero row).
 struct Cls {
     bool first, shared, rowstart, newid;
 };
 
-__device__ __forceinline__ Cls classify(const uint64_t *__restrict__ K, uint64_t N, uint64_t t, uint64_t key,
-                                        uint32_t sbits) {
+// L[0..cnt+1] = K[t0-1 .. t0+cnt] (out-of-range ends are complements of their
+// neighbour so they compare unequal).  Element t0+i is L[i+1].
+__device__ __forceinline__ void stage_tile(const uint64_t *__restrict__ K, uint64_t N, uint64_t t0, uint32_t cnt,
+                                           uint64_t *L) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += kNT) L[i + 1] = K[t0 + i];
+    if (threadIdx.x == 0) L[0] = t0 > 0 ? K[t0 - 1] : ~K[t0];
+    if (threadIdx.x == 1) L[cnt + 1] = (t0 + cnt < N) ? K[t0 + cnt] : ~K[t0 + cnt - 1];
+}
+
+__device__ __forceinline__ Cls classify_lds(const uint64_t *__restrict__ K, uint64_t N, uint64_t t0, uint32_t cnt,
+                                            const uint64_t *L, uint32_t i, uint32_t sbits) {
     Cls c;
+    const uint64_t key = L[i + 1], prev = L[i];
     const uint64_t id = key >> sbits;
-    const uint64_t prev = t > 0 ? K[t - 1] : ~key;
+    const uint64_t t = t0 + i;
     c.first = (t == 0) || prev != key;
     const bool left = c.first && t > 0 && (prev >> sbits) == id;
     bool right = false;
     if (c.first) {
-        uint64_t u = t + 1;
-        while (u < N && K[u] == key) ++u;  // skip repeats of this (ID, sample)
-        right = u < N && (K[u] >> sbits) == id;
+        // next distinct key: in the tile (or its halo), else (long runs of copies) in global memory
+        uint32_t j = i + 2;
+        while (j <= cnt + 1 && L[j] == key) ++j;
+        uint64_t nxt;
+        bool have = true;
+        if (j <= cnt + 1) {
+            nxt = L[j];
+            have = t0 + (j - 1) < N;
+        } else {
+            uint64_t u = t0 + cnt + 1;
+            while (u < N && K[u] == key) ++u;
+            have = u < N;
+            nxt = have ? K[u] : 0;
+        }
+        right = have && (nxt >> sbits) == id;
     }
     c.shared = c.first && (left || right);
     c.rowstart = c.shared && !left;
@@ -99,26 +144,31 @@ __global__ __launch_bounds__(kNT) void k_cls_count(const uint64_t *__restrict__ 
                                                     uint32_t *cS, uint32_t *cR, unsigned long long *card,
                                                     unsigned long long *st) {
     extern __shared__ uint32_t hist[];
+    __shared__ uint64_t L[kTile + 2];
     __shared__ uint64_t sh[kWaves];
     const uint32_t tid = threadIdx.x;
     if (lds_hist)
         for (int32_t i = tid; i < n; i += kNT) hist[i] = 0;
-    __syncthreads();
     const uint64_t c0 = (uint64_t)blockIdx.x * kChunk;
     const uint64_t c1 = min(N, c0 + kChunk);
     uint32_t nD = 0, nS = 0, nR = 0, nI = 0;
-    for (uint64_t t = c0 + tid; t < c1; t += kNT) {
-        const uint64_t key = K[t];
-        const Cls c = classify(K, N, t, key, sbits);
-        if (c.first) {
-            ++nD;
-            const uint32_t s = (uint32_t)(key & smask);
-            if (lds_hist) atomicAdd(&hist[s], 1u);
-            else atomicAdd(&card[s], 1ull);
+    for (uint64_t t0 = c0; t0 < c1; t0 += kTile) {
+        const uint32_t cnt = (uint32_t)min((uint64_t)kTile, c1 - t0);
+        __syncthreads();
+        stage_tile(K, N, t0, cnt, L);
+        __syncthreads();
+        for (uint32_t i = tid; i < cnt; i += kNT) {
+            const Cls c = classify_lds(K, N, t0, cnt, L, i, sbits);
+            if (c.first) {
+                ++nD;
+                const uint32_t s = (uint32_t)(L[i + 1] & smask);
+                if (lds_hist) atomicAdd(&hist[s], 1u);
+                else atomicAdd(&card[s], 1ull);
+            }
+            nS += c.shared;
+            nR += c.rowstart;
+            nI += c.newid;
         }
-        nS += c.shared;
-        nR += c.rowstart;
-        nI += c.newid;
     }
     uint64_t tD, tS, tR, tI;
     block_excl_scan<kNT>(nD, sh, &tD);
@@ -137,11 +187,13 @@ __global__ __launch_bounds__(kNT) void k_cls_count(const uint64_t *__restrict__ 
             if (hist[i]) atomicAdd(&card[i], (unsigned long long)hist[i]);
 }
 
-// Ordered compaction of the classified elements of one chunk.
+// Ordered compaction of the classified elements of one chunk: wave w of a
+// tile owns its elements [w*1024, (w+1)*1024), 64 per round, in order.
 __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ K, uint64_t N, uint32_t sbits,
                                                     uint64_t smask, const uint64_t *oD, const uint64_t *oS,
                                                     const uint64_t *oR, uint64_t *Dout, uint32_t *Sout,
                                                     uint64_t *row_id, uint64_t *row_ptr) {
+    __shared__ uint64_t L[kTile + 2];
     __shared__ uint32_t wc[3][kWaves];
     __shared__ uint64_t run[3];
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
@@ -154,19 +206,19 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
         run[2] = oR[blockIdx.x];
     }
     for (uint64_t t0 = c0; t0 < c1; t0 += kTile) {
+        const uint32_t cnt = (uint32_t)min((uint64_t)kTile, c1 - t0);
         __syncthreads();
-        const uint64_t wb = t0 + (uint64_t)w * (kTile / kWaves);
-        uint64_t key[kRounds];
+        stage_tile(K, N, t0, cnt, L);
+        __syncthreads();
+        const uint32_t wb = w * (kTile / kWaves);
         uint32_t fD = 0, fS = 0, fR = 0;
         uint32_t nD = 0, nS = 0, nR = 0;
-#pragma unroll
+#pragma unroll 2
         for (int j = 0; j < kRounds; ++j) {
-            const uint64_t t = wb + (uint64_t)j * kWave + lane;
+            const uint32_t i = wb + j * kWave + lane;
             bool d = false, s = false, r = false;
-            key[j] = 0;
-            if (t < c1) {
-                key[j] = K[t];
-                const Cls c = classify(K, N, t, key[j], sbits);
+            if (i < cnt) {
+                const Cls c = classify_lds(K, N, t0, cnt, L, i, sbits);
                 d = c.first;
                 s = c.shared;
                 r = c.rowstart;
@@ -197,11 +249,14 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
             const uint64_t posD = pD + __popcll(bd & lt);
             const uint64_t posS = pS + __popcll(bs & lt);
             const uint64_t posR = pR + __popcll(br & lt);
-            if (d && Dout) Dout[posD] = key[j];
-            if (s) Sout[posS] = (uint32_t)(key[j] & smask);
-            if (r) {
-                row_id[posR] = key[j] >> sbits;
-                row_ptr[posR] = posS;
+            if (d | s) {
+                const uint64_t key = L[wb + j * kWave + lane + 1];
+                if (d && Dout) Dout[posD] = key;
+                if (s) Sout[posS] = (uint32_t)(key & smask);
+                if (r) {
+                    row_id[posR] = key >> sbits;
+                    row_ptr[posR] = posS;
+                }
             }
             pD += __popcll(bd);
             pS += __popcll(bs);
@@ -218,7 +273,6 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
     }
 }
 
-// ---------------------------------------------------------------------------
 // Row degree histogram (degrees are <= n): input of the degree threshold choice.
 __global__ __launch_bounds__(kNT) void k_deg_hist(const uint64_t *row_ptr, uint64_t R, uint32_t nb,
                                                    int lds, unsigned long long *hist) {
@@ -408,14 +462,16 @@ uint64_t to_host_u64(const uint64_t *dptr, hipStream_t s) {
 }  // namespace
 
 void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
-                uint64_t *keys, uint32_t *err, hipStream_t s) {
+                uint64_t *keys, uint32_t *err, uint32_t *counts, hipStream_t s) {
     if (N == 0) return;
     const uint64_t hi_mask = U >= 64 ? 0 : ~((uint64_t(1) << U) - 1);
-    const uint64_t blocks = div_up(N, kTile);
+    const uint64_t blocks = div_up(N, kChunk);
     if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many IDs");
+    const uint32_t dmask = (1u << std::min<uint32_t>(8, U)) - 1u;
     {
         JAS_TIMED("build_keys", s);
-        k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, keys, err);
+        k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, dmask, keys, err, counts,
+                                                      (uint32_t)blocks);
     }
     check_launch("build keys");
 }

@@ -124,32 +124,49 @@ __global__ __launch_bounds__(kNT) void k_gram_popc(const uint64_t *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // int8 MFMA form of the same product.  Each bit of a packed word becomes a
-// 0/1 byte in registers (never in memory) and V_MFMA_I32_32X32X32_I8 sums
-// the byte products in int32: sum_k a_ki a_kj over the 32 bits of a half
-// word, exact (every partial sum is a count <= 2^31).  The K order inside
-// the instruction does not matter: lane group g (lanes 32g..32g+31) feeds
-// bits 16g..16g+15 of the half word for both operands, so every bit pairs
-// with itself.
+// 0/1 byte in registers (never in memory; through a 256-entry LDS table of
+// byte patterns) and V_MFMA_I32_32X32X32_I8 sums the byte products in int32:
+// sum_k a_ki a_kj over the 32 bits of a half word, exact (every partial sum
+// is a count <= 2^31).  The K order inside the instruction does not matter:
+// lane group g (lanes 32g..32g+31) feeds bits 16g..16g+15 of the half word
+// for both operands, so every bit pairs with itself.
 // Block = 2 waves over a 128 x 128 tile; wave c owns columns 64c..64c+63,
 // i.e. 4 x 2 MFMA tiles of 32 x 32 (128 int32 accumulators per lane).
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ v4i bits16_to_bytes(uint32_t x) {
-    // byte b of the result = bit b of x (0 or 1)
+constexpr int kMfmaNT = 128;
+
+// 8 bits -> 8 bytes (byte k = bit k), 256 entries: an operand of 16 bits is
+// two table reads instead of a dozen VALU operations.
+__device__ __forceinline__ void fill_byte_lut(unsigned long long *lut) {
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+        const unsigned long long lo = ((i & 0xFu) * 0x00204081u) & 0x01010101u;
+        const unsigned long long hi = (((i >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
+        lut[i] = lo | (hi << 32);
+    }
+}
+
+__device__ __forceinline__ v4i bits16_lut(const unsigned long long *lut, uint32_t x) {
+    const unsigned long long lo = lut[__builtin_amdgcn_ubfe(x, 0, 8)];
+    const unsigned long long hi = lut[__builtin_amdgcn_ubfe(x, 8, 8)];
     v4i r;
-    r[0] = (int)(((x & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[1] = (int)((((x >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[2] = (int)((((x >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
-    r[3] = (int)((((x >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[0] = (int)(uint32_t)lo;
+    r[1] = (int)(uint32_t)(lo >> 32);
+    r[2] = (int)(uint32_t)hi;
+    r[3] = (int)(uint32_t)(hi >> 32);
     return r;
 }
 
-constexpr int kMfmaNT = 128;
-
-__global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gram_mfma(const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H,
-                                                        uint64_t kper, uint32_t nt, uint32_t n,
-                                                        int32_t *__restrict__ B, int upper) {
+// The next word row is loaded while the current one is multiplied.  WPE =
+// waves per SIMD the register budget is sized for (2: 256 VGPRs, 3: 168).
+template <int WPE>
+__global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gram_mfma(
+    const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
+    int32_t *__restrict__ B, int upper) {
+    __shared__ unsigned long long lut[256];
+    // blockIdx.x enumerates the tile pairs I <= J row by row, blockIdx.y the K range
+    const uint64_t split = blockIdx.y;
     uint32_t p = blockIdx.x, I = 0, rowlen = nt;
     while (p >= rowlen) {
         p -= rowlen;
@@ -157,13 +174,14 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
         --rowlen;
     }
     const uint32_t Jt = I + p;
-    const uint64_t k0 = (uint64_t)blockIdx.y * kper;
+    const uint64_t k0 = split * kper;
     const uint64_t k1 = min(H, k0 + kper);
     if (k0 >= k1) return;
+    fill_byte_lut(lut);
+    __syncthreads();
     const uint32_t lane = threadIdx.x & 63, wc = threadIdx.x >> 6;
     const uint32_t lm = lane & 31, lg = lane >> 5;
     const uint32_t I0 = I * kT, J0 = Jt * kT + 64 * wc;
-    // in a diagonal tile the wave's 128 x 64 block has rows >= its first column only partly
     v16i acc[4][2];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
@@ -191,9 +209,9 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
             const uint32_t sh = 32 * h + 16 * lg;
             v4i va[4], vb[2];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) va[x] = bits16_to_bytes((uint32_t)(a[x] >> sh) & 0xFFFFu);
+            for (int x = 0; x < 4; ++x) va[x] = bits16_lut(lut, (uint32_t)(a[x] >> sh));
 #pragma unroll
-            for (int y = 0; y < 2; ++y) vb[y] = bits16_to_bytes((uint32_t)(b[y] >> sh) & 0xFFFFu);
+            for (int y = 0; y < 2; ++y) vb[y] = bits16_lut(lut, (uint32_t)(b[y] >> sh));
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -291,7 +309,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
             k_gram_popc<<<grid, kNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
         } else {
             JAS_TIMED("gram_mfma", s);
-            k_gram_mfma<<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            k_gram_mfma<2><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
         }
         check_launch("gram");
     }

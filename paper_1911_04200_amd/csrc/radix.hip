@@ -9,6 +9,8 @@
 //      keys by digit (stable: waves own consecutive quarters of the tile,
 //      rounds go in order), the tile is reordered in LDS, and each digit run
 //      is written out contiguously (coalesced).
+#include <algorithm>
+
 #include "device_util.hpp"
 #include "jas_internal.hpp"
 
@@ -147,20 +149,26 @@ uint64_t radix_work_bytes(uint64_t N) {
     return len * 4 + (len + 1) * 8 + scan_tmp_elems(len) * 8;
 }
 
-void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
-                    RadixWork &w, hipStream_t s, Budget *b) {
-    if (N <= 1 || hi_bit <= lo_bit) return;
-    const uint64_t nchunks = div_up(N, kChunk);
+uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b) {
+    const uint64_t nchunks = div_up(std::max<uint64_t>(N, 1), kChunk);
     if (nchunks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "radix sort: too many keys");
     const uint64_t len = (uint64_t)kRadix * nchunks;
     if (w.counts.n < len) w.counts.alloc(len, s, b, true, "radix counts");
     if (w.offs.n < len + 1) w.offs.alloc(len + 1, s, b, true, "radix offsets");
     const size_t tl = scan_tmp_elems(len);
     if (w.tmp.n < tl) w.tmp.alloc(tl, s, b, true, "radix scan scratch");
+    return nchunks;
+}
+
+void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
+                    RadixWork &w, hipStream_t s, Budget *b, bool first_counts_ready) {
+    if (N <= 1 || hi_bit <= lo_bit) return;
+    const uint64_t nchunks = radix_prepare(w, N, s, b);
+    const uint64_t len = (uint64_t)kRadix * nchunks;
     for (uint32_t bit = lo_bit; bit < hi_bit; bit += 8) {
         const uint32_t nbits = min(8u, hi_bit - bit);
         const uint32_t mask = (1u << nbits) - 1u;
-        {
+        if (!(first_counts_ready && bit == lo_bit)) {
             JAS_TIMED("radix_hist", s);
             k_radix_hist<<<(uint32_t)nchunks, kNT, 0, s>>>(keys.p, N, bit, mask, w.counts.p, (uint32_t)nchunks);
         }
