@@ -158,9 +158,10 @@ __device__ __forceinline__ v4i bits16_lut(const unsigned long long *lut, uint32_
     return r;
 }
 
-// The next word row is loaded while the current one is multiplied.  WPE =
-// waves per SIMD the register budget is sized for (2: 256 VGPRs, 3: 168).
-template <int WPE>
+// STEP word rows per loop iteration; the next STEP rows are loaded while the
+// current ones are multiplied.  WPE = waves per SIMD the register budget is
+// sized for (2: 256 VGPRs).
+template <int WPE, int STEP>
 __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gram_mfma(
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
@@ -192,36 +193,51 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WP
 
     const uint64_t *pa = W + I0 + lm;
     const uint64_t *pb = W + J0 + lm;
-    uint64_t a[4], b[2];
+    // STEP word rows per iteration; the next STEP rows are loaded while these are multiplied
+    uint64_t a[STEP][4], b[STEP][2];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) a[x] = pa[k0 * ldw + 32 * x];
+    for (int u = 0; u < STEP; ++u) {
+        const uint64_t ku = min(k0 + u, k1 - 1);
 #pragma unroll
-    for (int y = 0; y < 2; ++y) b[y] = pb[k0 * ldw + 32 * y];
-    for (uint64_t k = k0; k < k1; ++k) {
-        uint64_t na[4], nb[2];
-        const uint64_t kn = (k + 1 < k1) ? k + 1 : k;
+        for (int x = 0; x < 4; ++x) a[u][x] = pa[ku * ldw + 32 * x];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) na[x] = pa[kn * ldw + 32 * x];
+        for (int y = 0; y < 2; ++y) b[u][y] = pb[ku * ldw + 32 * y];
+    }
+    for (uint64_t k = k0; k < k1; k += STEP) {
+        uint64_t na[STEP][4], nb[STEP][2];
 #pragma unroll
-        for (int y = 0; y < 2; ++y) nb[y] = pb[kn * ldw + 32 * y];
+        for (int u = 0; u < STEP; ++u) {
+            const uint64_t kn = min(k + STEP + u, k1 - 1);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t sh = 32 * h + 16 * lg;
-            v4i va[4], vb[2];
+            for (int x = 0; x < 4; ++x) na[u][x] = pa[kn * ldw + 32 * x];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) va[x] = bits16_lut(lut, (uint32_t)(a[x] >> sh));
-#pragma unroll
-            for (int y = 0; y < 2; ++y) vb[y] = bits16_lut(lut, (uint32_t)(b[y] >> sh));
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-                    acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(va[x], vb[y], acc[x][y], 0, 0, 0);
+            for (int y = 0; y < 2; ++y) nb[u][y] = pb[kn * ldw + 32 * y];
         }
 #pragma unroll
-        for (int x = 0; x < 4; ++x) a[x] = na[x];
+        for (int u = 0; u < STEP; ++u) {
+            if (k + u >= k1) break;  // wave-uniform: the tail of the range
 #pragma unroll
-        for (int y = 0; y < 2; ++y) b[y] = nb[y];
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t sh = 32 * h + 16 * lg;
+                v4i va[4], vb[2];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) va[x] = bits16_lut(lut, (uint32_t)(a[u][x] >> sh));
+#pragma unroll
+                for (int y = 0; y < 2; ++y) vb[y] = bits16_lut(lut, (uint32_t)(b[u][y] >> sh));
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(va[x], vb[y], acc[x][y], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[u][x] = na[u][x];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) b[u][y] = nb[u][y];
+        }
     }
     // accumulator r of lane (lg, lm) holds row 8*(r/4) + 4*lg + r%4, column lm of each 32 x 32 tile
 #pragma unroll
@@ -309,7 +325,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
             k_gram_popc<<<grid, kNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
         } else {
             JAS_TIMED("gram_mfma", s);
-            k_gram_mfma<2><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            k_gram_mfma<2, 4><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
         }
         check_launch("gram");
     }

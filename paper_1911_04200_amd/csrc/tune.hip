@@ -10,8 +10,8 @@
 // The threshold t minimising time(t) is taken, among those whose packed matrix
 // (words(t) * 8 * ceil(n/128)*128 bytes) fits the memory cap.  r_pair and
 // r_word are the throughputs measured on MI355X for the two kernels
-// (k_list_pairs: 1.6e10 pair increments/s; k_gram_mfma: 1.37e13 word
-// pairs/s, 87.5e12 bit products/s).
+// (k_list_pairs: 1.5e10 pair increments/s; k_gram_mfma: 2.25e13 word
+// pairs/s, i.e. 1.44e15 bit products/s).
 #include <algorithm>
 #include <cmath>
 
@@ -20,8 +20,8 @@
 namespace jas {
 
 namespace {
-constexpr double kPairRate = 1.6e10;   // row-list pair increments per second
-constexpr double kWordRate = 1.37e13;  // packed 64-bit word pairs per second (MFMA kernel)
+constexpr double kPairRate = 1.5e10;   // row-list pair increments per second
+constexpr double kWordRate = 2.25e13;  // packed 64-bit word pairs per second (MFMA kernel)
 }  // namespace
 
 uint32_t choose_dense_min_degree(const std::vector<uint64_t> &h, uint32_t n, uint64_t nbatches,
