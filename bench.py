@@ -31,7 +31,8 @@ def log(msg):
 
 
 def kernel_source_hash(kernel: str) -> str:
-    src = {"radix_scatter": "radix.hip", "radix_hist": "radix.hip", "gram_popc": "gram.hip",
+    src = {"radix_scatter": "radix.hip", "radix_onesweep": "radix.hip", "radix_hist": "radix.hip",
+           "gram_popc": "gram.hip", "gram_mfma": "gram.hip", "list_pairs": "gram.hip",
            "cls_count": "encode.hip", "cls_write": "encode.hip", "pack": "encode.hip",
            "build_keys": "encode.hip"}.get(kernel)
     if src is None:
@@ -44,7 +45,7 @@ def kernel_source_hash(kernel: str) -> str:
 
 def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
     """(bound, algorithmic amount per launch, unit, per-unit description) of a kernel."""
-    if kernel == "radix_scatter":
+    if kernel in ("radix_scatter", "radix_onesweep"):
         return "hbm", 16.0 * N / 1e9, "GB/s", "16 B per key per pass (read 8 + write 8)"
     if kernel == "radix_hist":
         return "hbm", 8.0 * N / 1e9, "GB/s", "8 B per key per pass (read)"

@@ -35,6 +35,10 @@ jas_status guard(F &&f) {
 }
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0; }
+__global__ void k_zero_u64(unsigned long long *p, uint64_t len) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
 
 // Offsets to the host and validated: offsets[0] = 0, non-decreasing.
 std::vector<uint64_t> host_offsets(const uint64_t *offsets, int32_t n, bool host, hipStream_t s, const char *what) {
@@ -178,7 +182,13 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
             }
             RadixWork rw;
             radix_prepare(rw, N, s, &tb);
-            build_keys(dids, doff, n, N, sbits, U, keys.p, err.p, rw.counts.p, s);
+            DevBuf<unsigned long long> ghist;
+            ghist.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, &tb, true, "digit totals");
+            {
+                JAS_TIMED("zero_u32", s);
+                k_zero_u64<<<64, 256, 0, s>>>(ghist.p, (uint64_t)kGhistReplicas * kMaxPasses * 256);
+            }
+            build_keys(dids, doff, n, N, sbits, U, keys.p, err.p, rw.counts.p, ghist.p, s);
             uint32_t herr = 0;
             JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
@@ -186,7 +196,11 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
             ids_d.release();
             off_d.release();
             JAS_HOST_TIMED("sort_enqueue");
-            radix_sort_u64(keys, alt, N, sbits, sbits + U, rw, s, &tb, /*first_counts_ready=*/true);
+            if (!radix_sort_onesweep(keys, alt, N, sbits, sbits + U, ghist.p, err.p, s, &tb))
+                radix_sort_u64(keys, alt, N, sbits, sbits + U, rw, s, &tb, /*first_counts_ready=*/true);
+            JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipStreamSynchronize(s));
+            if (herr) fail(JAS_EDEVICE, "jas_encode: the radix sort's look-back waited too long (result discarded)");
         }
         try {
             encode_sorted(db.get(), keys.p, N, s, &tb);

@@ -45,18 +45,24 @@ enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
 // Keys of one radix chunk (kChunk entries) per block; also the chunk's
 // histogram of the first radix digit (bits sbits .. sbits+7 of the key), so
 // the first sort pass needs no histogram pass of its own.
+// Also the totals of every radix digit of every pass (ghist, kGhistReplicas
+// copies summed later), which the single-pass scatter needs.
 __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__ ids,
                                                      const uint64_t *__restrict__ off, int32_t n, uint64_t N,
                                                      uint32_t sbits, uint64_t hi_mask, uint32_t dmask,
                                                      uint64_t *__restrict__ keys, uint32_t *err,
-                                                     uint32_t *__restrict__ counts, uint32_t nchunks) {
+                                                     uint32_t *__restrict__ counts, uint32_t nchunks,
+                                                     uint32_t npass, unsigned long long *__restrict__ ghist) {
     __shared__ int32_t s_lo, s_hi;
     __shared__ uint32_t h[kWaves][256];
+    __shared__ uint32_t gh[kMaxPasses][256];
     const uint32_t tid = threadIdx.x, w = tid / kWave;
     const uint64_t b0 = (uint64_t)blockIdx.x * kChunk;
     const uint64_t b1 = min(N, b0 + kChunk);
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) h[k][tid] = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxPasses; ++k) gh[k][tid] = 0;
     if (tid == 0) {
         s_lo = find_sample(off, 0, n - 1, b0);
         s_hi = find_sample(off, s_lo, n - 1, b1 - 1);
@@ -71,6 +77,7 @@ __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__
         const uint64_t key = (id << sbits) | (uint64_t)lo;
         keys[t] = key;
         atomicAdd(&h[w][(uint32_t)(key >> sbits) & dmask], 1u);
+        for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(uint32_t)(id >> (8 * q)) & 255u], 1u);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1u);
     __syncthreads();
@@ -78,6 +85,9 @@ __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) c += h[k][tid];
     counts[(uint64_t)tid * nchunks + blockIdx.x] = c;
+    unsigned long long *g = ghist + (uint64_t)(blockIdx.x % kGhistReplicas) * kMaxPasses * 256;
+    for (uint32_t q = 0; q < npass; ++q)
+        if (gh[q][tid]) atomicAdd(&g[q * 256 + tid], (unsigned long long)gh[q][tid]);
 }
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t len, uint64_t v) {
@@ -162,8 +172,10 @@ __global__ __launch_bounds__(kNT) void k_cls_count(const uint64_t *__restrict__ 
             if (c.first) {
                 ++nD;
                 const uint32_t s = (uint32_t)(L[i + 1] & smask);
-                if (lds_hist) atomicAdd(&hist[s], 1u);
-                else atomicAdd(&card[s], 1ull);
+                if (s < (uint32_t)n) {
+                    if (lds_hist) atomicAdd(&hist[s], 1u);
+                    else atomicAdd(&card[s], 1ull);
+                }
             }
             nS += c.shared;
             nR += c.rowstart;
@@ -462,8 +474,9 @@ uint64_t to_host_u64(const uint64_t *dptr, hipStream_t s) {
 }  // namespace
 
 void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
-                uint64_t *keys, uint32_t *err, uint32_t *counts, hipStream_t s) {
+                uint64_t *keys, uint32_t *err, uint32_t *counts, unsigned long long *ghist, hipStream_t s) {
     if (N == 0) return;
+    const uint32_t npass = (U + 7) / 8;
     const uint64_t hi_mask = U >= 64 ? 0 : ~((uint64_t(1) << U) - 1);
     const uint64_t blocks = div_up(N, kChunk);
     if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many IDs");
@@ -471,7 +484,7 @@ void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_
     {
         JAS_TIMED("build_keys", s);
         k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, dmask, keys, err, counts,
-                                                      (uint32_t)blocks);
+                                                      (uint32_t)blocks, npass, ghist);
     }
     check_launch("build keys");
 }

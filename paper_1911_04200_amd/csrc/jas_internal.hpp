@@ -168,6 +168,16 @@ struct RadixWork {
 // counts (radix_prepare + build_keys computed them).
 void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
                     RadixWork &w, hipStream_t s, Budget *b, bool first_counts_ready = false);
+
+// Single-pass-per-digit sort (decoupled look-back) of keys whose digit totals
+// are known: ghist = kGhistReplicas copies of [kMaxPasses][256] totals of the
+// digits of bits lo_bit + 8q.  Returns false (and does nothing) when a digit
+// total reaches 2^30, where the caller uses radix_sort_u64.  A look-back that
+// waits too long sets bit 1 of err[0] (the result is then invalid).
+constexpr uint32_t kMaxPasses = 8;
+constexpr uint32_t kGhistReplicas = 32;
+bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
+                         uint32_t hi_bit, const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b);
 // Allocates w for N keys; returns the number of chunks (counts is [256][chunks]).
 uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b);
 uint64_t radix_work_bytes(uint64_t N);
@@ -175,7 +185,7 @@ uint64_t radix_work_bytes(uint64_t N);
 // Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;
 // counts[d][chunk]: histogram of the first radix digit per radix chunk.
 void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
-                uint64_t *keys, uint32_t *err, uint32_t *counts, hipStream_t s);
+                uint64_t *keys, uint32_t *err, uint32_t *counts, unsigned long long *ghist, hipStream_t s);
 
 // Encoding after the sort (see encode.hip).
 void encode_sorted(jas_db *db, const uint64_t *keys, uint64_t N, hipStream_t s, Budget *tmpb);

@@ -141,6 +141,168 @@ __global__ __launch_bounds__(kNT) void k_radix_scatter(const uint64_t *__restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass scatter with decoupled look-back (chained scan: Merrill &
+// Garland, "Single-pass parallel prefix scan with decoupled look-back",
+// 2016; as in Adinets & Merrill's Onesweep, 2022).  One 4096-key tile per
+// block; tiles take tickets from an atomic counter in launch order, so every
+// tile a block waits for already belongs to a running block.  Per tile and
+// digit a 32-bit status word holds a flag (aggregate / inclusive prefix) and
+// a 30-bit count; the caller guarantees every digit total is < 2^30.
+constexpr uint32_t kFlagA = 1u << 30;  // the tile's own count is available
+constexpr uint32_t kFlagP = 2u << 30;  // the inclusive prefix over tiles 0..t is available
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+constexpr uint32_t kMaxSpin = 1u << 20;  // bounded wait (~0.1 s of polls), then give up and flag
+
+__device__ __forceinline__ void status_store(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t status_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kNT) void k_radix_onesweep(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                                                         uint64_t N, uint32_t shift, uint32_t nbits,
+                                                         const uint64_t *__restrict__ gstart,
+                                                         uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
+                                                         uint32_t ntiles, uint32_t *__restrict__ err) {
+    __shared__ uint64_t stage[kTile];
+    __shared__ uint32_t wcnt[kWaves][kRadix];
+    __shared__ uint32_t tdp[kRadix];
+    __shared__ uint64_t base[kRadix];
+    __shared__ uint64_t sh[kWaves];
+    __shared__ uint32_t tile_sh;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const uint32_t mask = (1u << nbits) - 1u;
+    const uint64_t lt = lanemask_lt();
+    const uint64_t gs = gstart[tid];
+    // persistent: take tiles in ticket order until none is left
+    for (;;) {
+        if (tid == 0) tile_sh = atomicAdd(ticket, 1u);
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
+        __syncthreads();
+        const uint32_t tile = tile_sh;
+        if (tile >= ntiles) break;  // uniform: every thread read the same ticket
+        const uint64_t t0 = (uint64_t)tile * kTile;
+        const uint64_t c1 = min(N, t0 + kTile);
+        const uint64_t wb = t0 + (uint64_t)w * (kTile / kWaves);
+        uint64_t key[kRounds];
+        uint32_t rank[kRounds];
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            const uint64_t t = wb + (uint64_t)j * kWave + lane;
+            key[j] = t < c1 ? in[t] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            const uint64_t t = wb + (uint64_t)j * kWave + lane;
+            const bool valid = t < c1;
+            const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
+            uint64_t peers = __ballot(valid);
+            for (uint32_t b = 0; b < nbits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t vote = __ballot(valid && bit);
+                peers &= bit ? vote : ~vote;
+            }
+            const uint32_t before = __popcll(peers & lt);
+            const uint32_t cnt = __popcll(peers);
+            uint32_t b0 = 0;
+            if (valid) b0 = wcnt[w][d];
+            if (valid && before == 0) wcnt[w][d] = b0 + cnt;
+            rank[j] = b0 + before;
+        }
+        __syncthreads();
+        uint32_t c[kWaves];
+        uint32_t tc = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            c[k] = wcnt[k][tid];
+            tc += c[k];
+        }
+        // thread tid = digit: publish, look back, publish the inclusive prefix
+        uint32_t *st = status + (uint64_t)tile * kRadix + tid;
+        uint32_t excl = 0;
+        if (tile == 0) {
+            status_store(st, kFlagP | tc);
+        } else {
+            status_store(st, kFlagA | tc);
+            for (int64_t j = (int64_t)tile - 1; j >= 0; --j) {
+                const uint32_t *pj = status + (uint64_t)j * kRadix + tid;
+                uint32_t v = status_load(pj);
+                uint32_t spins = 0;
+                while ((v & ~kValMask) == 0) {
+                    // give up after kMaxSpin polls, or at once when any tile has given up
+                    if (++spins > kMaxSpin || (status_load(err) & 2u)) {
+                        atomicOr(err, 2u);
+                        v = kFlagP;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    v = status_load(pj);
+                }
+                excl += v & kValMask;
+                if ((v & ~kValMask) == kFlagP) break;
+            }
+            status_store(st, kFlagP | ((excl + tc) & kValMask));
+        }
+        base[tid] = gs + excl;
+        uint64_t tot;
+        const uint32_t ex = (uint32_t)block_excl_scan<kNT>(tc, sh, &tot);
+        tdp[tid] = ex;
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            wcnt[k][tid] = run;
+            run += c[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRounds; ++j) {
+            const uint64_t t = wb + (uint64_t)j * kWave + lane;
+            if (t < c1) {
+                const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
+                stage[tdp[d] + wcnt[w][d] + rank[j]] = key[j];
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt_tile = (uint32_t)(c1 - t0);
+        for (uint32_t i = tid; i < cnt_tile; i += kNT) {
+            const uint64_t k = stage[i];
+            const uint32_t d = (uint32_t)(k >> shift) & mask;
+            out[base[d] + (i - tdp[d])] = k;
+        }
+        __syncthreads();  // stage, tdp, base and tile_sh are reused by the next tile
+    }
+}
+
+// gstart[q][d] = exclusive scan over digits of the summed replicas; maxima[q] = largest digit total.
+__global__ __launch_bounds__(kNT) void k_digit_starts(const unsigned long long *__restrict__ ghist, uint32_t npass,
+                                                       uint64_t *__restrict__ gstart, uint64_t *__restrict__ maxima) {
+    __shared__ uint64_t sh[kWaves];
+    __shared__ uint64_t tot_sh[kRadix];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t q = 0; q < npass; ++q) {
+        uint64_t t = 0;
+        for (uint32_t r = 0; r < kGhistReplicas; ++r) t += ghist[((uint64_t)r * kMaxPasses + q) * kRadix + tid];
+        uint64_t all;
+        gstart[q * kRadix + tid] = block_excl_scan<kNT>(t, sh, &all);
+        tot_sh[tid] = t;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t m = 0;
+            for (int d = 0; d < kRadix; ++d) m = m > tot_sh[d] ? m : tot_sh[d];
+            maxima[q] = m;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill32(uint32_t *p, uint64_t len) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 }  // namespace
 
 uint64_t radix_work_bytes(uint64_t N) {
@@ -183,6 +345,57 @@ void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, u
         std::swap(keys.p, alt.p);
         std::swap(keys.n, alt.n);
     }
+}
+
+}  // namespace jas
+
+namespace jas {
+
+bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
+                         uint32_t hi_bit, const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b) {
+    if (N <= 1 || hi_bit <= lo_bit) return true;
+    const uint32_t npass = (hi_bit - lo_bit + 7) / 8;
+    if (npass > kMaxPasses) return false;
+    DevBuf<uint64_t> gstart, maxima;
+    gstart.alloc((uint64_t)kMaxPasses * kRadix, s, b, true, "digit starts");
+    maxima.alloc(kMaxPasses, s, b, true, "digit maxima");
+    {
+        JAS_TIMED("digit_starts", s);
+        k_digit_starts<<<1, kNT, 0, s>>>(ghist, npass, gstart.p, maxima.p);
+    }
+    check_launch("digit starts");
+    uint64_t hm[kMaxPasses];
+    JAS_HIP(hipMemcpyAsync(hm, maxima.p, sizeof(uint64_t) * npass, hipMemcpyDeviceToHost, s));
+    JAS_HIP(hipStreamSynchronize(s));
+    for (uint32_t q = 0; q < npass; ++q)
+        if (hm[q] >= (uint64_t)kValMask) return false;
+    const uint64_t ntiles = div_up(N, kTile);
+    if (ntiles > 0xFFFFFFFFull) return false;
+    // persistent blocks: a few per CU (256 CUs), never more than there are tiles
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 8);
+    DevBuf<uint32_t> status, ticket;
+    status.alloc(ntiles * kRadix + 1, s, b, true, "look-back status");
+    ticket.alloc(1, s, b, true, "tile ticket");
+    for (uint32_t q = 0; q < npass; ++q) {
+        const uint32_t bit = lo_bit + 8 * q;
+        const uint32_t nbits = min(8u, hi_bit - bit);
+        {
+            JAS_TIMED("fill_status", s);
+            k_fill32<<<(uint32_t)std::min<uint64_t>(div_up(ntiles * kRadix + 1, 256), 65536), 256, 0, s>>>(
+                status.p, ntiles * kRadix + 1);
+            k_fill32<<<1, 64, 0, s>>>(ticket.p, 1);
+        }
+        check_launch("look-back reset");
+        {
+            JAS_TIMED("radix_onesweep", s);
+            k_radix_onesweep<<<grid, kNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
+                                                  ticket.p, (uint32_t)ntiles, err);
+        }
+        check_launch("radix scatter (look-back)");
+        std::swap(keys.p, alt.p);
+        std::swap(keys.n, alt.n);
+    }
+    return true;
 }
 
 }  // namespace jas
