@@ -169,46 +169,51 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
                 dids = ids_d.p;
             }
         }
-        DevBuf<uint64_t> keys;
+        // Sort the keys on their top ID bits (the rest is finished per bucket
+        // range in LDS by encode_sorted).  Both buffers get two spare entries:
+        // after the sort the free one holds the shared pairs and row pointers.
+        DevBuf<uint64_t> keys, alt;
+        const SortPlan plan = sort_plan(N, U);
         if (N > 0) {
-            DevBuf<uint64_t> alt;
             DevBuf<uint32_t> err;
-            keys.alloc(N, s, &tb, true, "sort keys");
-            alt.alloc(N, s, &tb, true, "sort keys (second buffer)");
+            keys.alloc(N + 2, s, &tb, true, "sort keys");
+            alt.alloc(N + 2, s, &tb, true, "sort keys (second buffer)");
             err.alloc(1, s, &tb, true, "error flag");
             {
                 JAS_TIMED("zero_u32", s);
                 k_zero_u32<<<1, 1, 0, s>>>(err.p);
             }
-            RadixWork rw;
-            radix_prepare(rw, N, s, &tb);
             DevBuf<unsigned long long> ghist;
             ghist.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, &tb, true, "digit totals");
             {
                 JAS_TIMED("zero_u32", s);
                 k_zero_u64<<<64, 256, 0, s>>>(ghist.p, (uint64_t)kGhistReplicas * kMaxPasses * 256);
             }
-            build_keys(dids, doff, n, N, sbits, U, keys.p, err.p, rw.counts.p, ghist.p, s);
+            build_keys(dids, doff, n, N, sbits, U, plan, keys.p, err.p, ghist.p, s);
             uint32_t herr = 0;
             JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
             if (herr) fail(JAS_EINVAL, "jas_encode: an ID is >= 2^universe_bits");
             ids_d.release();
-            off_d.release();
             JAS_HOST_TIMED("sort_enqueue");
-            if (!radix_sort_onesweep(keys, alt, N, sbits, sbits + U, ghist.p, err.p, s, &tb))
-                radix_sort_u64(keys, alt, N, sbits, sbits + U, rw, s, &tb, /*first_counts_ready=*/true);
+            const uint32_t lo = sbits + U - plan.top_bits, hi = sbits + U;
+            if (plan.top_bits > 0 && !radix_sort_onesweep(keys, alt, N, lo, hi, plan.width, ghist.p, err.p, s, &tb)) {
+                RadixWork rw;
+                radix_sort_u64(keys, alt, N, lo, hi, rw, s, &tb);
+            }
             JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
             if (herr) fail(JAS_EDEVICE, "jas_encode: the radix sort's look-back waited too long (result discarded)");
         }
         try {
-            encode_sorted(db.get(), keys.p, N, s, &tb);
+            encode_sorted(db.get(), keys, alt, N, plan, doff, s, &tb);
         } catch (...) {
             // the db's buffers return to the cache as idle: let their kernels finish first
             (void)hipStreamSynchronize(s);
             throw;
         }
+        alt.release();
+        off_d.release();
         keys.release();
         db->budget.limit = 0;
         db->budget.other = nullptr;

@@ -42,25 +42,21 @@ constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass
 enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
 
 // ---------------------------------------------------------------------------
-// Keys of one radix chunk (kChunk entries) per block; also the chunk's
-// histogram of the first radix digit (bits sbits .. sbits+7 of the key), so
-// the first sort pass needs no histogram pass of its own.
-// Also the totals of every radix digit of every pass (ghist, kGhistReplicas
-// copies summed later), which the single-pass scatter needs.
+// Keys of one chunk (kChunk entries) per block, and the totals of every digit
+// of every global sort pass (ghist, kGhistReplicas copies summed later), which
+// the single-pass scatter needs.  Pass q's digit is ID bits
+// [idlo + width*q, idlo + width*(q+1)).
 __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__ ids,
                                                      const uint64_t *__restrict__ off, int32_t n, uint64_t N,
-                                                     uint32_t sbits, uint64_t hi_mask, uint32_t dmask,
-                                                     uint64_t *__restrict__ keys, uint32_t *err,
-                                                     uint32_t *__restrict__ counts, uint32_t nchunks,
-                                                     uint32_t npass, unsigned long long *__restrict__ ghist) {
+                                                     uint32_t sbits, uint64_t hi_mask, uint64_t *__restrict__ keys,
+                                                     uint32_t *err, uint32_t npass, uint32_t idlo, uint32_t width,
+                                                     unsigned long long *__restrict__ ghist) {
     __shared__ int32_t s_lo, s_hi;
-    __shared__ uint32_t h[kWaves][256];
     __shared__ uint32_t gh[kMaxPasses][256];
-    const uint32_t tid = threadIdx.x, w = tid / kWave;
+    const uint32_t tid = threadIdx.x;
     const uint64_t b0 = (uint64_t)blockIdx.x * kChunk;
     const uint64_t b1 = min(N, b0 + kChunk);
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) h[k][tid] = 0;
+    const uint32_t dmask = (1u << width) - 1u;
 #pragma unroll
     for (int k = 0; k < kMaxPasses; ++k) gh[k][tid] = 0;
     if (tid == 0) {
@@ -74,17 +70,11 @@ __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__
         lo = find_sample(off, lo, s_hi, t);  // t only grows, so the search range only shrinks
         const uint64_t id = ids[t];
         bad |= (id & hi_mask) != 0;
-        const uint64_t key = (id << sbits) | (uint64_t)lo;
-        keys[t] = key;
-        atomicAdd(&h[w][(uint32_t)(key >> sbits) & dmask], 1u);
-        for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(uint32_t)(id >> (8 * q)) & 255u], 1u);
+        keys[t] = (id << sbits) | (uint64_t)lo;
+        for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(uint32_t)(id >> (idlo + width * q)) & dmask], 1u);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1u);
     __syncthreads();
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) c += h[k][tid];
-    counts[(uint64_t)tid * nchunks + blockIdx.x] = c;
     unsigned long long *g = ghist + (uint64_t)(blockIdx.x % kGhistReplicas) * kMaxPasses * 256;
     for (uint32_t q = 0; q < npass; ++q)
         if (gh[q][tid]) atomicAdd(&g[q * 256 + tid], (unsigned long long)gh[q][tid]);
@@ -285,6 +275,257 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Classification in LDS after a sort of the top ID bits only.
+//
+// The keys are ordered by bucket = key >> bsh (the top ID bits) and, inside a
+// bucket, still in input order (every pass was stable, so entries of one ID
+// are in ascending sample order).  Range c runs from the first bucket edge at
+// or after c*kLStride to the first at or after (c+1)*kLStride (k_range_starts).
+// A range is made of whole buckets, so it holds whole rows of A and needs no
+// halo.  One block loads a range (<= kLocalCapKeys keys) into LDS, finishes
+// the sort there (stable LSD passes over the ID bits below the range's first
+// bucket), classifies as k_cls_count/k_cls_write do, and writes its results
+// at the range's own position (distinct keys in place over the range, shared
+// pairs at the range start, rows at half the range start) with its counts;
+// k_local_move then packs them after a scan of the counts.  A range longer
+// than kLocalCapKeys (a bucket with very many keys) sets err bit 8 before any
+// block writes; the caller then sorts every ID bit and uses
+// k_cls_count/k_cls_write.
+constexpr int kLNT = 512;
+constexpr int kLWaves = kLNT / kWave;
+constexpr uint32_t kLRounds = kLocalCapKeys / kLNT;  // 16 keys per thread
+constexpr uint64_t kLStride = 4096;
+
+__device__ __forceinline__ uint64_t bucket_of(uint64_t key, uint32_t bsh) { return bsh >= 64 ? 0 : key >> bsh; }
+__device__ __forceinline__ uint32_t dev_ceil_log2(uint64_t v) { return v <= 1 ? 0u : 64u - (uint32_t)__clzll(v - 1); }
+
+// rs[c] = first bucket edge at or after c*kLStride, c in [0, nlc]; positions
+// 0 and N are edges.  One wave per c, 256 keys per step.  An edge more than
+// kLocalCapKeys keys away is not looked for: rs[c] = ~0 and err |= 8.
+__global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict__ K, uint64_t N, uint32_t bsh,
+                                                       uint64_t nlc, uint64_t *__restrict__ rs, uint32_t *err) {
+    const uint64_t c = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint32_t lane = lane_id();
+    if (c > nlc) return;  // whole waves
+    const uint64_t x = c * kLStride;
+    if (x == 0 || x >= N) {
+        if (lane == 0) rs[c] = min(x, N);
+        return;
+    }
+    const uint64_t b0 = bucket_of(K[x - 1], bsh);
+    for (uint64_t y = x; y < x + kLocalCapKeys; y += 4 * kWave) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t t = y + k * kWave + lane;
+            const uint64_t m = __ballot(t >= N || bucket_of(K[t], bsh) != b0);
+            if (m) {
+                if (lane == 0) rs[c] = y + k * kWave + (uint64_t)__builtin_ctzll(m);
+                return;
+            }
+        }
+    }
+    if (lane == 0) {
+        rs[c] = ~0ull;
+        atomicOr(err, 8u);
+    }
+}
+
+__global__ void k_range_check(const uint64_t *rs, uint64_t nlc, uint32_t *err) {
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nlc; c += (uint64_t)gridDim.x * blockDim.x)
+        if (rs[c] == ~0ull || rs[c + 1] == ~0ull || rs[c + 1] < rs[c] || rs[c + 1] - rs[c] > kLocalCapKeys)
+            atomicOr(err, 8u);
+}
+
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void k_local_cls(
+    uint64_t *__restrict__ K, uint32_t sbits, uint64_t smask, uint32_t bsh, uint32_t lowbits,
+    const uint64_t *__restrict__ rs, uint32_t nlc, uint32_t *__restrict__ cnt, int keep, uint32_t *__restrict__ Sg,
+    uint64_t *__restrict__ rid_g, uint64_t *__restrict__ rptr_g, unsigned long long *__restrict__ dupc,
+    unsigned long long *__restrict__ st) {
+    __shared__ uint64_t A[kLocalCapKeys];
+    __shared__ uint32_t wcnt[kLWaves][256];
+    __shared__ uint32_t tdp[256];
+    __shared__ uint64_t sh[kLWaves];
+    __shared__ uint32_t wc[3][kLWaves];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const uint64_t lt = lanemask_lt();
+    const uint32_t c = blockIdx.x;
+    const uint64_t s0 = rs[c], s1 = rs[c + 1];
+    const uint32_t L = (uint32_t)(s1 - s0);  // <= kLocalCapKeys (k_range_check)
+    for (uint32_t i = tid; i < L; i += kLNT) A[i] = K[s0 + i];
+    // wave w owns positions [w*seg, (w+1)*seg), 64 per round, in order
+    const uint32_t seg = ((L + kLWaves - 1) / kLWaves + kWave - 1) / kWave * kWave;
+    const uint32_t rounds = seg / kWave;
+    const uint32_t wb = w * seg;
+    __syncthreads();
+
+    // --- finish the sort: stable LSD passes (8-bit digits) over the relative ID
+    if (L > 1) {
+        const uint64_t bf = bucket_of(A[0], bsh), bl = bucket_of(A[L - 1], bsh);
+        const uint64_t rbase = bf << lowbits;  // bf > 0 only when lowbits < U <= 63
+        const uint32_t nb = lowbits + dev_ceil_log2(bl - bf + 1);  // relative IDs are < 2^nb
+        for (uint32_t p = 0; p < nb; p += 8) {
+            for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&wcnt[0][0])[i] = 0;
+            uint64_t key[kLRounds];
+            uint32_t dig[kLRounds], rank[kLRounds];
+#pragma unroll
+            for (uint32_t j = 0; j < kLRounds; ++j) {
+                const uint32_t t = wb + j * kWave + lane;
+                key[j] = (j < rounds && t < L) ? A[t] : 0;
+                dig[j] = (uint32_t)((((key[j] >> sbits) - rbase) >> p)) & 255u;
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t j = 0; j < kLRounds; ++j) {
+                if (j < rounds) {
+                    const bool valid = wb + j * kWave + lane < L;
+                    const uint32_t d = dig[j];
+                    uint64_t peers = __ballot(valid);
+#pragma unroll
+                    for (uint32_t b = 0; b < 8; ++b) {
+                        const bool bit = (d >> b) & 1u;
+                        const uint64_t vote = __ballot(bit);
+                        peers &= bit ? vote : ~vote;
+                    }
+                    const uint32_t before = __popcll(peers & lt);
+                    uint32_t b0 = 0;
+                    if (valid) b0 = wcnt[w][d];
+                    if (valid && before == 0) wcnt[w][d] = b0 + __popcll(peers);
+                    rank[j] = b0 + before;
+                }
+            }
+            __syncthreads();
+            uint32_t tc = 0;
+            if (tid < 256)
+                for (int k = 0; k < kLWaves; ++k) tc += wcnt[k][tid];
+            uint64_t all;
+            const uint32_t ex = (uint32_t)block_excl_scan<kLNT>(tc, sh, &all);
+            if (tid < 256) {
+                tdp[tid] = ex;
+                uint32_t run = 0;
+                for (int k = 0; k < kLWaves; ++k) {
+                    const uint32_t v = wcnt[k][tid];
+                    wcnt[k][tid] = run;
+                    run += v;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t j = 0; j < kLRounds; ++j)
+                if (j < rounds && wb + j * kWave + lane < L) A[tdp[dig[j]] + wcnt[w][dig[j]] + rank[j]] = key[j];
+            __syncthreads();
+        }
+    }
+
+    // --- classify (as classify_lds, with the whole row in LDS)
+    uint32_t fD = 0, fS = 0, fR = 0;
+    uint32_t nD = 0, nS = 0, nR = 0;
+    uint64_t rows = 0;  // nonzero rows of A (distinct IDs) seen by this thread
+    for (uint32_t j = 0; j < rounds; ++j) {
+        const uint32_t t = wb + j * kWave + lane;
+        bool d = false, sh_ = false, r = false;
+        if (t < L) {
+            const uint64_t key = A[t], id = key >> sbits;
+            const bool first = t == 0 || A[t - 1] != key;
+            const bool left = first && t > 0 && (A[t - 1] >> sbits) == id;
+            bool right = false;
+            if (first) {
+                uint32_t u = t + 1;
+                while (u < L && A[u] == key) ++u;
+                right = u < L && (A[u] >> sbits) == id;
+            }
+            d = first;
+            sh_ = first && (left || right);
+            r = sh_ && !left;
+            rows += first && !left;
+            if (!first) atomicAdd(&dupc[key & smask], 1ull);
+        }
+        fD |= (uint32_t)d << j;
+        fS |= (uint32_t)sh_ << j;
+        fR |= (uint32_t)r << j;
+        nD += __popcll(__ballot(d));
+        nS += __popcll(__ballot(sh_));
+        nR += __popcll(__ballot(r));
+    }
+    if (lane == 0) {
+        wc[0][w] = nD;
+        wc[1][w] = nS;
+        wc[2][w] = nR;
+    }
+    uint64_t all_rows;
+    block_excl_scan<kLNT>(rows, sh, &all_rows);  // synchronises: wc is complete after it
+    if (tid == 0) {
+        uint32_t tD = 0, tS = 0, tR = 0;
+        for (int k = 0; k < kLWaves; ++k) {
+            tD += wc[0][k];
+            tS += wc[1][k];
+            tR += wc[2][k];
+        }
+        cnt[c] = tD;
+        cnt[nlc + c] = tS;
+        cnt[2 * (uint64_t)nlc + c] = tR;
+        if (all_rows) atomicAdd(&st[ST_ROWS], (unsigned long long)all_rows);
+    }
+
+    // --- ordered writes at the range's own position (every read of the range is done)
+    uint32_t pD = 0, pS = 0, pR = 0;
+    for (uint32_t k = 0; k < w; ++k) {
+        pD += wc[0][k];
+        pS += wc[1][k];
+        pR += wc[2][k];
+    }
+    const uint64_t r0 = s0 / 2;
+    for (uint32_t j = 0; j < rounds; ++j) {
+        const bool d = (fD >> j) & 1u, sh_ = (fS >> j) & 1u, r = (fR >> j) & 1u;
+        const uint64_t bd = __ballot(d), bs = __ballot(sh_), br = __ballot(r);
+        if (d | sh_) {
+            const uint64_t key = A[wb + j * kWave + lane];
+            const uint32_t posS = pS + __popcll(bs & lt);
+            if (d && keep) K[s0 + pD + __popcll(bd & lt)] = key;
+            if (sh_) Sg[s0 + posS] = (uint32_t)(key & smask);
+            if (r) {
+                const uint64_t posR = r0 + pR + __popcll(br & lt);
+                rid_g[posR] = key >> sbits;
+                rptr_g[posR] = posS;
+            }
+        }
+        pD += __popcll(bd);
+        pS += __popcll(bs);
+        pR += __popcll(br);
+    }
+}
+
+// Packs what k_local_cls wrote per range: one block per range (grid-stride).
+__global__ __launch_bounds__(256) void k_local_move(const uint64_t *__restrict__ rs, uint64_t nlc,
+                                                     const uint64_t *__restrict__ oD, const uint64_t *__restrict__ oS,
+                                                     const uint64_t *__restrict__ oR, const uint64_t *__restrict__ K,
+                                                     const uint32_t *__restrict__ Sg,
+                                                     const uint64_t *__restrict__ rid_g,
+                                                     const uint64_t *__restrict__ rptr_g, uint64_t *__restrict__ Dk,
+                                                     uint32_t *__restrict__ S, uint64_t *__restrict__ row_id,
+                                                     uint64_t *__restrict__ row_ptr) {
+    for (uint64_t c = blockIdx.x; c < nlc; c += gridDim.x) {
+        const uint64_t s0 = rs[c], r0 = s0 / 2;
+        const uint64_t d0 = oD[c], nd = oD[c + 1] - d0;
+        const uint64_t q0 = oS[c], ns = oS[c + 1] - q0;
+        const uint64_t w0 = oR[c], nr = oR[c + 1] - w0;
+        for (uint64_t i = threadIdx.x; i < ns; i += blockDim.x) S[q0 + i] = Sg[s0 + i];
+        for (uint64_t i = threadIdx.x; i < nr; i += blockDim.x) {
+            row_id[w0 + i] = rid_g[r0 + i];
+            row_ptr[w0 + i] = q0 + rptr_g[r0 + i];
+        }
+        if (Dk)
+            for (uint64_t i = threadIdx.x; i < nd; i += blockDim.x) Dk[d0 + i] = K[s0 + i];
+    }
+}
+
+// |X_i| = entries of sample i minus its repeated (ID, sample) entries.
+__global__ void k_card_from_dups(const uint64_t *off, const unsigned long long *dupc, int32_t n,
+                                 unsigned long long *card) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        card[i] = (off[i + 1] - off[i]) - dupc[i];
+}
+
 // Row degree histogram (degrees are <= n): input of the degree threshold choice.
 __global__ __launch_bounds__(kNT) void k_deg_hist(const uint64_t *row_ptr, uint64_t R, uint32_t nb,
                                                    int lds, unsigned long long *hist) {
@@ -474,22 +715,21 @@ uint64_t to_host_u64(const uint64_t *dptr, hipStream_t s) {
 }  // namespace
 
 void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
-                uint64_t *keys, uint32_t *err, uint32_t *counts, unsigned long long *ghist, hipStream_t s) {
+                const SortPlan &plan, uint64_t *keys, uint32_t *err, unsigned long long *ghist, hipStream_t s) {
     if (N == 0) return;
-    const uint32_t npass = (U + 7) / 8;
     const uint64_t hi_mask = U >= 64 ? 0 : ~((uint64_t(1) << U) - 1);
     const uint64_t blocks = div_up(N, kChunk);
     if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many IDs");
-    const uint32_t dmask = (1u << std::min<uint32_t>(8, U)) - 1u;
     {
         JAS_TIMED("build_keys", s);
-        k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, dmask, keys, err, counts,
-                                                      (uint32_t)blocks, npass, ghist);
+        k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, keys, err, plan.npass,
+                                                      U - plan.top_bits, plan.width, ghist);
     }
     check_launch("build keys");
 }
 
-void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Budget *tb) {
+void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, const SortPlan &plan,
+                   const uint64_t *offsets, hipStream_t s, Budget *tb) {
     const int32_t n = db->n;
     const uint32_t sbits = db->sbits;
     const uint64_t smask = sbits ? ((uint64_t(1) << sbits) - 1) : 0;
@@ -509,14 +749,108 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
     }
     check_launch("fill");
 
-    // --- classify: counts per chunk, then ordered compaction -----------------
-    const uint64_t nch = div_up(N, kChunk);
-    DevBuf<uint32_t> cnt;
-    DevBuf<uint64_t> offD, offS, offR, stmp;
+    // Outputs of the classification: distinct keys (query index), shared
+    // pairs S in row order, and per shared row its ID and first pair.
     uint64_t NDk = 0, NS = 0, R = 0;
-    DevBuf<uint64_t> Dk, row_id, row_ptr;
-    DevBuf<uint32_t> S;
-    if (N > 0) {
+    DevBuf<uint64_t> Dk, rid_own, rptr_own;
+    DevBuf<uint32_t> S_own;
+    uint32_t *Sp = nullptr;
+    uint64_t *ridp = nullptr, *rptrp = nullptr;
+    bool done = N == 0;
+
+    // --- classify each range of whole buckets in LDS ------------------------
+    const uint64_t nlc = div_up(N, kLStride);
+    if (!done && nlc <= 0xFFFFFFFFull && alt.n >= N + 2) {
+        const uint32_t lowbits = db->U - plan.top_bits;
+        const uint32_t bsh = sbits + lowbits;
+        DevBuf<uint64_t> rs, flags;
+        rs.alloc(nlc + 1, s, tb, true, "range starts");
+        flags.alloc(1, s, tb, true, "range error flag");
+        uint32_t *errL = reinterpret_cast<uint32_t *>(flags.p);
+        {
+            JAS_TIMED("fill_u64", s);
+            k_fill_u64<<<1, 64, 0, s>>>(flags.p, 1, 0);
+        }
+        {
+            JAS_TIMED("range_starts", s);
+            k_range_starts<<<(uint32_t)div_up(nlc + 1, 256 / kWave), 256, 0, s>>>(keys.p, N, bsh, nlc, rs.p, errL);
+            k_range_check<<<(uint32_t)std::min<uint64_t>(div_up(nlc, 256), 4096), 256, 0, s>>>(rs.p, nlc, errL);
+        }
+        check_launch("range starts");
+        uint64_t herr = 0;
+        JAS_HIP(hipMemcpyAsync(&herr, flags.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+        if (herr == 0) {
+            DevBuf<unsigned long long> dupc;
+            DevBuf<uint32_t> cnt;
+            DevBuf<uint64_t> rid_g, offD, offS, offR, stmp;
+            dupc.alloc(std::max<int32_t>(n, 1), s, tb, true, "repeat counts");
+            cnt.alloc(3 * nlc, s, tb, true, "range counts");
+            rid_g.alloc(N / 2 + 1, s, tb, true, "row ids (by range)");
+            {
+                JAS_TIMED("fill_u64", s);
+                k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)dupc.p, (uint64_t)std::max<int32_t>(n, 1), 0);
+            }
+            // shared pairs at the range starts in the first half of the free sort
+            // buffer, row pointers (relative to the range) after it
+            uint32_t *Sg = reinterpret_cast<uint32_t *>(alt.p);
+            uint64_t *rptr_g = alt.p + div_up(N, 2);
+            {
+                JAS_TIMED("local_cls", s);
+                k_local_cls<<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p, (uint32_t)nlc,
+                                                           cnt.p, keep ? 1 : 0, Sg, rid_g.p, rptr_g, dupc.p, st.p);
+            }
+            check_launch("local classify");
+            offD.alloc(nlc + 1, s, tb, true, "range offsets");
+            offS.alloc(nlc + 1, s, tb, true, "range offsets");
+            offR.alloc(nlc + 1, s, tb, true, "range offsets");
+            stmp.alloc(scan_tmp_elems(nlc), s, tb, true, "scan scratch");
+            scan_excl_u32(cnt.p, offD.p, nlc, stmp.p, s);
+            scan_excl_u32(cnt.p + nlc, offS.p, nlc, stmp.p, s);
+            scan_excl_u32(cnt.p + 2 * nlc, offR.p, nlc, stmp.p, s);
+            uint64_t t3[3];
+            JAS_HIP(hipMemcpyAsync(&t3[0], offD.p + nlc, 8, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipMemcpyAsync(&t3[1], offS.p + nlc, 8, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipMemcpyAsync(&t3[2], offR.p + nlc, 8, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipStreamSynchronize(s));
+            NDk = t3[0];
+            NS = t3[1];
+            R = t3[2];
+            if (keep) Dk.alloc(NDk, s, &db->budget, false, "query index keys");
+            S_own.alloc(NS, s, tb, true, "shared pairs");
+            rid_own.alloc(R, s, tb, true, "row ids");
+            rptr_own.alloc(R + 1, s, tb, true, "row pointers");
+            Sp = S_own.p;
+            ridp = rid_own.p;
+            rptrp = rptr_own.p;
+            {
+                JAS_TIMED("local_move", s);
+                k_local_move<<<(uint32_t)std::min<uint64_t>(nlc, 65536), 256, 0, s>>>(
+                    rs.p, nlc, offD.p, offS.p, offR.p, keys.p, Sg, rid_g.p, rptr_g, keep ? Dk.p : nullptr, Sp, ridp,
+                    rptrp);
+            }
+            check_launch("local move");
+            {
+                JAS_TIMED("card", s);
+                k_card_from_dups<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 1024)), 256, 0,
+                                   s>>>(offsets, dupc.p, n, cardc.p);
+            }
+            check_launch("column sums");
+            done = true;
+        }
+    }
+
+    // --- otherwise: sort every ID bit, classify with neighbours in global memory
+    if (!done) {
+        JAS_HOST_TIMED("classify_fallback");
+        {
+            RadixWork rw;
+            radix_sort_u64(keys, alt, N, sbits, sbits + db->U, rw, s, tb);
+        }
+        const uint64_t *K = keys.p;
+        const uint64_t nch = div_up(N, kChunk);
+        DevBuf<uint32_t> cnt;
+        DevBuf<uint64_t> offD, offS, offR, stmp;
         cnt.alloc(3 * nch, s, tb, true, "classify counts");
         const int lds_hist = n <= kHistMax;
         const size_t shmem = lds_hist ? (size_t)n * sizeof(uint32_t) : 0;
@@ -533,15 +867,34 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         scan_excl_u32(cnt.p, offD.p, nch, stmp.p, s);
         scan_excl_u32(cnt.p + nch, offS.p, nch, stmp.p, s);
         scan_excl_u32(cnt.p + 2 * nch, offR.p, nch, stmp.p, s);
-        uint64_t tot[3];
-        JAS_HIP(hipMemcpyAsync(&tot[0], offD.p + nch, 8, hipMemcpyDeviceToHost, s));
-        JAS_HIP(hipMemcpyAsync(&tot[1], offS.p + nch, 8, hipMemcpyDeviceToHost, s));
-        JAS_HIP(hipMemcpyAsync(&tot[2], offR.p + nch, 8, hipMemcpyDeviceToHost, s));
+        uint64_t t3[3];
+        JAS_HIP(hipMemcpyAsync(&t3[0], offD.p + nch, 8, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipMemcpyAsync(&t3[1], offS.p + nch, 8, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipMemcpyAsync(&t3[2], offR.p + nch, 8, hipMemcpyDeviceToHost, s));
         JAS_HIP(hipStreamSynchronize(s));
-        NDk = tot[0];
-        NS = tot[1];
-        R = tot[2];
+        NDk = t3[0];
+        NS = t3[1];
+        R = t3[2];
+        if (keep) Dk.alloc(NDk, s, &db->budget, false, "query index keys");
+        S_own.alloc(NS, s, tb, true, "shared pairs");
+        rid_own.alloc(R, s, tb, true, "row ids");
+        rptr_own.alloc(R + 1, s, tb, true, "row pointers");
+        Sp = S_own.p;
+        ridp = rid_own.p;
+        rptrp = rptr_own.p;
+        {
+            JAS_TIMED("cls_write", s);
+            k_cls_write<<<(uint32_t)nch, kNT, 0, s>>>(K, N, sbits, smask, offD.p, offS.p, offR.p,
+                                                      keep ? Dk.p : nullptr, Sp, ridp, rptrp);
+        }
+        check_launch("classify write");
     }
+    if (N > 0) {
+        JAS_TIMED("fill_u64", s);
+        k_fill_u64<<<1, 1, 0, s>>>(rptrp + R, 1, NS);
+    }
+    check_launch("fill");
+
     // column sums -> |X_i| (int32 B needs every |X_i| < 2^31)
     db->card.alloc(std::max<int32_t>(n, 1), s, &db->budget, false, "card");
     if (n > 0) {
@@ -555,29 +908,6 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         JAS_HIP(hipMemcpyAsync(db->card.p, cardc.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
     }
     cardc.release();
-
-    if (N > 0) {
-        if (keep) Dk.alloc(NDk, s, &db->budget, false, "query index keys");
-        S.alloc(NS, s, tb, true, "shared pairs");
-        row_id.alloc(R, s, tb, true, "row ids");
-        row_ptr.alloc(R + 1, s, tb, true, "row pointers");
-        {
-            JAS_TIMED("cls_write", s);
-            k_cls_write<<<(uint32_t)nch, kNT, 0, s>>>(K, N, sbits, smask, offD.p, offS.p, offR.p,
-                                                      keep ? Dk.p : nullptr, S.p, row_id.p, row_ptr.p);
-        }
-        check_launch("classify write");
-        {
-            JAS_TIMED("fill_u64", s);
-            k_fill_u64<<<1, 1, 0, s>>>(row_ptr.p + R, 1, NS);
-        }
-        check_launch("fill");
-    }
-    cnt.release();
-    offD.release();
-    offS.release();
-    offR.release();
-    stmp.release();
 
     // --- split rows by degree ------------------------------------------------
     uint64_t QD = 0, QL = 0;
@@ -593,7 +923,7 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(div_up(R, 256), 2048);
         {
             JAS_TIMED("deg_hist", s);
-            k_deg_hist<<<blocks, kNT, lds ? nb * sizeof(uint32_t) : 0, s>>>(row_ptr.p, R, nb, lds, hist.p);
+            k_deg_hist<<<blocks, kNT, lds ? nb * sizeof(uint32_t) : 0, s>>>(rptrp, R, nb, lds, hist.p);
         }
         check_launch("degree histogram");
         std::vector<uint64_t> hh(nb);
@@ -619,7 +949,7 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         launch_1d(R, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("row_flags", st_);
-                k_row_flags<<<b, 256, 0, st_>>>(row_ptr.p, R, db->dmin, fDense.p, fList.p, st.p);
+                k_row_flags<<<b, 256, 0, st_>>>(rptrp, R, db->dmin, fDense.p, fList.p, st.p);
             }
         });
         check_launch("row flags");
@@ -652,7 +982,7 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("batch_flag", st_);
-                k_batch_flag<<<b, 256, 0, st_>>>(Drow.p, row_id.p, QD, bbits, bs.p);
+                k_batch_flag<<<b, 256, 0, st_>>>(Drow.p, ridp, QD, bbits, bs.p);
             }
         });
         check_launch("batch flags");
@@ -689,8 +1019,8 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         const uint32_t grid = (uint32_t)std::min<uint64_t>(H, 4096);
         {
             JAS_TIMED("pack", s);
-            k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, wq0.p, wq1.p, Drow.p, row_ptr.p,
-                                                                        S.p, cols, st.p);
+            k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, wq0.p, wq1.p, Drow.p, rptrp,
+                                                                        Sp, cols, st.p);
         }
         check_launch("pack");
     }
@@ -702,7 +1032,7 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
     if (QL > 0) {
         DevBuf<uint64_t> deg, tmp;
         deg.alloc(QL, s, tb, true, "row list degrees");
-        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("list_deg", st_); k_list_deg<<<b, 256, 0, st_>>>(Lrow.p, row_ptr.p, QL, deg.p); } });
+        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("list_deg", st_); k_list_deg<<<b, 256, 0, st_>>>(Lrow.p, rptrp, QL, deg.p); } });
         check_launch("list degrees");
         tmp.alloc(scan_tmp_elems(QL), s, tb, true, "scan scratch");
         scan_excl_u64(deg.p, db->list_ptr.p, QL, tmp.p, s);
@@ -711,7 +1041,7 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
         launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("list_gather", st_);
-                k_list_gather<<<b, 256, 0, st_>>>(Lrow.p, row_ptr.p, S.p, db->list_ptr.p, QL, db->list_smp.p);
+                k_list_gather<<<b, 256, 0, st_>>>(Lrow.p, rptrp, Sp, db->list_ptr.p, QL, db->list_smp.p);
             }
         });
         check_launch("list gather");
@@ -756,7 +1086,7 @@ void encode_sorted(jas_db *db, const uint64_t *K, uint64_t N, hipStream_t s, Bud
     JAS_HIP(hipStreamSynchronize(s));
     jas_encode_stats &o = db->stats;
     o.n_ids = N;
-    o.n_pairs = hst[ST_PAIRS];
+    o.n_pairs = NDk;
     o.n_rows = hst[ST_ROWS];
     o.n_shared_rows = R;
     o.n_packed_rows = QD;

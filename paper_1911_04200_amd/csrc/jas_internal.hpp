@@ -164,31 +164,46 @@ struct RadixWork {
     DevBuf<uint32_t> counts;
     DevBuf<uint64_t> offs, tmp;
 };
-// first_counts_ready: w.counts already holds the first pass's per-chunk digit
-// counts (radix_prepare + build_keys computed them).
 void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
-                    RadixWork &w, hipStream_t s, Budget *b, bool first_counts_ready = false);
+                    RadixWork &w, hipStream_t s, Budget *b);
 
 // Single-pass-per-digit sort (decoupled look-back) of keys whose digit totals
-// are known: ghist = kGhistReplicas copies of [kMaxPasses][256] totals of the
-// digits of bits lo_bit + 8q.  Returns false (and does nothing) when a digit
-// total reaches 2^30, where the caller uses radix_sort_u64.  A look-back that
-// waits too long sets bit 1 of err[0] (the result is then invalid).
+// are known: ghist = kGhistReplicas copies of [kMaxPasses][256] totals; pass q
+// sorts on bits [lo_bit + width*q, min(lo_bit + width*(q+1), hi_bit)),
+// width <= 8.  Returns false (and does nothing) when a digit total reaches
+// 2^30, where the caller uses radix_sort_u64.  A look-back that waits too long
+// sets bit 1 of err[0] (the result is then invalid).
 constexpr uint32_t kMaxPasses = 8;
 constexpr uint32_t kGhistReplicas = 32;
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
-                         uint32_t hi_bit, const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b);
+                         uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
+                         hipStream_t s, Budget *b);
 // Allocates w for N keys; returns the number of chunks (counts is [256][chunks]).
 uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b);
 uint64_t radix_work_bytes(uint64_t N);
 
-// Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;
-// counts[d][chunk]: histogram of the first radix digit per radix chunk.
-void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
-                uint64_t *keys, uint32_t *err, uint32_t *counts, unsigned long long *ghist, hipStream_t s);
+// How the ID bits are sorted.  Only the top `top_bits` of the U ID bits are
+// sorted globally (npass passes of `width` bits); that makes every bucket of
+// equal top bits contiguous, with about kBucketKeys keys per bucket for
+// uniformly spread IDs, and the encoder finishes each run of whole buckets in
+// LDS.
+struct SortPlan {
+    uint32_t top_bits = 0, npass = 0, width = 8;
+};
+constexpr uint64_t kBucketKeys = 1024;
+constexpr uint32_t kLocalCapKeys = 8192;  // keys one LDS range can hold
+SortPlan sort_plan(uint64_t N, uint32_t U);
 
-// Encoding after the sort (see encode.hip).
-void encode_sorted(jas_db *db, const uint64_t *keys, uint64_t N, hipStream_t s, Budget *tmpb);
+// Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;
+// ghist: totals of every digit of the plan's passes (kGhistReplicas copies).
+void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
+                const SortPlan &plan, uint64_t *keys, uint32_t *err, unsigned long long *ghist, hipStream_t s);
+
+// Encoding after the global sort (see encode.hip).  keys holds the N keys
+// ordered by their top plan.top_bits ID bits; alt (N + 2 entries) is free and
+// is used as scratch; offsets are the device CSR offsets.
+void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, const SortPlan &plan,
+                   const uint64_t *offsets, hipStream_t s, Budget *tmpb);
 
 // Degree threshold: rows of degree >= the result are bit-packed, 2..result-1
 // kept as row lists; minimises the modelled Gram time (see tune.hip).

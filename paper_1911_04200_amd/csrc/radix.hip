@@ -305,6 +305,15 @@ __global__ void k_fill32(uint32_t *p, uint64_t len) {
 
 }  // namespace
 
+SortPlan sort_plan(uint64_t N, uint32_t U) {
+    SortPlan p;
+    if (N <= kLocalCapKeys) return p;  // one LDS range holds everything
+    p.top_bits = std::min<uint32_t>(U, ceil_log2_u64(div_up(N, kBucketKeys)));
+    p.npass = (p.top_bits + 7) / 8;
+    p.width = p.npass ? (p.top_bits + p.npass - 1) / p.npass : 8;
+    return p;
+}
+
 uint64_t radix_work_bytes(uint64_t N) {
     const uint64_t nchunks = div_up(N, kChunk);
     const uint64_t len = (uint64_t)kRadix * nchunks;
@@ -323,14 +332,14 @@ uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b) {
 }
 
 void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
-                    RadixWork &w, hipStream_t s, Budget *b, bool first_counts_ready) {
+                    RadixWork &w, hipStream_t s, Budget *b) {
     if (N <= 1 || hi_bit <= lo_bit) return;
     const uint64_t nchunks = radix_prepare(w, N, s, b);
     const uint64_t len = (uint64_t)kRadix * nchunks;
     for (uint32_t bit = lo_bit; bit < hi_bit; bit += 8) {
         const uint32_t nbits = min(8u, hi_bit - bit);
         const uint32_t mask = (1u << nbits) - 1u;
-        if (!(first_counts_ready && bit == lo_bit)) {
+        {
             JAS_TIMED("radix_hist", s);
             k_radix_hist<<<(uint32_t)nchunks, kNT, 0, s>>>(keys.p, N, bit, mask, w.counts.p, (uint32_t)nchunks);
         }
@@ -352,9 +361,11 @@ void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, u
 namespace jas {
 
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
-                         uint32_t hi_bit, const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b) {
+                         uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
+                         hipStream_t s, Budget *b) {
     if (N <= 1 || hi_bit <= lo_bit) return true;
-    const uint32_t npass = (hi_bit - lo_bit + 7) / 8;
+    if (width < 1 || width > 8) return false;
+    const uint32_t npass = (hi_bit - lo_bit + width - 1) / width;
     if (npass > kMaxPasses) return false;
     DevBuf<uint64_t> gstart, maxima;
     gstart.alloc((uint64_t)kMaxPasses * kRadix, s, b, true, "digit starts");
@@ -377,8 +388,8 @@ bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t
     status.alloc(ntiles * kRadix + 1, s, b, true, "look-back status");
     ticket.alloc(1, s, b, true, "tile ticket");
     for (uint32_t q = 0; q < npass; ++q) {
-        const uint32_t bit = lo_bit + 8 * q;
-        const uint32_t nbits = min(8u, hi_bit - bit);
+        const uint32_t bit = lo_bit + width * q;
+        const uint32_t nbits = min(width, hi_bit - bit);
         {
             JAS_TIMED("fill_status", s);
             k_fill32<<<(uint32_t)std::min<uint64_t>(div_up(ntiles * kRadix + 1, 256), 65536), 256, 0, s>>>(

@@ -110,6 +110,56 @@ def test_duplicates_and_empty_sets():
     assert res["J"][3, 17] == 1.0 and res["J"][3, 5] == 0.0 and res["J"][5, 20] == 1.0
 
 
+def encode_timed(ids, off, U, **kw):
+    """Encode and Gram with the library's timers on; returns (result, stats, timer names)."""
+    cabi.jas_timing_report()
+    cabi.jas_timing_enable(True)
+    try:
+        res, st = gpu_all_pairs(ids, off, U, **kw)
+    finally:
+        names = set(cabi.jas_timing_report())
+        cabi.jas_timing_enable(False)
+    return res, st, names
+
+
+def csr(sets):
+    off = np.zeros(len(sets) + 1, np.uint64)
+    off[1:] = np.cumsum([s.size for s in sets])
+    return np.concatenate(sets).astype(np.uint64), off
+
+
+@pytest.mark.parametrize("case", ["uniform", "narrow_ids", "one_hot_id"])
+def test_bucket_ranges_and_fallback(case):
+    """Keys are sorted on their top ID bits only and each range of whole buckets is
+    finished in LDS; a bucket too large for LDS (IDs crowded into a narrow range, or
+    one ID repeated many times) must take the full sort and give the same result."""
+    rng = np.random.default_rng({"uniform": 1, "narrow_ids": 2, "one_hot_id": 3}[case])
+    if case == "uniform":
+        U, n = 36, 90
+        core = rng.integers(0, 1 << 36, 4000, dtype=np.uint64)
+        sets = [np.concatenate([rng.choice(core, int(rng.integers(0, 3000))),
+                                rng.integers(0, 1 << 36, int(rng.integers(0, 3000)), dtype=np.uint64)])
+                for _ in range(n)]
+    elif case == "narrow_ids":
+        U, n = 40, 60
+        sets = [rng.choice(1 << 12, int(rng.integers(500, 2500)), replace=False).astype(np.uint64)
+                for _ in range(n)]
+    else:
+        U, n = 32, 40
+        sets = [rng.integers(0, 1 << 32, 2000, dtype=np.uint64) for _ in range(n)]
+        sets[7] = np.concatenate([sets[7], np.full(20000, 12345, np.uint64)])
+        sets[9] = np.concatenate([sets[9], np.array([12345], np.uint64)])
+    ids, off = csr(sets)
+    ref = oracle.all_pairs(ids, off)
+    res, st, names = encode_timed(ids, off, U, dmin=0)
+    assert_matches(res, ref)
+    assert st["n_pairs"] == int(ref["card"].sum())
+    if case == "uniform":
+        assert "local_cls" in names and "host:classify_fallback" not in names
+    else:
+        assert "host:classify_fallback" in names and "cls_write" in names
+
+
 @pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 255, 257])
 @pytest.mark.parametrize("path", ["popcount", "mfma"])
 def test_tile_edges(n, path):
