@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
 // k_cls_count/k_cls_write.
 constexpr int kLNT = 512;
 constexpr int kLWaves = kLNT / kWave;
-constexpr uint32_t kLRounds = kLocalCapKeys / kLNT;  // 16 keys per thread
+constexpr uint32_t kLRounds = (kLocalCapKeys + kLNT - 1) / kLNT;  // keys per thread
 constexpr uint64_t kLStride = 4096;
 
 __device__ __forceinline__ uint64_t bucket_of(uint64_t key, uint32_t bsh) { return bsh >= 64 ? 0 : key >> bsh; }
@@ -344,12 +344,14 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
     unsigned long long *__restrict__ st) {
     __shared__ uint64_t A[kLocalCapKeys];
     __shared__ uint32_t wcnt[kLWaves][256];
+    __shared__ uint64_t T[kLWaves][256];  // per wave: lanes of the current round with digit d
     __shared__ uint32_t tdp[256];
     __shared__ uint64_t sh[kLWaves];
     __shared__ uint32_t wc[3][kLWaves];
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint64_t lt = lanemask_lt();
     const uint32_t c = blockIdx.x;
+    for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&T[0][0])[i] = 0;
     const uint64_t s0 = rs[c], s1 = rs[c + 1];
     const uint32_t L = (uint32_t)(s1 - s0);  // <= kLocalCapKeys (k_range_check)
     for (uint32_t i = tid; i < L; i += kLNT) A[i] = K[s0 + i];
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
         for (uint32_t p = 0; p < nb; p += 8) {
             for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&wcnt[0][0])[i] = 0;
             uint64_t key[kLRounds];
-            uint32_t dig[kLRounds], rank[kLRounds];
+            uint32_t dig[kLRounds], rank[kLRounds], info[kLRounds];
 #pragma unroll
             for (uint32_t j = 0; j < kLRounds; ++j) {
                 const uint32_t t = wb + j * kWave + lane;
@@ -375,25 +377,35 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
                 dig[j] = (uint32_t)((((key[j] >> sbits) - rbase) >> p)) & 255u;
             }
             __syncthreads();
+            // Rank within the wave: the lanes of a round with the same digit
+            // find each other through T[w][d] (each ORs in its lane bit, reads
+            // the set back, and clears it; one wave's LDS operations run in
+            // order), take consecutive slots after the digit's count so far,
+            // and the lowest of them adds the group to the count with one LDS
+            // atomic whose return its peers fetch later, so the rounds do not
+            // wait on each other.
 #pragma unroll
             for (uint32_t j = 0; j < kLRounds; ++j) {
                 if (j < rounds) {
                     const bool valid = wb + j * kWave + lane < L;
                     const uint32_t d = dig[j];
-                    uint64_t peers = __ballot(valid);
-#pragma unroll
-                    for (uint32_t b = 0; b < 8; ++b) {
-                        const bool bit = (d >> b) & 1u;
-                        const uint64_t vote = __ballot(bit);
-                        peers &= bit ? vote : ~vote;
+                    uint64_t peers = 0;
+                    if (valid) {
+                        atomicOr((unsigned long long *)&T[w][d], 1ull << lane);
+                        peers = __hip_atomic_load(&T[w][d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_store(&T[w][d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                     const uint32_t before = __popcll(peers & lt);
-                    uint32_t b0 = 0;
-                    if (valid) b0 = wcnt[w][d];
-                    if (valid && before == 0) wcnt[w][d] = b0 + __popcll(peers);
-                    rank[j] = b0 + before;
+                    const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : lane;
+                    uint32_t old = 0;
+                    if (valid && before == 0) old = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(peers));
+                    rank[j] = old;
+                    info[j] = (leader << 8) | before;
                 }
             }
+#pragma unroll
+            for (uint32_t j = 0; j < kLRounds; ++j)
+                if (j < rounds) rank[j] = (uint32_t)__shfl((int)rank[j], (int)(info[j] >> 8), kWave) + (info[j] & 255u);
             __syncthreads();
             uint32_t tc = 0;
             if (tid < 256)
@@ -685,6 +697,52 @@ __global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, con
         const uint64_t r = Lrow[j];
         const uint64_t a0 = row_ptr[r], d = row_ptr[r + 1] - a0, o = lptr[j];
         for (uint64_t k = 0; k < d; ++k) lsmp[o + k] = S[a0 + k];
+    }
+}
+
+// Row lists by sample (Gustavson's row-by-row form of B = A^T A over the row
+// lists): every list entry that is not the last of its row is filed under its
+// sample a with the range of the samples after it in the row.  A counting
+// sort: per-sample totals, a scan, then blocks of rows reserve a slice of each
+// sample's range with one global atomic per sample and fill it through LDS
+// cursors.
+__global__ __launch_bounds__(256) void k_by_count(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls,
+                                                   uint64_t QL, int32_t n, unsigned long long *__restrict__ cnt) {
+    extern __shared__ uint32_t h[];
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < QL; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e0 = lp[r], e1 = lp[r + 1];
+        for (uint64_t e = e0; e + 1 < e1; ++e) atomicAdd(&h[ls[e]], 1u);
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+        if (h[i]) atomicAdd(&cnt[i], (unsigned long long)h[i]);
+}
+
+__global__ __launch_bounds__(256) void k_by_fill(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls,
+                                                  uint64_t QL, uint64_t rows_per_block, int32_t n,
+                                                  unsigned long long *__restrict__ cursor,
+                                                  uint64_t *__restrict__ by_smp) {
+    extern __shared__ uint32_t h[];  // counts, then slice cursors (positions < 2^32)
+    const uint64_t r0 = (uint64_t)blockIdx.x * rows_per_block;
+    const uint64_t r1 = min(QL, r0 + rows_per_block);
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const uint64_t e0 = lp[r], e1 = lp[r + 1];
+        for (uint64_t e = e0; e + 1 < e1; ++e) atomicAdd(&h[ls[e]], 1u);
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+        if (h[i]) h[i] = (uint32_t)atomicAdd(&cursor[i], (unsigned long long)h[i]);
+    __syncthreads();
+    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const uint64_t e0 = lp[r], e1 = lp[r + 1];
+        for (uint64_t e = e0; e + 1 < e1; ++e) {
+            const uint32_t pos = atomicAdd(&h[ls[e]], 1u);
+            by_smp[pos] = (e + 1) | (e1 << 32);
+        }
     }
 }
 
@@ -1045,6 +1103,36 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             }
         });
         check_launch("list gather");
+        // by-sample index (its positions are 32-bit)
+        if (n <= kSampleMajorMaxN && db->list_nnz < (uint64_t(1) << 32)) {
+            DevBuf<unsigned long long> bc;
+            DevBuf<uint64_t> tmp2;
+            bc.alloc(n, s, tb, true, "per-sample list counts");
+            {
+                JAS_TIMED("fill_u64", s);
+                k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)bc.p, n, 0);
+            }
+            const size_t lds = (size_t)n * sizeof(uint32_t);
+            {
+                JAS_TIMED("by_count", s);
+                k_by_count<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 2048), 256, lds, s>>>(
+                    db->list_ptr.p, db->list_smp.p, QL, n, bc.p);
+            }
+            check_launch("by-sample counts");
+            db->by_start.alloc(n + 1, s, &db->budget, false, "by-sample starts");
+            tmp2.alloc(scan_tmp_elems(n), s, tb, true, "scan scratch");
+            scan_excl_u64((const uint64_t *)bc.p, db->by_start.p, n, tmp2.p, s);
+            db->n_by = to_host_u64(db->by_start.p + n, s);
+            db->by_smp.alloc(std::max<uint64_t>(db->n_by, 1), s, &db->budget, false, "by-sample lists");
+            JAS_HIP(hipMemcpyAsync(bc.p, db->by_start.p, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+            const uint64_t rpb = std::max<uint64_t>(4096, div_up(QL, 2048));
+            {
+                JAS_TIMED("by_fill", s);
+                k_by_fill<<<(uint32_t)div_up(QL, rpb), 256, lds, s>>>(db->list_ptr.p, db->list_smp.p, QL, rpb, n,
+                                                                      bc.p, db->by_smp.p);
+            }
+            check_launch("by-sample fill");
+        }
     } else {
         {
             JAS_TIMED("fill_u64", s);

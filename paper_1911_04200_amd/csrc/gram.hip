@@ -265,6 +265,61 @@ __global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__
     }
 }
 
+// Row lists by sample: block g takes by-sample entries [g*kByChunk, ...); for
+// each sample a in that range it counts, in an LDS row cnt[b], the rows that
+// hold both a and b > a, then adds the touched counters to row a of B (one
+// atomic per touched pair instead of one per row and pair).
+constexpr uint64_t kByChunk = 8192;
+
+__global__ __launch_bounds__(256) void k_list_by_sample(const uint64_t *__restrict__ by_start,
+                                                         const uint64_t *__restrict__ by_smp, uint64_t T,
+                                                         const uint32_t *__restrict__ ls, uint32_t n,
+                                                         int32_t *__restrict__ B, int upper) {
+    extern __shared__ uint32_t lds[];
+    uint32_t *cnt = lds;                                     // n counters
+    uint16_t *touched = reinterpret_cast<uint16_t *>(lds + n);  // n entries (n <= 65535)
+    __shared__ uint32_t ntouched;
+    const uint64_t lo = (uint64_t)blockIdx.x * kByChunk, hi = min(T, lo + kByChunk);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
+    // first sample with by_start[a+1] > lo
+    uint32_t a;
+    {
+        uint32_t l = 0, h = n - 1;  // largest a with by_start[a] <= lo
+        while (l < h) {
+            const uint32_t m = (l + h + 1) >> 1;
+            if (by_start[m] <= lo) l = m;
+            else h = m - 1;
+        }
+        a = l;
+    }
+    if (threadIdx.x == 0) ntouched = 0;
+    __syncthreads();
+    for (; a < n; ++a) {
+        const uint64_t s0 = max(lo, by_start[a]), s1 = min(hi, by_start[a + 1]);
+        if (by_start[a] >= hi) break;
+        if (s0 < s1) {
+            for (uint64_t p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
+                const uint64_t v = by_smp[p];
+                const uint32_t e1 = (uint32_t)v, e2 = (uint32_t)(v >> 32);
+                for (uint32_t e = e1; e < e2; ++e) {
+                    const uint32_t b = ls[e];
+                    if (atomicAdd(&cnt[b], 1u) == 0) touched[atomicAdd(&ntouched, 1u)] = (uint16_t)b;
+                }
+            }
+            __syncthreads();
+            const uint32_t nt = ntouched;
+            for (uint32_t k = threadIdx.x; k < nt; k += blockDim.x) {
+                const uint32_t b = touched[k];
+                atomicAdd(B + out_index(a, b, n, upper), (int32_t)cnt[b]);
+                cnt[b] = 0;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) ntouched = 0;
+            __syncthreads();
+        }
+    }
+}
+
 // Diagonal, mirror (full layout), unions and J.
 __global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ card, uint32_t n, int upper,
                            uint32_t jblocks, int64_t *__restrict__ den, double *__restrict__ J) {
@@ -329,7 +384,17 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         }
         check_launch("gram");
     }
-    if (db->n_list > 0) {
+    if (db->n_list > 0 && db->by_start.p) {
+        if (db->n_by > 0) {
+            const uint64_t blocks = div_up(db->n_by, kByChunk);
+            if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "row lists too long");
+            const size_t lds = (size_t)n * (sizeof(uint32_t) + sizeof(uint16_t));
+            JAS_TIMED("list_by_sample", s);
+            k_list_by_sample<<<(uint32_t)blocks, 256, lds, s>>>(db->by_start.p, db->by_smp.p, db->n_by,
+                                                                db->list_smp.p, n, B, upper);
+        }
+        check_launch("row lists by sample");
+    } else if (db->n_list > 0) {
         const uint64_t blocks = std::min<uint64_t>(div_up(db->n_list, 256), 65536);
         {
             JAS_TIMED("list_pairs", s);

@@ -139,6 +139,12 @@ struct jas_db {
     uint64_t n_list = 0, list_nnz = 0;
     jas::DevBuf<uint64_t> list_ptr;   // n_list + 1
     jas::DevBuf<uint32_t> list_smp;   // list_nnz
+    // the same lists by sample (built when n <= kSampleMajorMaxN): for sample a,
+    // entries by_smp[by_start[a] .. by_start[a+1]) are (first, end) list_smp
+    // positions (low, high 32 bits) of the samples after a in one row containing a
+    uint64_t n_by = 0;
+    jas::DevBuf<uint64_t> by_start;   // n + 1
+    jas::DevBuf<uint64_t> by_smp;     // n_by
     // query index (JAS_KEEP_IDS): distinct keys (id << sbits | sample) in ascending
     // order and a table of their start by the top `ibits` bits of the ID.
     uint64_t n_keys = 0;
@@ -190,8 +196,9 @@ uint64_t radix_work_bytes(uint64_t N);
 struct SortPlan {
     uint32_t top_bits = 0, npass = 0, width = 8;
 };
-constexpr uint64_t kBucketKeys = 1024;
-constexpr uint32_t kLocalCapKeys = 8192;  // keys one LDS range can hold
+constexpr uint64_t kBucketKeys = 512;
+constexpr int32_t kSampleMajorMaxN = 10240;  // LDS row of per-sample counters (6 bytes each)
+constexpr uint32_t kLocalCapKeys = 6912;  // keys one LDS range can hold
 SortPlan sort_plan(uint64_t N, uint32_t U);
 
 // Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;

@@ -160,6 +160,23 @@ def test_bucket_ranges_and_fallback(case):
         assert "host:classify_fallback" in names and "cls_write" in names
 
 
+@pytest.mark.parametrize("n,dmin", [(300, 1000), (10300, 0)])
+def test_row_lists_by_sample_and_by_row(n, dmin):
+    """Rows kept as lists are summed sample by sample (an LDS row of counters per
+    sample, up to 10240 samples) or, for more samples, pair by pair per row."""
+    rng = np.random.default_rng(n)
+    pool = rng.choice(1 << 20, 3000, replace=False).astype(np.uint64)
+    sets = [np.unique(rng.choice(pool, int(rng.integers(0, 7)))) for _ in range(n)]
+    sets[5] = pool[:40].copy()  # one sample in many rows
+    ids, off = csr(sets)
+    ref = oracle.all_pairs(ids, off)
+    res, st = gpu_all_pairs(ids, off, 20, 0, dmin)
+    assert st["n_list_rows"] > 0
+    assert_matches(res, ref)
+    res, _ = gpu_all_pairs(ids, off, 20, 0, dmin, upper=True)
+    assert_matches(res, ref, upper=True)
+
+
 @pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 255, 257])
 @pytest.mark.parametrize("path", ["popcount", "mfma"])
 def test_tile_edges(n, path):
