@@ -153,6 +153,7 @@ constexpr uint32_t kFlagA = 1u << 30;  // the tile's own count is available
 constexpr uint32_t kFlagP = 2u << 30;  // the inclusive prefix over tiles 0..t is available
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr uint32_t kMaxSpin = 1u << 20;  // bounded wait (~0.1 s of polls), then give up and flag
+constexpr int kLookWindow = 8;           // predecessor tiles read per look-back step
 
 __device__ __forceinline__ void status_store(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -161,7 +162,7 @@ __device__ __forceinline__ uint32_t status_load(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kNT) void k_radix_onesweep(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                          uint64_t N, uint32_t shift, uint32_t nbits,
                                                          const uint64_t *__restrict__ gstart,
                                                          uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
@@ -220,33 +221,10 @@ __global__ __launch_bounds__(kNT) void k_radix_onesweep(const uint64_t *__restri
             c[k] = wcnt[k][tid];
             tc += c[k];
         }
-        // thread tid = digit: publish, look back, publish the inclusive prefix
+        // thread tid = digit: publish the tile's count at once
         uint32_t *st = status + (uint64_t)tile * kRadix + tid;
-        uint32_t excl = 0;
-        if (tile == 0) {
-            status_store(st, kFlagP | tc);
-        } else {
-            status_store(st, kFlagA | tc);
-            for (int64_t j = (int64_t)tile - 1; j >= 0; --j) {
-                const uint32_t *pj = status + (uint64_t)j * kRadix + tid;
-                uint32_t v = status_load(pj);
-                uint32_t spins = 0;
-                while ((v & ~kValMask) == 0) {
-                    // give up after kMaxSpin polls, or at once when any tile has given up
-                    if (++spins > kMaxSpin || (status_load(err) & 2u)) {
-                        atomicOr(err, 2u);
-                        v = kFlagP;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    v = status_load(pj);
-                }
-                excl += v & kValMask;
-                if ((v & ~kValMask) == kFlagP) break;
-            }
-            status_store(st, kFlagP | ((excl + tc) & kValMask));
-        }
-        base[tid] = gs + excl;
+        status_store(st, (tile == 0 ? kFlagP : kFlagA) | tc);
+        // reorder the tile in LDS by digit (local offsets only)
         uint64_t tot;
         const uint32_t ex = (uint32_t)block_excl_scan<kNT>(tc, sh, &tot);
         tdp[tid] = ex;
@@ -265,6 +243,38 @@ __global__ __launch_bounds__(kNT) void k_radix_onesweep(const uint64_t *__restri
                 stage[tdp[d] + wcnt[w][d] + rank[j]] = key[j];
             }
         }
+        // then look back for the digit's global offset: kLookWindow
+        // predecessor tiles per step, loaded together (one memory round trip)
+        // and taken nearest first
+        uint32_t excl = 0;
+        if (tile > 0) {
+            bool found = false;
+            for (int64_t j0 = (int64_t)tile - 1; j0 >= 0 && !found; j0 -= kLookWindow) {
+                uint32_t v[kLookWindow];
+#pragma unroll
+                for (int k = 0; k < kLookWindow; ++k)
+                    v[k] = j0 - k >= 0 ? status_load(status + (uint64_t)(j0 - k) * kRadix + tid) : kFlagP;
+#pragma unroll
+                for (int k = 0; k < kLookWindow; ++k) {
+                    if (found) break;
+                    uint32_t spins = 0;
+                    while ((v[k] & ~kValMask) == 0) {
+                        // give up after kMaxSpin polls, or at once when any tile has given up
+                        if (++spins > kMaxSpin || (status_load(err) & 2u)) {
+                            atomicOr(err, 2u);
+                            v[k] = kFlagP;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        v[k] = status_load(status + (uint64_t)(j0 - k) * kRadix + tid);
+                    }
+                    excl += v[k] & kValMask;
+                    found = (v[k] & ~kValMask) == kFlagP;
+                }
+            }
+            status_store(st, kFlagP | ((excl + tc) & kValMask));
+        }
+        base[tid] = gs + excl;
         __syncthreads();
         const uint32_t cnt_tile = (uint32_t)(c1 - t0);
         for (uint32_t i = tid; i < cnt_tile; i += kNT) {
