@@ -162,32 +162,36 @@ __device__ __forceinline__ uint32_t status_load(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
-                                                         uint64_t N, uint32_t shift, uint32_t nbits,
-                                                         const uint64_t *__restrict__ gstart,
-                                                         uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
-                                                         uint32_t ntiles, uint32_t *__restrict__ err) {
-    __shared__ uint64_t stage[kTile];
-    __shared__ uint32_t wcnt[kWaves][kRadix];
+// One tile = kOsNT threads x kRounds keys; threads tid < kRadix also own digit tid.
+constexpr int kOsNT = 512;
+constexpr int kOsWaves = kOsNT / kWave;
+constexpr uint32_t kOsTile = kOsNT * kRounds;  // 8192 keys
+
+__global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(
+    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t N, uint32_t shift, uint32_t nbits,
+    const uint64_t *__restrict__ gstart, uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
+    uint32_t ntiles, uint32_t *__restrict__ err) {
+    __shared__ uint64_t stage[kOsTile];
+    __shared__ uint32_t wcnt[kOsWaves][kRadix];
     __shared__ uint32_t tdp[kRadix];
     __shared__ uint64_t base[kRadix];
-    __shared__ uint64_t sh[kWaves];
+    __shared__ uint64_t sh[kOsWaves];
     __shared__ uint32_t tile_sh;
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const bool digit = tid < kRadix;  // this thread owns digit tid
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t lt = lanemask_lt();
-    const uint64_t gs = gstart[tid];
+    const uint64_t gs = digit ? gstart[tid] : 0;
     // persistent: take tiles in ticket order until none is left
     for (;;) {
         if (tid == 0) tile_sh = atomicAdd(ticket, 1u);
-#pragma unroll
-        for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
+        for (uint32_t i = tid; i < kOsWaves * kRadix; i += kOsNT) (&wcnt[0][0])[i] = 0;
         __syncthreads();
         const uint32_t tile = tile_sh;
         if (tile >= ntiles) break;  // uniform: every thread read the same ticket
-        const uint64_t t0 = (uint64_t)tile * kTile;
-        const uint64_t c1 = min(N, t0 + kTile);
-        const uint64_t wb = t0 + (uint64_t)w * (kTile / kWaves);
+        const uint64_t t0 = (uint64_t)tile * kOsTile;
+        const uint64_t c1 = min(N, t0 + kOsTile);
+        const uint64_t wb = t0 + (uint64_t)w * (kOsTile / kOsWaves);
         uint64_t key[kRounds];
         uint32_t rank[kRounds];
 #pragma unroll
@@ -214,25 +218,25 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k
             rank[j] = b0 + before;
         }
         __syncthreads();
-        uint32_t c[kWaves];
         uint32_t tc = 0;
+        if (digit) {
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
-            c[k] = wcnt[k][tid];
-            tc += c[k];
+            for (int k = 0; k < kOsWaves; ++k) tc += wcnt[k][tid];
+            // publish the tile's count of digit tid at once
+            status_store(status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagP : kFlagA) | tc);
         }
-        // thread tid = digit: publish the tile's count at once
-        uint32_t *st = status + (uint64_t)tile * kRadix + tid;
-        status_store(st, (tile == 0 ? kFlagP : kFlagA) | tc);
         // reorder the tile in LDS by digit (local offsets only)
         uint64_t tot;
-        const uint32_t ex = (uint32_t)block_excl_scan<kNT>(tc, sh, &tot);
-        tdp[tid] = ex;
-        uint32_t run = 0;
+        const uint32_t ex = (uint32_t)block_excl_scan<kOsNT>(tc, sh, &tot);
+        if (digit) {
+            tdp[tid] = ex;
+            uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
-            wcnt[k][tid] = run;
-            run += c[k];
+            for (int k = 0; k < kOsWaves; ++k) {
+                const uint32_t v = wcnt[k][tid];
+                wcnt[k][tid] = run;
+                run += v;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -246,38 +250,40 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k
         // then look back for the digit's global offset: kLookWindow
         // predecessor tiles per step, loaded together (one memory round trip)
         // and taken nearest first
-        uint32_t excl = 0;
-        if (tile > 0) {
-            bool found = false;
-            for (int64_t j0 = (int64_t)tile - 1; j0 >= 0 && !found; j0 -= kLookWindow) {
-                uint32_t v[kLookWindow];
+        if (digit) {
+            uint32_t excl = 0;
+            if (tile > 0) {
+                bool found = false;
+                for (int64_t j0 = (int64_t)tile - 1; j0 >= 0 && !found; j0 -= kLookWindow) {
+                    uint32_t v[kLookWindow];
 #pragma unroll
-                for (int k = 0; k < kLookWindow; ++k)
-                    v[k] = j0 - k >= 0 ? status_load(status + (uint64_t)(j0 - k) * kRadix + tid) : kFlagP;
+                    for (int k = 0; k < kLookWindow; ++k)
+                        v[k] = j0 - k >= 0 ? status_load(status + (uint64_t)(j0 - k) * kRadix + tid) : kFlagP;
 #pragma unroll
-                for (int k = 0; k < kLookWindow; ++k) {
-                    if (found) break;
-                    uint32_t spins = 0;
-                    while ((v[k] & ~kValMask) == 0) {
-                        // give up after kMaxSpin polls, or at once when any tile has given up
-                        if (++spins > kMaxSpin || (status_load(err) & 2u)) {
-                            atomicOr(err, 2u);
-                            v[k] = kFlagP;
-                            break;
+                    for (int k = 0; k < kLookWindow; ++k) {
+                        if (found) break;
+                        uint32_t spins = 0;
+                        while ((v[k] & ~kValMask) == 0) {
+                            // give up after kMaxSpin polls, or at once when any tile has given up
+                            if (++spins > kMaxSpin || (status_load(err) & 2u)) {
+                                atomicOr(err, 2u);
+                                v[k] = kFlagP;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                            v[k] = status_load(status + (uint64_t)(j0 - k) * kRadix + tid);
                         }
-                        __builtin_amdgcn_s_sleep(1);
-                        v[k] = status_load(status + (uint64_t)(j0 - k) * kRadix + tid);
+                        excl += v[k] & kValMask;
+                        found = (v[k] & ~kValMask) == kFlagP;
                     }
-                    excl += v[k] & kValMask;
-                    found = (v[k] & ~kValMask) == kFlagP;
                 }
+                status_store(status + (uint64_t)tile * kRadix + tid, kFlagP | ((excl + tc) & kValMask));
             }
-            status_store(st, kFlagP | ((excl + tc) & kValMask));
+            base[tid] = gs + excl;
         }
-        base[tid] = gs + excl;
         __syncthreads();
         const uint32_t cnt_tile = (uint32_t)(c1 - t0);
-        for (uint32_t i = tid; i < cnt_tile; i += kNT) {
+        for (uint32_t i = tid; i < cnt_tile; i += kOsNT) {
             const uint64_t k = stage[i];
             const uint32_t d = (uint32_t)(k >> shift) & mask;
             out[base[d] + (i - tdp[d])] = k;
@@ -390,10 +396,10 @@ bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t
     JAS_HIP(hipStreamSynchronize(s));
     for (uint32_t q = 0; q < npass; ++q)
         if (hm[q] >= (uint64_t)kValMask) return false;
-    const uint64_t ntiles = div_up(N, kTile);
+    const uint64_t ntiles = div_up(N, kOsTile);
     if (ntiles > 0xFFFFFFFFull) return false;
-    // persistent blocks: a few per CU (256 CUs), never more than there are tiles
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 8);
+    // persistent blocks: two per CU (256 CUs) fit, never more than there are tiles
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 2);
     DevBuf<uint32_t> status, ticket;
     status.alloc(ntiles * kRadix + 1, s, b, true, "look-back status");
     ticket.alloc(1, s, b, true, "tile ticket");
@@ -409,7 +415,7 @@ bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t
         check_launch("look-back reset");
         {
             JAS_TIMED("radix_onesweep", s);
-            k_radix_onesweep<<<grid, kNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
+            k_radix_onesweep<<<grid, kOsNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
                                                   ticket.p, (uint32_t)ntiles, err);
         }
         check_launch("radix scatter (look-back)");
