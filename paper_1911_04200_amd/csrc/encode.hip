@@ -700,50 +700,44 @@ __global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, con
     }
 }
 
-// Row lists by sample (Gustavson's row-by-row form of B = A^T A over the row
-// lists): every list entry that is not the last of its row is filed under its
-// sample a with the range of the samples after it in the row.  A counting
-// sort: per-sample totals, a scan, then blocks of rows reserve a slice of each
-// sample's range with one global atomic per sample and fill it through LDS
-// cursors.
-__global__ __launch_bounds__(256) void k_by_count(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls,
-                                                   uint64_t QL, int32_t n, unsigned long long *__restrict__ cnt) {
-    extern __shared__ uint32_t h[];
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) h[i] = 0;
-    __syncthreads();
+// Row lists as pairs for the Gram step: every pair (a, b), a < b, of every
+// list row as the 32-bit word (a << 16) | b, then sorted by a (single-pass
+// scatters over the bits of a), so that the Gram step reads each sample's
+// pairs as one contiguous run (the row-by-row form of B = A^T A over the row
+// lists).
+__global__ void k_list_npairs(const uint64_t *lp, uint64_t QL, uint64_t *np) {
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < QL; r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t e0 = lp[r], e1 = lp[r + 1];
-        for (uint64_t e = e0; e + 1 < e1; ++e) atomicAdd(&h[ls[e]], 1u);
+        const uint64_t d = lp[r + 1] - lp[r];
+        np[r] = d * (d - 1) / 2;
     }
-    __syncthreads();
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
-        if (h[i]) atomicAdd(&cnt[i], (unsigned long long)h[i]);
 }
 
-__global__ __launch_bounds__(256) void k_by_fill(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls,
-                                                  uint64_t QL, uint64_t rows_per_block, int32_t n,
-                                                  unsigned long long *__restrict__ cursor,
-                                                  uint64_t *__restrict__ by_smp) {
-    extern __shared__ uint32_t h[];  // counts, then slice cursors (positions < 2^32)
-    const uint64_t r0 = (uint64_t)blockIdx.x * rows_per_block;
-    const uint64_t r1 = min(QL, r0 + rows_per_block);
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) h[i] = 0;
+// One thread per row writes its pairs at po[r]; per-block LDS totals of the
+// sort digits of a (digit q = bits [16 + width*q, 16 + width*(q+1)) of the word).
+__global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls,
+                                                    uint64_t QL, const uint64_t *__restrict__ po,
+                                                    uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
+                                                    unsigned long long *__restrict__ ghist) {
+    __shared__ uint32_t gh[kMaxPasses][256];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t dmask = (1u << width) - 1u;
+#pragma unroll
+    for (int k = 0; k < kMaxPasses; ++k) gh[k][tid] = 0;
     __syncthreads();
-    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + tid; r < QL; r += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t e0 = lp[r], e1 = lp[r + 1];
-        for (uint64_t e = e0; e + 1 < e1; ++e) atomicAdd(&h[ls[e]], 1u);
-    }
-    __syncthreads();
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
-        if (h[i]) h[i] = (uint32_t)atomicAdd(&cursor[i], (unsigned long long)h[i]);
-    __syncthreads();
-    for (uint64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const uint64_t e0 = lp[r], e1 = lp[r + 1];
-        for (uint64_t e = e0; e + 1 < e1; ++e) {
-            const uint32_t pos = atomicAdd(&h[ls[e]], 1u);
-            by_smp[pos] = (e + 1) | (e1 << 32);
+        uint64_t o = po[r];
+        for (uint64_t i = e0; i + 1 < e1; ++i) {
+            const uint32_t a = ls[i];
+            const uint32_t m = (uint32_t)(e1 - i - 1);  // pairs with a as the smaller sample
+            for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(a >> (width * q)) & dmask], m);
+            for (uint64_t j = i + 1; j < e1; ++j) pairs[o++] = (a << 16) | ls[j];
         }
     }
+    __syncthreads();
+    unsigned long long *g = ghist + (uint64_t)(blockIdx.x % kGhistReplicas) * kMaxPasses * 256;
+    for (uint32_t q = 0; q < npass; ++q)
+        if (gh[q][tid]) atomicAdd(&g[q * 256 + tid], (unsigned long long)gh[q][tid]);
 }
 
 // Query index: bucket[b] = first distinct key whose ID has top bits >= b.
@@ -1103,35 +1097,51 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             }
         });
         check_launch("list gather");
-        // by-sample index (its positions are 32-bit)
-        if (n <= kSampleMajorMaxN && db->list_nnz < (uint64_t(1) << 32)) {
-            DevBuf<unsigned long long> bc;
-            DevBuf<uint64_t> tmp2;
-            bc.alloc(n, s, tb, true, "per-sample list counts");
+        // the rows' pairs, sorted by their smaller sample
+        if (n <= kSampleMajorMaxN) {
+            DevBuf<uint64_t> np, npo, tmp2;
+            np.alloc(QL, s, tb, true, "row pair counts");
+            launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
+                {
+                    JAS_TIMED("list_npairs", st_);
+                    k_list_npairs<<<b, 256, 0, st_>>>(db->list_ptr.p, QL, np.p);
+                }
+            });
+            check_launch("row pair counts");
+            npo.alloc(QL + 1, s, tb, true, "row pair offsets");
+            tmp2.alloc(scan_tmp_elems(QL), s, tb, true, "scan scratch");
+            scan_excl_u64(np.p, npo.p, QL, tmp2.p, s);
+            const uint64_t P = to_host_u64(npo.p + QL, s);
+            np.release();
+            tmp2.release();
+            const uint32_t sb = std::max<uint32_t>(1, ceil_log2_u64((uint64_t)n));
+            const uint32_t npass = (sb + 7) / 8, width = (sb + npass - 1) / npass;
+            DevBuf<uint32_t> pk, palt, perr;
+            DevBuf<unsigned long long> gh;
+            pk.alloc(P + 2, s, &db->budget, false, "row-list pairs");
+            palt.alloc(P + 2, s, tb, true, "row-list pairs (second buffer)");
+            gh.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, tb, true, "pair digit totals");
+            perr.alloc(2, s, tb, true, "pair sort flag");
             {
                 JAS_TIMED("fill_u64", s);
-                k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)bc.p, n, 0);
+                k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)gh.p, (uint64_t)kGhistReplicas * kMaxPasses * 256, 0);
+                k_fill_u64<<<1, 64, 0, s>>>((uint64_t *)perr.p, 1, 0);
             }
-            const size_t lds = (size_t)n * sizeof(uint32_t);
             {
-                JAS_TIMED("by_count", s);
-                k_by_count<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 2048), 256, lds, s>>>(
-                    db->list_ptr.p, db->list_smp.p, QL, n, bc.p);
+                JAS_TIMED("pair_emit", s);
+                k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 4096), 256, 0, s>>>(
+                    db->list_ptr.p, db->list_smp.p, QL, npo.p, pk.p, npass, width, gh.p);
             }
-            check_launch("by-sample counts");
-            db->by_start.alloc(n + 1, s, &db->budget, false, "by-sample starts");
-            tmp2.alloc(scan_tmp_elems(n), s, tb, true, "scan scratch");
-            scan_excl_u64((const uint64_t *)bc.p, db->by_start.p, n, tmp2.p, s);
-            db->n_by = to_host_u64(db->by_start.p + n, s);
-            db->by_smp.alloc(std::max<uint64_t>(db->n_by, 1), s, &db->budget, false, "by-sample lists");
-            JAS_HIP(hipMemcpyAsync(bc.p, db->by_start.p, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
-            const uint64_t rpb = std::max<uint64_t>(4096, div_up(QL, 2048));
-            {
-                JAS_TIMED("by_fill", s);
-                k_by_fill<<<(uint32_t)div_up(QL, rpb), 256, lds, s>>>(db->list_ptr.p, db->list_smp.p, QL, rpb, n,
-                                                                      bc.p, db->by_smp.p);
+            check_launch("pair emit");
+            bool ok = radix_sort_onesweep_u32(pk, palt, P, 16, 16 + sb, width, gh.p, perr.p, s, tb);
+            uint32_t herr = 0;
+            JAS_HIP(hipMemcpyAsync(&herr, perr.p, 4, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipStreamSynchronize(s));
+            if (ok && herr == 0) {
+                db->n_lpairs = P;
+                db->pairs = std::move(pk);
             }
-            check_launch("by-sample fill");
+            // else: the Gram step adds the rows pair by pair (k_list_pairs)
         }
     } else {
         {

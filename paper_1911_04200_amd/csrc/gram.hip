@@ -265,58 +265,52 @@ __global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__
     }
 }
 
-// Row lists by sample: block g takes by-sample entries [g*kByChunk, ...); for
-// each sample a in that range it counts, in an LDS row cnt[b], the rows that
-// hold both a and b > a, then adds the touched counters to row a of B (one
-// atomic per touched pair instead of one per row and pair).
-constexpr uint64_t kByChunk = 8192;
+// Row-list pairs sorted by their smaller sample a: block g takes pairs
+// [g*kPairChunk, ...); for each run of one a in it, an LDS row cnt[b] counts the
+// rows holding both a and b, and each touched counter is added to row a of B
+// once (one atomic per touched pair instead of one per row and pair).
+constexpr uint64_t kPairChunk = 16384;
 
-__global__ __launch_bounds__(256) void k_list_by_sample(const uint64_t *__restrict__ by_start,
-                                                         const uint64_t *__restrict__ by_smp, uint64_t T,
-                                                         const uint32_t *__restrict__ ls, uint32_t n,
-                                                         int32_t *__restrict__ B, int upper) {
+__global__ __launch_bounds__(256) void k_pair_count(const uint32_t *__restrict__ pairs, uint64_t P, uint32_t n,
+                                                     int32_t *__restrict__ B, int upper) {
     extern __shared__ uint32_t lds[];
-    uint32_t *cnt = lds;                                     // n counters
-    uint16_t *touched = reinterpret_cast<uint16_t *>(lds + n);  // n entries (n <= 65535)
+    uint32_t *cnt = lds;                                         // n counters
+    uint16_t *touched = reinterpret_cast<uint16_t *>(lds + n);  // n entries (n < 2^16)
     __shared__ uint32_t ntouched;
-    const uint64_t lo = (uint64_t)blockIdx.x * kByChunk, hi = min(T, lo + kByChunk);
+    __shared__ uint64_t seg_end;
+    const uint64_t lo = (uint64_t)blockIdx.x * kPairChunk, hi = min(P, lo + kPairChunk);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
-    // first sample with by_start[a+1] > lo
-    uint32_t a;
-    {
-        uint32_t l = 0, h = n - 1;  // largest a with by_start[a] <= lo
-        while (l < h) {
-            const uint32_t m = (l + h + 1) >> 1;
-            if (by_start[m] <= lo) l = m;
-            else h = m - 1;
-        }
-        a = l;
-    }
     if (threadIdx.x == 0) ntouched = 0;
     __syncthreads();
-    for (; a < n; ++a) {
-        const uint64_t s0 = max(lo, by_start[a]), s1 = min(hi, by_start[a + 1]);
-        if (by_start[a] >= hi) break;
-        if (s0 < s1) {
-            for (uint64_t p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
-                const uint64_t v = by_smp[p];
-                const uint32_t e1 = (uint32_t)v, e2 = (uint32_t)(v >> 32);
-                for (uint32_t e = e1; e < e2; ++e) {
-                    const uint32_t b = ls[e];
-                    if (atomicAdd(&cnt[b], 1u) == 0) touched[atomicAdd(&ntouched, 1u)] = (uint16_t)b;
-                }
+    for (uint64_t s0 = lo; s0 < hi;) {
+        const uint32_t a = pairs[s0] >> 16;
+        // end of the run of a inside the chunk (the chunk is sorted by a)
+        if (threadIdx.x == 0) {
+            uint64_t l = s0, h = hi;  // first position in [s0, hi) whose sample exceeds a
+            while (l < h) {
+                const uint64_t m = (l + h) >> 1;
+                if ((pairs[m] >> 16) <= a) l = m + 1;
+                else h = m;
             }
-            __syncthreads();
-            const uint32_t nt = ntouched;
-            for (uint32_t k = threadIdx.x; k < nt; k += blockDim.x) {
-                const uint32_t b = touched[k];
-                atomicAdd(B + out_index(a, b, n, upper), (int32_t)cnt[b]);
-                cnt[b] = 0;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) ntouched = 0;
-            __syncthreads();
+            seg_end = l;
         }
+        __syncthreads();
+        const uint64_t s1 = seg_end;
+        for (uint64_t p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
+            const uint32_t b = pairs[p] & 0xFFFFu;
+            if (atomicAdd(&cnt[b], 1u) == 0) touched[atomicAdd(&ntouched, 1u)] = (uint16_t)b;
+        }
+        __syncthreads();
+        const uint32_t nt = ntouched;
+        for (uint32_t k = threadIdx.x; k < nt; k += blockDim.x) {
+            const uint32_t b = touched[k];
+            atomicAdd(B + out_index(a, b, n, upper), (int32_t)cnt[b]);
+            cnt[b] = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) ntouched = 0;
+        s0 = s1;
+        __syncthreads();
     }
 }
 
@@ -384,16 +378,15 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         }
         check_launch("gram");
     }
-    if (db->n_list > 0 && db->by_start.p) {
-        if (db->n_by > 0) {
-            const uint64_t blocks = div_up(db->n_by, kByChunk);
-            if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "row lists too long");
-            const size_t lds = (size_t)n * (sizeof(uint32_t) + sizeof(uint16_t));
-            JAS_TIMED("list_by_sample", s);
-            k_list_by_sample<<<(uint32_t)blocks, 256, lds, s>>>(db->by_start.p, db->by_smp.p, db->n_by,
-                                                                db->list_smp.p, n, B, upper);
+    if (db->n_list > 0 && db->n_lpairs > 0) {
+        const uint64_t blocks = div_up(db->n_lpairs, kPairChunk);
+        if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "row lists too long");
+        const size_t lds = (size_t)n * (sizeof(uint32_t) + sizeof(uint16_t));
+        {
+            JAS_TIMED("pair_count", s);
+            k_pair_count<<<(uint32_t)blocks, 256, lds, s>>>(db->pairs.p, db->n_lpairs, n, B, upper);
         }
-        check_launch("row lists by sample");
+        check_launch("row-list pairs");
     } else if (db->n_list > 0) {
         const uint64_t blocks = std::min<uint64_t>(div_up(db->n_list, 256), 65536);
         {

@@ -139,12 +139,10 @@ struct jas_db {
     uint64_t n_list = 0, list_nnz = 0;
     jas::DevBuf<uint64_t> list_ptr;   // n_list + 1
     jas::DevBuf<uint32_t> list_smp;   // list_nnz
-    // the same lists by sample (built when n <= kSampleMajorMaxN): for sample a,
-    // entries by_smp[by_start[a] .. by_start[a+1]) are (first, end) list_smp
-    // positions (low, high 32 bits) of the samples after a in one row containing a
-    uint64_t n_by = 0;
-    jas::DevBuf<uint64_t> by_start;   // n + 1
-    jas::DevBuf<uint64_t> by_smp;     // n_by
+    // the rows' pairs (a << 16) | b, a < b, sorted by a (built when
+    // n <= kSampleMajorMaxN; else n_pairs = 0 and the Gram step walks the rows)
+    uint64_t n_lpairs = 0;
+    jas::DevBuf<uint32_t> pairs;
     // query index (JAS_KEEP_IDS): distinct keys (id << sbits | sample) in ascending
     // order and a table of their start by the top `ibits` bits of the ID.
     uint64_t n_keys = 0;
@@ -184,6 +182,9 @@ constexpr uint32_t kGhistReplicas = 32;
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
                          uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
                          hipStream_t s, Budget *b);
+bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,
+                             uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
+                             hipStream_t s, Budget *b);
 // Allocates w for N keys; returns the number of chunks (counts is [256][chunks]).
 uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b);
 uint64_t radix_work_bytes(uint64_t N);
@@ -197,7 +198,7 @@ struct SortPlan {
     uint32_t top_bits = 0, npass = 0, width = 8;
 };
 constexpr uint64_t kBucketKeys = 512;
-constexpr int32_t kSampleMajorMaxN = 10240;  // LDS row of per-sample counters (6 bytes each)
+constexpr int32_t kSampleMajorMaxN = 10240;  // LDS row of per-sample counters (6 bytes each); < 2^16
 constexpr uint32_t kLocalCapKeys = 6912;  // keys one LDS range can hold
 SortPlan sort_plan(uint64_t N, uint32_t U);
 

@@ -167,11 +167,12 @@ constexpr int kOsNT = 512;
 constexpr int kOsWaves = kOsNT / kWave;
 constexpr uint32_t kOsTile = kOsNT * kRounds;  // 8192 keys
 
+template <class K>
 __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(
-    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t N, uint32_t shift, uint32_t nbits,
+    const K *__restrict__ in, K *__restrict__ out, uint64_t N, uint32_t shift, uint32_t nbits,
     const uint64_t *__restrict__ gstart, uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
     uint32_t ntiles, uint32_t *__restrict__ err) {
-    __shared__ uint64_t stage[kOsTile];
+    __shared__ K stage[kOsTile];
     __shared__ uint32_t wcnt[kOsWaves][kRadix];
     __shared__ uint32_t tdp[kRadix];
     __shared__ uint64_t base[kRadix];
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
         const uint64_t t0 = (uint64_t)tile * kOsTile;
         const uint64_t c1 = min(N, t0 + kOsTile);
         const uint64_t wb = t0 + (uint64_t)w * (kOsTile / kOsWaves);
-        uint64_t key[kRounds];
+        K key[kRounds];
         uint32_t rank[kRounds];
 #pragma unroll
         for (int j = 0; j < kRounds; ++j) {
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
         __syncthreads();
         const uint32_t cnt_tile = (uint32_t)(c1 - t0);
         for (uint32_t i = tid; i < cnt_tile; i += kOsNT) {
-            const uint64_t k = stage[i];
+            const K k = stage[i];
             const uint32_t d = (uint32_t)(k >> shift) & mask;
             out[base[d] + (i - tdp[d])] = k;
         }
@@ -376,9 +377,10 @@ void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, u
 
 namespace jas {
 
-bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
-                         uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
-                         hipStream_t s, Budget *b) {
+namespace {
+template <class K>
+bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit, uint32_t width,
+                   const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b, const char *name) {
     if (N <= 1 || hi_bit <= lo_bit) return true;
     if (width < 1 || width > 8) return false;
     const uint32_t npass = (hi_bit - lo_bit + width - 1) / width;
@@ -414,8 +416,8 @@ bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t
         }
         check_launch("look-back reset");
         {
-            JAS_TIMED("radix_onesweep", s);
-            k_radix_onesweep<<<grid, kOsNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
+            JAS_TIMED(name, s);
+            k_radix_onesweep<K><<<grid, kOsNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
                                                   ticket.p, (uint32_t)ntiles, err);
         }
         check_launch("radix scatter (look-back)");
@@ -423,6 +425,19 @@ bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t
         std::swap(keys.n, alt.n);
     }
     return true;
+}
+}  // namespace
+
+bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
+                         uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
+                         hipStream_t s, Budget *b) {
+    return onesweep_sort<uint64_t>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, "radix_onesweep");
+}
+
+bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,
+                             uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
+                             hipStream_t s, Budget *b) {
+    return onesweep_sort<uint32_t>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, "pair_sort");
 }
 
 }  // namespace jas

@@ -162,8 +162,9 @@ def test_bucket_ranges_and_fallback(case):
 
 @pytest.mark.parametrize("n,dmin", [(300, 1000), (10300, 0)])
 def test_row_lists_by_sample_and_by_row(n, dmin):
-    """Rows kept as lists are summed sample by sample (an LDS row of counters per
-    sample, up to 10240 samples) or, for more samples, pair by pair per row."""
+    """Rows kept as lists are summed sample by sample (their pairs sorted by the
+    smaller sample, an LDS row of counters per sample, up to 10240 samples) or,
+    for more samples, pair by pair per row."""
     rng = np.random.default_rng(n)
     pool = rng.choice(1 << 20, 3000, replace=False).astype(np.uint64)
     sets = [np.unique(rng.choice(pool, int(rng.integers(0, 7)))) for _ in range(n)]
