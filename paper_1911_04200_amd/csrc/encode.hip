@@ -712,26 +712,52 @@ __global__ void k_list_npairs(const uint64_t *lp, uint64_t QL, uint64_t *np) {
     }
 }
 
-// One thread per row writes its pairs at po[r]; per-block LDS totals of the
-// sort digits of a (digit q = bits [16 + width*q, 16 + width*(q+1)) of the word).
+// One lane per row: a wave's 64 consecutive rows own one contiguous stretch of
+// the output, which is assembled in LDS and written out coalesced (written
+// directly when it exceeds the stage); per-block LDS totals of the sort
+// digits of a (digit q = bits [16 + width*q, 16 + width*(q+1)) of the word).
+constexpr uint32_t kEmitStage = 2048;  // words per wave
+
 __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls,
                                                     uint64_t QL, const uint64_t *__restrict__ po,
                                                     uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
                                                     unsigned long long *__restrict__ ghist) {
     __shared__ uint32_t gh[kMaxPasses][256];
-    const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t stg[256 / kWave][kEmitStage];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint32_t dmask = (1u << width) - 1u;
 #pragma unroll
     for (int k = 0; k < kMaxPasses; ++k) gh[k][tid] = 0;
     __syncthreads();
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + tid; r < QL; r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t e0 = lp[r], e1 = lp[r + 1];
-        uint64_t o = po[r];
+    uint32_t *st = stg[w];
+    for (uint64_t r0 = ((uint64_t)blockIdx.x * (256 / kWave) + w) * kWave; r0 < QL;
+         r0 += (uint64_t)gridDim.x * 256) {
+        const uint64_t r = r0 + lane;
+        uint64_t e0 = 0, e1 = 0;
+        if (r < QL) {
+            e0 = lp[r];
+            e1 = lp[r + 1];
+        }
+        const uint64_t base = po[r0];
+        const uint64_t total = po[min(r0 + kWave, QL)] - base;
+        const uint64_t my = r < QL ? po[r] - base : 0;
+        const bool staged = total <= kEmitStage;  // wave-uniform
+        uint64_t o = my;
         for (uint64_t i = e0; i + 1 < e1; ++i) {
             const uint32_t a = ls[i];
             const uint32_t m = (uint32_t)(e1 - i - 1);  // pairs with a as the smaller sample
             for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(a >> (width * q)) & dmask], m);
-            for (uint64_t j = i + 1; j < e1; ++j) pairs[o++] = (a << 16) | ls[j];
+            for (uint64_t j = i + 1; j < e1; ++j, ++o) {
+                const uint32_t v = (a << 16) | ls[j];
+                if (staged) st[o] = v;
+                else pairs[base + o] = v;
+            }
+        }
+        if (staged) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t k = lane; k < total; k += kWave) pairs[base + k] = st[k];
+            __builtin_amdgcn_wave_barrier();
         }
     }
     __syncthreads();
@@ -1129,7 +1155,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             }
             {
                 JAS_TIMED("pair_emit", s);
-                k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 4096), 256, 0, s>>>(
+                k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 8192), 256, 0, s>>>(
                     db->list_ptr.p, db->list_smp.p, QL, npo.p, pk.p, npass, width, gh.p);
             }
             check_launch("pair emit");

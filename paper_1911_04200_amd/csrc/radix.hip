@@ -183,10 +183,17 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t lt = lanemask_lt();
     const uint64_t gs = digit ? gstart[tid] : 0;
+    // while ranking, the first kOsWaves*256 words of stage are per-wave tables
+    // of the lanes of the current round that have digit d
+    static_assert(kOsWaves * kRadix * sizeof(uint64_t) <= kOsTile * sizeof(K), "match tables fit the stage");
+    uint64_t *T = reinterpret_cast<uint64_t *>(stage) + w * kRadix;
     // persistent: take tiles in ticket order until none is left
     for (;;) {
         if (tid == 0) tile_sh = atomicAdd(ticket, 1u);
-        for (uint32_t i = tid; i < kOsWaves * kRadix; i += kOsNT) (&wcnt[0][0])[i] = 0;
+        for (uint32_t i = tid; i < kOsWaves * kRadix; i += kOsNT) {
+            (&wcnt[0][0])[i] = 0;
+            if constexpr (sizeof(K) == 4) reinterpret_cast<uint64_t *>(stage)[i] = 0;
+        }
         __syncthreads();
         const uint32_t tile = tile_sh;
         if (tile >= ntiles) break;  // uniform: every thread read the same ticket
@@ -200,23 +207,61 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             const uint64_t t = wb + (uint64_t)j * kWave + lane;
             key[j] = t < c1 ? in[t] : 0;
         }
-#pragma unroll
-        for (int j = 0; j < kRounds; ++j) {
-            const uint64_t t = wb + (uint64_t)j * kWave + lane;
-            const bool valid = t < c1;
-            const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
-            uint64_t peers = __ballot(valid);
-            for (uint32_t b = 0; b < nbits; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t vote = __ballot(valid && bit);
-                peers &= bit ? vote : ~vote;
+        if constexpr (sizeof(K) == 4) {
+            // Rank within the wave: lanes of a round with the same digit find each
+            // other through T[d] (each ORs in its lane bit, reads the set back and
+            // clears it; one wave's LDS operations run in order), take consecutive
+            // slots after the digit's count so far, and the lowest of them adds the
+            // group to the count with an LDS atomic whose return its peers fetch
+            // afterwards (in two halves, which keeps fewer registers live).
+    #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint32_t info[kRounds / 2];
+    #pragma unroll
+                for (int j = h * (kRounds / 2); j < (h + 1) * (kRounds / 2); ++j) {
+                    const uint64_t t = wb + (uint64_t)j * kWave + lane;
+                    const bool valid = t < c1;
+                    const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
+                    uint64_t peers = 0;
+                    if (valid) {
+                        atomicOr((unsigned long long *)&T[d], 1ull << lane);
+                        peers = __hip_atomic_load(&T[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_store(&T[d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    const uint32_t before = __popcll(peers & lt);
+                    const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : lane;
+                    uint32_t old = 0;
+                    if (valid && before == 0) old = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(peers));
+                    rank[j] = old;
+                    info[j - h * (kRounds / 2)] = (leader << 8) | before;
+                }
+    #pragma unroll
+                for (int j = h * (kRounds / 2); j < (h + 1) * (kRounds / 2); ++j) {
+                    const uint32_t f = info[j - h * (kRounds / 2)];
+                    rank[j] = (uint32_t)__shfl((int)rank[j], (int)(f >> 8), kWave) + (f & 255u);
+                }
             }
-            const uint32_t before = __popcll(peers & lt);
-            const uint32_t cnt = __popcll(peers);
-            uint32_t b0 = 0;
-            if (valid) b0 = wcnt[w][d];
-            if (valid && before == 0) wcnt[w][d] = b0 + cnt;
-            rank[j] = b0 + before;
+        } else {
+            // 64-bit keys: rank by one ballot per digit bit (fewer registers
+            // than the table form, which spills with 64-bit keys)
+    #pragma unroll
+            for (int j = 0; j < kRounds; ++j) {
+                const uint64_t t = wb + (uint64_t)j * kWave + lane;
+                const bool valid = t < c1;
+                const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
+                uint64_t peers = __ballot(valid);
+                for (uint32_t b = 0; b < nbits; ++b) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t vote = __ballot(valid && bit);
+                    peers &= bit ? vote : ~vote;
+                }
+                const uint32_t before = __popcll(peers & lt);
+                const uint32_t cnt = __popcll(peers);
+                uint32_t b0 = 0;
+                if (valid) b0 = wcnt[w][d];
+                if (valid && before == 0) wcnt[w][d] = b0 + cnt;
+                rank[j] = b0 + before;
+            }
         }
         __syncthreads();
         uint32_t tc = 0;
