@@ -33,8 +33,9 @@ def log(msg):
 def kernel_source_hash(kernel: str) -> str:
     src = {"radix_scatter": "radix.hip", "radix_onesweep": "radix.hip", "radix_hist": "radix.hip",
            "gram_popc": "gram.hip", "gram_mfma": "gram.hip", "list_pairs": "gram.hip",
-           "list_by_sample": "gram.hip", "cls_count": "encode.hip", "cls_write": "encode.hip",
-           "local_cls": "encode.hip", "local_move": "encode.hip", "by_fill": "encode.hip",
+           "pair_count": "gram.hip", "cls_count": "encode.hip", "cls_write": "encode.hip",
+           "local_cls": "encode.hip", "local_move": "encode.hip", "pair_emit": "encode.hip",
+           "pair_sort": "radix.hip",
            "pack": "encode.hip", "build_keys": "encode.hip"}.get(kernel)
     if src is None:
         return ""
@@ -65,9 +66,12 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
         shared = stats["n_pairs"] - (stats["n_rows"] - stats["n_shared_rows"])
         return ("hbm", (8.0 * shared + 32.0 * stats["n_shared_rows"]) / 1e9, "GB/s",
                 "4 B per shared pair and 16 B per shared row, each read and written once")
-    if kernel == "list_by_sample":
-        return ("hbm", 4.0 * stats["list_pairs"] / 1e9, "GB/s",
-                "4 B per counted pair (the later sample of the pair, read from its row)")
+    if kernel == "pair_sort":
+        return "hbm", 8.0 * stats["list_pairs"] / 1e9, "GB/s", "8 B per 32-bit pair word per pass (read 4 + write 4)"
+    if kernel == "pair_emit":
+        return "hbm", 4.0 * stats["list_pairs"] / 1e9, "GB/s", "4 B per pair word written (+ the row lists read)"
+    if kernel == "pair_count":
+        return "hbm", 4.0 * stats["list_pairs"] / 1e9, "GB/s", "4 B per pair word read"
     if kernel == "pack":
         ldw = math.ceil(n / 128) * 128
         return "hbm", 8.0 * stats["n_word_rows"] * ldw / 1e9, "GB/s", "8 B per packed word written"
