@@ -53,6 +53,7 @@ typedef enum {
 #define JAS_UPPER 0x10u         /* jas_gram: outputs in the packed upper layout (j >= i) */
 #define JAS_FORCE_POPCOUNT 0x20u /* jas_gram: every packed tile on the AND+popcount kernel */
 #define JAS_FORCE_MFMA 0x40u    /* jas_gram: every packed tile on the int8 MFMA kernel */
+#define JAS_TUNE 0x80u          /* jas_gram: time the MFMA tile variants on this db first (see jas_gram) */
 
 typedef struct jas_db jas_db; /* opaque, library-owned, device-resident encoding of A */
 
@@ -112,9 +113,16 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
  *  den   int64, same layout as B: C_ij = |X_i cup X_j|; may be NULL.
  *  J     double, same layout as B: C_ij == 0 ? 1.0 : (double)B_ij / (double)C_ij,
  *        IEEE binary64 round-to-nearest; may be NULL.
- *  flags JAS_UPPER, JAS_FORCE_POPCOUNT / JAS_FORCE_MFMA (at most one), JAS_HOST_PTRS.
+ *  flags JAS_UPPER, JAS_FORCE_POPCOUNT / JAS_FORCE_MFMA (at most one), JAS_HOST_PTRS,
+ *        JAS_TUNE.
  * The result does not depend on flags other than the layout: every tile path
- * is exact.  Does not synchronise unless JAS_HOST_PTRS is given.
+ * is exact.  Does not synchronise unless JAS_HOST_PTRS or JAS_TUNE is given.
+ * JAS_TUNE (autotuner): before the product, the MFMA Gram runs once in each of
+ * its tile variants (word rows per step, K split) on this db, timed with HIP
+ * events on the stream (synchronising); the fastest is kept, in this process,
+ * for every later db on the device with the same n and the same power of two
+ * of word rows, and is used by later calls without the flag.  Not capturable
+ * in a HIP graph; calls without it are.
  */
 jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t *B, int64_t *card, int64_t *den,
                     double *J);

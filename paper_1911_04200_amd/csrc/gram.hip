@@ -13,6 +13,11 @@
 #include <algorithm>
 #include <vector>
 
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device_util.hpp"
 #include "jas_internal.hpp"
 
@@ -340,6 +345,46 @@ __global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ 
     if (J) J[pos] = c == 0 ? 1.0 : (double)b / (double)c;
 }
 
+// Tile variants of the MFMA Gram: word rows per step of the K loop, and how
+// many blocks the K split aims for.  The autotuner (JAS_TUNE) times each on the
+// caller's db and keeps the fastest for dbs of the same shape.
+struct GramVariant {
+    int step;
+    uint64_t want_blocks;
+};
+constexpr GramVariant kVariants[] = {{4, 2048}, {2, 2048}, {4, 1024}, {4, 4096}, {2, 4096}, {2, 1024}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, uint32_t, uint32_t>, int> g_tuned;  // (device, n, ceil(log2 H)) -> variant
+
+void k_split(uint64_t H, uint64_t np, uint64_t want, uint64_t &kper, uint64_t &splits) {
+    splits = std::max<uint64_t>(1, div_up(want, np));
+    kper = div_up(H, splits);
+    kper = std::max<uint64_t>(kper, 64);
+    kper = div_up(kper, kKC) * kKC;
+    splits = div_up(H, kper);
+    if (splits > 65535) {
+        splits = 65535;
+        kper = div_up(div_up(H, splits), kKC) * kKC;
+        splits = div_up(H, kper);
+    }
+}
+
+void launch_mfma(const jas_db *db, int v, hipStream_t s, int32_t *B, bool upper) {
+    const uint32_t n = (uint32_t)db->n;
+    const uint32_t nt = (uint32_t)div_up(n, kT);
+    const uint64_t np = (uint64_t)nt * (nt + 1) / 2;
+    uint64_t kper, splits;
+    k_split(db->H, np, kVariants[v].want_blocks, kper, splits);
+    const uint64_t ldw = div_up(n, 128) * 128;
+    dim3 grid((uint32_t)np, (uint32_t)splits);
+    if (kVariants[v].step == 4)
+        k_gram_mfma<2, 4><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+    else
+        k_gram_mfma<2, 2><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+}
+
 }  // namespace
 
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J) {
@@ -353,28 +398,53 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
     }
     check_launch("zero B");
     if (db->H > 0 && n >= 2) {
-        const uint32_t nt = (uint32_t)div_up(n, kT);
-        const uint64_t np = (uint64_t)nt * (nt + 1) / 2;
-        // K split: enough blocks to fill 256 CUs several times over
-        const uint64_t want = 2048;
-        uint64_t splits = std::max<uint64_t>(1, div_up(want, np));
-        uint64_t kper = div_up(db->H, splits);
-        kper = std::max<uint64_t>(kper, 64);
-        kper = div_up(kper, kKC) * kKC;
-        splits = div_up(db->H, kper);
-        if (splits > 65535) {
-            splits = 65535;
-            kper = div_up(div_up(db->H, splits), kKC) * kKC;
-            splits = div_up(db->H, kper);
-        }
-        const uint64_t ldw = div_up(n, 128) * 128;
-        dim3 grid((uint32_t)np, (uint32_t)splits);
         if (flags & JAS_FORCE_POPCOUNT) {
+            const uint32_t nt = (uint32_t)div_up(n, kT);
+            const uint64_t np = (uint64_t)nt * (nt + 1) / 2;
+            uint64_t kper, splits;
+            k_split(db->H, np, 2048, kper, splits);
+            const uint64_t ldw = div_up(n, 128) * 128;
+            dim3 grid((uint32_t)np, (uint32_t)splits);
             JAS_TIMED("gram_popc", s);
             k_gram_popc<<<grid, kNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
         } else {
+            const auto key = std::make_tuple(db->device, n, ceil_log2_u64(db->H));
+            int v = 0;
+            if (flags & JAS_TUNE) {
+                // time every variant on this db (each adds into B, which is cleared again after)
+                JAS_HOST_TIMED("gram_tune");
+                hipEvent_t e0, e1;
+                JAS_HIP(hipEventCreate(&e0));
+                JAS_HIP(hipEventCreate(&e1));
+                float best = INFINITY;
+                for (int c = 0; c < kNumVariants; ++c) {
+                    JAS_HIP(hipEventRecord(e0, s));
+                    launch_mfma(db, c, s, B, upper);
+                    check_launch("gram (tuning)");
+                    JAS_HIP(hipEventRecord(e1, s));
+                    JAS_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    JAS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) {
+                        best = ms;
+                        v = c;
+                    }
+                }
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                {
+                    std::lock_guard<std::mutex> lk(g_tune_mu);
+                    g_tuned[key] = v;
+                }
+                k_fill_i32<<<(uint32_t)std::min<uint64_t>(div_up(len, 256), 65536), 256, 0, s>>>(B, len, 0);
+                check_launch("zero B");
+            } else {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                const auto it = g_tuned.find(key);
+                if (it != g_tuned.end()) v = it->second;
+            }
             JAS_TIMED("gram_mfma", s);
-            k_gram_mfma<2, 4><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            launch_mfma(db, v, s, B, upper);
         }
         check_launch("gram");
     }

@@ -22,6 +22,7 @@ JAS_KEEP_IDS = 0x2
 JAS_UPPER = 0x10
 JAS_FORCE_POPCOUNT = 0x20
 JAS_FORCE_MFMA = 0x40
+JAS_TUNE = 0x80
 
 STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERFLOW", -4: "JAS_EDEVICE",
                 -6: "JAS_EUNSUPPORTED"}

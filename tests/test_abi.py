@@ -26,6 +26,16 @@ def test_library_exports_every_declared_symbol():
     assert sorted(jas.EXPORTS) == names
 
 
+def test_flag_and_status_values_match_the_header():
+    text = open(os.path.join(ROOT, "include", "jas.h")).read()
+    flags = dict(re.findall(r"#define (JAS_\w+) (0x[0-9a-fA-F]+)u", text))
+    assert len(flags) >= 6
+    for name, value in flags.items():
+        assert getattr(jas, name) == int(value, 16), name
+    for name, value in re.findall(r"(JAS_E\w+|JAS_OK)\s*=\s*(-?\d+)", text):
+        assert getattr(jas, name) == int(value), name
+
+
 def test_version():
     assert "gfx950" in jas.jas_version()
 

@@ -281,6 +281,22 @@ def test_mfma_equals_popcount_on_dense_tiles(name):
     assert_matches({k: v.cpu().numpy() for k, v in b.items()}, ref)
 
 
+def test_gram_autotuner_keeps_results_exact():
+    spec = synth.scaled(synth.workload("precision"), n=300, size_scale=0.01, pool_scale=0.01)
+    ids, off = synth.generate(spec)
+    db, st = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, dense_min_degree=2)
+    assert st["n_word_rows"] > 0
+    plain = jas.gram(db, upper=True)
+    tuned = jas.gram(db, upper=True, flags=cabi.JAS_TUNE)    # times every tile variant, then runs the fastest
+    again = jas.gram(db, upper=True)                          # the kept choice
+    torch.cuda.synchronize()
+    for k in ("B", "den", "J", "card"):
+        assert torch.equal(plain[k], tuned[k]) and torch.equal(plain[k], again[k]), k
+    db.close()
+    ref = oracle.all_pairs(ids, off)
+    assert_matches({k: v.cpu().numpy() for k, v in tuned.items()}, ref, upper=True)
+
+
 def test_repeat_runs_are_identical():
     spec = synth.scaled(synth.workload("precision"), n=300, size_scale=0.01, pool_scale=0.01)
     ids, off = synth.generate(spec)
