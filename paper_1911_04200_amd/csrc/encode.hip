@@ -705,10 +705,11 @@ __global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, con
 // scatters over the bits of a), so that the Gram step reads each sample's
 // pairs as one contiguous run (the row-by-row form of B = A^T A over the row
 // lists).
-__global__ void k_list_npairs(const uint64_t *lp, uint64_t QL, uint64_t *np) {
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < QL; r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t d = lp[r + 1] - lp[r];
-        np[r] = d * (d - 1) / 2;
+__global__ void k_list_npairs(const uint64_t *Lrow, const uint64_t *row_ptr, uint64_t QL, uint64_t *np) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = Lrow[j];
+        const uint64_t d = row_ptr[r + 1] - row_ptr[r];
+        np[j] = d * (d - 1) / 2;
     }
 }
 
@@ -718,8 +719,10 @@ __global__ void k_list_npairs(const uint64_t *lp, uint64_t QL, uint64_t *np) {
 // digits of a (digit q = bits [16 + width*q, 16 + width*(q+1)) of the word).
 constexpr uint32_t kEmitStage = 2048;  // words per wave
 
-__global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls,
-                                                    uint64_t QL, const uint64_t *__restrict__ po,
+__global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ Lrow,
+                                                    const uint64_t *__restrict__ row_ptr,
+                                                    const uint32_t *__restrict__ ls, uint64_t QL,
+                                                    const uint64_t *__restrict__ po,
                                                     uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
                                                     unsigned long long *__restrict__ ghist) {
     __shared__ uint32_t gh[kMaxPasses][256];
@@ -735,8 +738,9 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
         const uint64_t r = r0 + lane;
         uint64_t e0 = 0, e1 = 0;
         if (r < QL) {
-            e0 = lp[r];
-            e1 = lp[r + 1];
+            const uint64_t rr = Lrow[r];
+            e0 = row_ptr[rr];
+            e1 = row_ptr[rr + 1];
         }
         const uint64_t base = po[r0];
         const uint64_t total = po[min(r0 + kWave, QL)] - base;
@@ -1105,9 +1109,58 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     db->H = H;
 
     // --- row lists -----------------------------------------------------------
+    // Up to kSampleMajorMaxN samples: the rows' pairs, sorted by their smaller
+    // sample, straight from the shared pairs.  Otherwise (or if that sort
+    // cannot run) the rows as a CSR of samples, summed pair by pair.
     db->n_list = QL;
-    db->list_ptr.alloc(QL + 1, s, &db->budget, false, "row list pointers");
-    if (QL > 0) {
+    bool pairs_done = false;
+    if (QL > 0 && n <= kSampleMajorMaxN) {
+        DevBuf<uint64_t> np, npo, tmp2;
+        np.alloc(QL, s, tb, true, "row pair counts");
+        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
+            {
+                JAS_TIMED("list_npairs", st_);
+                k_list_npairs<<<b, 256, 0, st_>>>(Lrow.p, rptrp, QL, np.p);
+            }
+        });
+        check_launch("row pair counts");
+        npo.alloc(QL + 1, s, tb, true, "row pair offsets");
+        tmp2.alloc(scan_tmp_elems(QL), s, tb, true, "scan scratch");
+        scan_excl_u64(np.p, npo.p, QL, tmp2.p, s);
+        const uint64_t P = to_host_u64(npo.p + QL, s);
+        np.release();
+        tmp2.release();
+        const uint32_t sb = std::max<uint32_t>(1, ceil_log2_u64((uint64_t)n));
+        const uint32_t npass = (sb + 7) / 8, width = (sb + npass - 1) / npass;
+        DevBuf<uint32_t> pk, palt, perr;
+        DevBuf<unsigned long long> gh;
+        pk.alloc(P + 2, s, &db->budget, false, "row-list pairs");
+        palt.alloc(P + 2, s, tb, true, "row-list pairs (second buffer)");
+        gh.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, tb, true, "pair digit totals");
+        perr.alloc(2, s, tb, true, "pair sort flag");
+        {
+            JAS_TIMED("fill_u64", s);
+            k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)gh.p, (uint64_t)kGhistReplicas * kMaxPasses * 256, 0);
+            k_fill_u64<<<1, 64, 0, s>>>((uint64_t *)perr.p, 1, 0);
+        }
+        {
+            JAS_TIMED("pair_emit", s);
+            k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 8192), 256, 0, s>>>(
+                Lrow.p, rptrp, Sp, QL, npo.p, pk.p, npass, width, gh.p);
+        }
+        check_launch("pair emit");
+        const bool ok = radix_sort_onesweep_u32(pk, palt, P, 16, 16 + sb, width, gh.p, perr.p, s, tb);
+        uint32_t herr = 0;
+        JAS_HIP(hipMemcpyAsync(&herr, perr.p, 4, hipMemcpyDeviceToHost, s));
+        JAS_HIP(hipStreamSynchronize(s));
+        if (ok && herr == 0) {
+            db->n_lpairs = P;
+            db->pairs = std::move(pk);
+            pairs_done = true;
+        }
+    }
+    if (QL > 0 && !pairs_done) {
+        db->list_ptr.alloc(QL + 1, s, &db->budget, false, "row list pointers");
         DevBuf<uint64_t> deg, tmp;
         deg.alloc(QL, s, tb, true, "row list degrees");
         launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("list_deg", st_); k_list_deg<<<b, 256, 0, st_>>>(Lrow.p, rptrp, QL, deg.p); } });
@@ -1123,53 +1176,8 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             }
         });
         check_launch("list gather");
-        // the rows' pairs, sorted by their smaller sample
-        if (n <= kSampleMajorMaxN) {
-            DevBuf<uint64_t> np, npo, tmp2;
-            np.alloc(QL, s, tb, true, "row pair counts");
-            launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
-                {
-                    JAS_TIMED("list_npairs", st_);
-                    k_list_npairs<<<b, 256, 0, st_>>>(db->list_ptr.p, QL, np.p);
-                }
-            });
-            check_launch("row pair counts");
-            npo.alloc(QL + 1, s, tb, true, "row pair offsets");
-            tmp2.alloc(scan_tmp_elems(QL), s, tb, true, "scan scratch");
-            scan_excl_u64(np.p, npo.p, QL, tmp2.p, s);
-            const uint64_t P = to_host_u64(npo.p + QL, s);
-            np.release();
-            tmp2.release();
-            const uint32_t sb = std::max<uint32_t>(1, ceil_log2_u64((uint64_t)n));
-            const uint32_t npass = (sb + 7) / 8, width = (sb + npass - 1) / npass;
-            DevBuf<uint32_t> pk, palt, perr;
-            DevBuf<unsigned long long> gh;
-            pk.alloc(P + 2, s, &db->budget, false, "row-list pairs");
-            palt.alloc(P + 2, s, tb, true, "row-list pairs (second buffer)");
-            gh.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, tb, true, "pair digit totals");
-            perr.alloc(2, s, tb, true, "pair sort flag");
-            {
-                JAS_TIMED("fill_u64", s);
-                k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)gh.p, (uint64_t)kGhistReplicas * kMaxPasses * 256, 0);
-                k_fill_u64<<<1, 64, 0, s>>>((uint64_t *)perr.p, 1, 0);
-            }
-            {
-                JAS_TIMED("pair_emit", s);
-                k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 8192), 256, 0, s>>>(
-                    db->list_ptr.p, db->list_smp.p, QL, npo.p, pk.p, npass, width, gh.p);
-            }
-            check_launch("pair emit");
-            bool ok = radix_sort_onesweep_u32(pk, palt, P, 16, 16 + sb, width, gh.p, perr.p, s, tb);
-            uint32_t herr = 0;
-            JAS_HIP(hipMemcpyAsync(&herr, perr.p, 4, hipMemcpyDeviceToHost, s));
-            JAS_HIP(hipStreamSynchronize(s));
-            if (ok && herr == 0) {
-                db->n_lpairs = P;
-                db->pairs = std::move(pk);
-            }
-            // else: the Gram step adds the rows pair by pair (k_list_pairs)
-        }
     } else {
+        db->list_ptr.alloc(1, s, &db->budget, false, "row list pointers");
         {
             JAS_TIMED("fill_u64", s);
             k_fill_u64<<<1, 1, 0, s>>>(db->list_ptr.p, 1, 0);
