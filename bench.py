@@ -145,9 +145,9 @@ def run_serving(n_requests: int, n_saturation: int, seed: int = 1):
     del ids_d
     torch.cuda.synchronize()
     log(f"[serving] encoded in {enc_s:.2f} s; generating requests")
-    warm = serve.make_requests(spec, 8, seed=seed * 1000 + 1, first_id=100000)
-    sat = serve.make_requests(spec, n_saturation, seed=seed * 1000 + 2, first_id=200000)
-    reqs = serve.make_requests(spec, n_requests, seed=seed * 1000 + 3, first_id=300000)
+    warm = serve.make_requests(spec, 8, seed=seed * 1000 + 1, first_id=100000, pinned=True)
+    sat = serve.make_requests(spec, n_saturation, seed=seed * 1000 + 2, first_id=200000, pinned=True)
+    reqs = serve.make_requests(spec, n_requests, seed=seed * 1000 + 3, first_id=300000, pinned=True)
     server = serve.Server(db, slots=4, budget_bytes=8 << 30, max_batch_sets=64)
     server.run(warm)
     t = time.perf_counter()

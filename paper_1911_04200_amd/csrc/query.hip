@@ -20,12 +20,17 @@ constexpr int kNT = 256;
 constexpr uint64_t kQChunk = 16384;  // query entries per block
 constexpr int32_t kHistMax = 16384;
 
+// Keys (q << U) | id of 4096 entries per block, and the totals of every
+// 8-bit digit of the keys (kGhistReplicas copies) for the single-pass sort.
 __global__ __launch_bounds__(kNT) void k_qkeys(const uint64_t *__restrict__ ids, const uint64_t *__restrict__ off,
                                                 int32_t nq, uint64_t N, uint32_t U, uint64_t *__restrict__ keys,
-                                                uint32_t *err) {
+                                                uint32_t *err, uint32_t npass, unsigned long long *__restrict__ ghist) {
     __shared__ int32_t s_lo, s_hi;
+    __shared__ uint32_t gh[kMaxPasses][256];
     const uint64_t b0 = (uint64_t)blockIdx.x * 4096;
     const uint64_t b1 = min(N, b0 + 4096);
+#pragma unroll
+    for (int k = 0; k < kMaxPasses; ++k) gh[k][threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         s_lo = find_sample(off, 0, nq - 1, b0);
         s_hi = find_sample(off, s_lo, nq - 1, b1 - 1);
@@ -37,9 +42,17 @@ __global__ __launch_bounds__(kNT) void k_qkeys(const uint64_t *__restrict__ ids,
         const int32_t q = find_sample(off, s_lo, s_hi, t);
         const uint64_t id = ids[t];
         bad |= (id & hi_mask) != 0;
-        keys[t] = ((uint64_t)q << U) | (id & ~hi_mask);
+        const uint64_t key = ((uint64_t)q << U) | (id & ~hi_mask);
+        keys[t] = key;
+        for (uint32_t p = 0; p < npass; ++p) atomicAdd(&gh[p][(uint32_t)(key >> (8 * p)) & 255u], 1u);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1u);
+    __syncthreads();
+    if (ghist) {
+        unsigned long long *g = ghist + (uint64_t)(blockIdx.x % kGhistReplicas) * kMaxPasses * 256;
+        for (uint32_t p = 0; p < npass; ++p)
+            if (gh[p][threadIdx.x]) atomicAdd(&g[p * 256 + threadIdx.x], (unsigned long long)gh[p][threadIdx.x]);
+    }
 }
 
 __global__ void k_qblocks(const uint64_t *off, int32_t nq, uint64_t *nb) {
@@ -134,8 +147,11 @@ __global__ void k_qfinalize(const int32_t *__restrict__ B, const unsigned long l
 
 uint64_t query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids) {
     (void)db;
-    return 2 * 8 * std::max<uint64_t>(n_q_ids, 1) + radix_work_bytes(n_q_ids) + 8 * (uint64_t)(nq + 1) * 4 +
-           scan_tmp_elems(nq) * 8 + 4096;
+    // keys and second buffer, the per-pass fallback's counts, look-back status
+    // (1 KiB per 8192 keys), digit totals and starts, per-query blocks
+    const uint64_t nk = std::max<uint64_t>(n_q_ids, 1);
+    return 2 * 8 * nk + radix_work_bytes(n_q_ids) + (nk / 8192 + 1) * 1024 + 4 + 2 * (uint64_t)kGhistReplicas * 8 * 256 * 8 +
+           8 * (uint64_t)(nq + 1) * 4 + scan_tmp_elems(nq) * 8 + 4096;
 }
 
 void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint64_t NQ,
@@ -171,17 +187,40 @@ void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, i
             k_fill_u32<<<1, 64, 0, s>>>(err.p, 1);
         }
         const uint64_t kb = div_up(NQ, 4096);
+        const uint32_t kbits = U + qbits, npass = (kbits + 7) / 8;
+        DevBuf<unsigned long long> ghist;
+        ghist.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, nullptr, true, "query digit totals");
+        {
+            JAS_TIMED("fill_u64", s);
+            k_fill_u64<<<64, 256, 0, s>>>(ghist.p, (uint64_t)kGhistReplicas * kMaxPasses * 256);
+        }
         {
             JAS_TIMED("qkeys", s);
-            k_qkeys<<<(uint32_t)kb, kNT, 0, s>>>(q_ids, q_offsets, nq, NQ, U, keys.p, err.p);
+            k_qkeys<<<(uint32_t)kb, kNT, 0, s>>>(q_ids, q_offsets, nq, NQ, U, keys.p, err.p, npass, ghist.p);
         }
         check_launch("query keys");
         uint32_t herr = 0;
         JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
         JAS_HIP(hipStreamSynchronize(s));
         if (herr) fail(JAS_EINVAL, "a query ID is >= 2^universe_bits");
-        RadixWork rw;
-        radix_sort_u64(keys, alt, NQ, 0, U + qbits, rw, s, nullptr);
+        // single-pass scatters; if one cannot run (or its look-back gave up),
+        // the keys are rebuilt and sorted with per-pass histograms instead
+        bool sorted = radix_sort_onesweep(keys, alt, NQ, 0, kbits, 8, ghist.p, err.p, s, nullptr);
+        if (sorted) {
+            JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipStreamSynchronize(s));
+            sorted = herr == 0;
+        }
+        if (!sorted) {
+            {
+                JAS_TIMED("fill_u32", s);
+                k_fill_u32<<<1, 64, 0, s>>>(err.p, 1);
+            }
+            k_qkeys<<<(uint32_t)kb, kNT, 0, s>>>(q_ids, q_offsets, nq, NQ, U, keys.p, err.p, 0, nullptr);
+            check_launch("query keys");
+            RadixWork rw;
+            radix_sort_u64(keys, alt, NQ, 0, kbits, rw, s, nullptr);
+        }
         alt.release();
         DevBuf<uint64_t> nb, bo, tmp;
         nb.alloc(nq, s, nullptr, true, "query blocks");

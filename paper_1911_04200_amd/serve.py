@@ -195,8 +195,11 @@ def summarize(reqs: List[Request], n: int, wall: float) -> dict:
 
 
 def make_requests(db_spec, count: int, seed: int, max_sets: int = 64, size_scale: float = 1.0,
-                  first_id: int = 0) -> List[Request]:
-    """Seeded synthetic requests: 1..max_sets query sets each (sizes and sharing as synth.query_spec)."""
+                  first_id: int = 0, pinned: bool = False) -> List[Request]:
+    """Seeded synthetic requests: 1..max_sets query sets each (sizes and sharing as synth.query_spec).
+
+    pinned: the IDs are received into page-locked host memory (as a server's
+    receive buffers would be), so their copy to the device is a plain DMA."""
     import synth
     rng = np.random.default_rng(seed)
     out = []
@@ -205,8 +208,18 @@ def make_requests(db_spec, count: int, seed: int, max_sets: int = 64, size_scale
         spec = synth.query_spec(db_spec, first_id + k, nq)
         if size_scale != 1.0:
             spec = synth.scaled(spec, size_scale=size_scale)
-        ids, off = synth.generate(spec)
-        out.append(Request(first_id + k, ids, off))
+        if pinned:
+            import torch
+            off = synth.offsets(spec)
+            buf = torch.empty(max(int(off[-1]), 1), dtype=torch.int64, pin_memory=True)
+            ids = buf.numpy().view(np.uint64)[:int(off[-1])]
+            synth.generate(spec, out=ids)
+            req = Request(first_id + k, ids, off)
+            req._pinned = buf  # keeps the page-locked buffer alive
+        else:
+            ids, off = synth.generate(spec)
+            req = Request(first_id + k, ids, off)
+        out.append(req)
     return out
 
 
