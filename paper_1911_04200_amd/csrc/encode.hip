@@ -2,20 +2,22 @@
 //
 // Input: CSR sets.  Keys (id << sbits) | sample are built in CSR order, which
 // is already ascending in `sample`, so a stable sort on the ID bits alone
-// leaves every ID's entries together with samples ascending.
+// leaves every ID's entries together with samples ascending.  The global sort
+// (radix.hip) orders the keys by their top ID bits only; each range of whole
+// buckets is finished here, in LDS (k_local_cls).
 //
 // After the sort (encode_sorted):
 //   classify   first occurrence of a key = a distinct (ID, sample) pair, i.e. a
 //              nonzero of A (repeats dropped: the (max, x) write of Sec. IV-A);
-//              |X_i| = distinct pairs of sample i (column sums, Eq. (4));
-//              an ID's run of distinct pairs is one nonzero row of A (the
-//              filter of Eq. (5)); rows with >= 2 pairs ("shared") are the
+//              |X_i| = entries of sample i minus its repeats (column sums,
+//              Eq. (4)); an ID's run of distinct pairs is one nonzero row of A
+//              (the filter of Eq. (5)); rows with >= 2 pairs ("shared") are the
 //              only rows off-diagonal B depends on, because a row with one
 //              nonzero adds only to B_ii = |X_i|.
 //   compaction shared rows are numbered in ID order by a prefix sum (Eq. (6)).
 //   split      rows of degree >= dmin are bit-packed; rows of degree 2..dmin-1
-//              are kept as plain row lists (their outer products are added
-//              pair by pair in the Gram step).
+//              are kept as row lists: their pairs, sorted by the smaller
+//              sample, are counted per sample in the Gram step.
 //   batches    packed rows are grouped by batch l = id >> batch_bits (Eq. (3));
 //              inside a batch, row p (in ID order) is bit p % 64 of word row
 //              p / 64, so words never straddle batches.

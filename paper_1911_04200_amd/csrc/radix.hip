@@ -1,8 +1,9 @@
-// Stable LSD radix sort of 64-bit keys on a bit range (8-bit digits).
+// Stable LSD radix sorts of keys on a bit range.
 //
 // Used to group equal IDs (the zero-row filter f of Eq. (5) and the
 // compaction of Eq. (6) need every nonzero row's entries together).
-// Each pass is reduce-then-scan with no inter-block waiting:
+// radix_sort_u64 (the path for inputs the single-pass scatter below cannot
+// take): each pass is reduce-then-scan with no inter-block waiting:
 //   1. k_radix_hist:    per-chunk digit histograms (digit-major counts[d][chunk]);
 //   2. exclusive scan:  global start of every (digit, chunk) bucket;
 //   3. k_radix_scatter: per 4096-key tile, a wave64 ballot multisplit ranks
@@ -144,11 +145,13 @@ __global__ __launch_bounds__(kNT) void k_radix_scatter(const uint64_t *__restric
 // ---------------------------------------------------------------------------
 // Single-pass scatter with decoupled look-back (chained scan: Merrill &
 // Garland, "Single-pass parallel prefix scan with decoupled look-back",
-// 2016; as in Adinets & Merrill's Onesweep, 2022).  One 4096-key tile per
-// block; tiles take tickets from an atomic counter in launch order, so every
+// 2016; as in Adinets & Merrill's Onesweep, 2022).  Persistent blocks take
+// 8192-key tiles by ticket from an atomic counter in launch order, so every
 // tile a block waits for already belongs to a running block.  Per tile and
 // digit a 32-bit status word holds a flag (aggregate / inclusive prefix) and
-// a 30-bit count; the caller guarantees every digit total is < 2^30.
+// a 30-bit count; the caller guarantees every digit total is < 2^30.  The
+// same kernel sorts 64-bit keys (the encoder and the query path) and 32-bit
+// row-list pair words.
 constexpr uint32_t kFlagA = 1u << 30;  // the tile's own count is available
 constexpr uint32_t kFlagP = 2u << 30;  // the inclusive prefix over tiles 0..t is available
 constexpr uint32_t kValMask = (1u << 30) - 1u;

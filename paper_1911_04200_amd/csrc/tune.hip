@@ -10,10 +10,10 @@
 //   time(t)   = pairs(t) / r_pair + rows(t) / r_row + words(t) * 128^2 T / r_word
 // The threshold t minimising time(t) is taken, among those whose packed matrix
 // (words(t) * 8 * ceil(n/128)*128 bytes) fits the memory cap.  The rates were
-// fitted on MI355X to the list kernels (k_by_count, k_by_fill,
-// k_list_by_sample, k_list_gather: 7.4e10 pairs/s and 1.6e10 rows/s) and to
-// k_pack + k_gram_mfma (1.9e13 word pairs/s) over a sweep of thresholds on the
-// paper-like workload, whose measured optimum (t = 8) the model reproduces.
+// fitted on MI355X to the row-list kernels (7.4e10 pairs/s and 1.6e10 rows/s)
+// and to k_pack + k_gram_mfma (1.9e13 word pairs/s) over a sweep of
+// thresholds on the paper-like workload, whose measured optimum (t = 8) the
+// model reproduces.
 #include <algorithm>
 #include <cmath>
 
