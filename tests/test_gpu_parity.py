@@ -160,6 +160,43 @@ def test_bucket_ranges_and_fallback(case):
         assert "host:classify_fallback" in names and "cls_write" in names
 
 
+@pytest.mark.parametrize("case", ["uniform", "narrow_ids"])
+def test_query_index_on_both_classification_paths(case):
+    """With JAS_KEEP_IDS the distinct keys form the query index, whether the
+    ranges were finished in LDS or the full sort had to run."""
+    rng = np.random.default_rng(7)
+    if case == "uniform":
+        U, n = 36, 70
+        core = rng.integers(0, 1 << 36, 3000, dtype=np.uint64)
+        sets = [np.concatenate([rng.choice(core, int(rng.integers(0, 2500))),
+                                rng.integers(0, 1 << 36, int(rng.integers(0, 2500)), dtype=np.uint64)])
+                for _ in range(n)]
+    else:
+        U, n = 40, 60
+        sets = [rng.choice(1 << 12, int(rng.integers(500, 2500)), replace=False).astype(np.uint64)
+                for _ in range(n)]
+    ids, off = csr(sets)
+    cabi.jas_timing_report()
+    cabi.jas_timing_enable(True)
+    try:
+        db, st = jas.encode(dev(ids), dev(off), universe_bits=U, keep_ids=True)
+        torch.cuda.synchronize()
+    finally:
+        names = set(cabi.jas_timing_report())
+        cabi.jas_timing_enable(False)
+    assert ("host:classify_fallback" in names) == (case == "narrow_ids")
+    qsets = [sets[3], sets[11][::2], np.concatenate([sets[20][:50], np.array([(1 << U) - 1], np.uint64)])]
+    qi, qo = csr(qsets)
+    out = jas.query(db, dev(qi), dev(qo))
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    db.close()
+    ref = oracle.cross(qi, qo, ids, off)
+    assert np.array_equal(res["q_card"], ref["q_card"])
+    assert np.array_equal(res["B"], ref["inter"])
+    assert np.array_equal(res["J"].view(np.uint64), ref["J"].view(np.uint64))
+
+
 @pytest.mark.parametrize("n,dmin", [(300, 1000), (10300, 0)])
 def test_row_lists_by_sample_and_by_row(n, dmin):
     """Rows kept as lists are summed sample by sample (their pairs sorted by the
