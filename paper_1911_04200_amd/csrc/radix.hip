@@ -165,17 +165,18 @@ __device__ __forceinline__ uint32_t status_load(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One tile = kOsNT threads x kRounds keys; threads tid < kRadix also own digit tid.
-constexpr int kOsNT = 512;
+// One tile = kOsNT threads x R keys; threads tid < kRadix also own digit tid.
+constexpr int kOsNT = 512;  // 512 x 16 keys measured best of 512 x 8/12/16 and 1024 x 16 (one block per CU)
 constexpr int kOsWaves = kOsNT / kWave;
-constexpr uint32_t kOsTile = kOsNT * kRounds;  // 8192 keys
+constexpr int kOsMaxRounds = 16;
+constexpr uint32_t kOsMaxTile = kOsNT * kOsMaxRounds;  // 8192 keys
 
-template <class K>
+template <class K, int R, bool kTable>
 __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(
     const K *__restrict__ in, K *__restrict__ out, uint64_t N, uint32_t shift, uint32_t nbits,
     const uint64_t *__restrict__ gstart, uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
     uint32_t ntiles, uint32_t *__restrict__ err) {
-    __shared__ K stage[kOsTile];
+    __shared__ K stage[kOsNT * R];
     __shared__ uint32_t wcnt[kOsWaves][kRadix];
     __shared__ uint32_t tdp[kRadix];
     __shared__ uint64_t base[kRadix];
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
     const uint64_t gs = digit ? gstart[tid] : 0;
     // while ranking, the first kOsWaves*256 words of stage are per-wave tables
     // of the lanes of the current round that have digit d
-    static_assert(kOsWaves * kRadix * sizeof(uint64_t) <= kOsTile * sizeof(K), "match tables fit the stage");
+    static_assert(kOsWaves * kRadix * sizeof(uint64_t) <= (kOsNT * R) * sizeof(K), "match tables fit the stage");
     uint64_t *T = reinterpret_cast<uint64_t *>(stage) + w * kRadix;
     // persistent: take tiles in ticket order until none is left
     for (;;) {
@@ -200,13 +201,13 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
         __syncthreads();
         const uint32_t tile = tile_sh;
         if (tile >= ntiles) break;  // uniform: every thread read the same ticket
-        const uint64_t t0 = (uint64_t)tile * kOsTile;
-        const uint64_t c1 = min(N, t0 + kOsTile);
-        const uint64_t wb = t0 + (uint64_t)w * (kOsTile / kOsWaves);
-        K key[kRounds];
-        uint32_t rank[kRounds];
+        const uint64_t t0 = (uint64_t)tile * (kOsNT * R);
+        const uint64_t c1 = min(N, t0 + (kOsNT * R));
+        const uint64_t wb = t0 + (uint64_t)w * ((kOsNT * R) / kOsWaves);
+        K key[R];
+        uint32_t rank[R];
 #pragma unroll
-        for (int j = 0; j < kRounds; ++j) {
+        for (int j = 0; j < R; ++j) {
             const uint64_t t = wb + (uint64_t)j * kWave + lane;
             key[j] = t < c1 ? in[t] : 0;
         }
@@ -219,9 +220,9 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             // afterwards (in two halves, which keeps fewer registers live).
     #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                uint32_t info[kRounds / 2];
+                uint32_t info[R / 2];
     #pragma unroll
-                for (int j = h * (kRounds / 2); j < (h + 1) * (kRounds / 2); ++j) {
+                for (int j = h * (R / 2); j < (h + 1) * (R / 2); ++j) {
                     const uint64_t t = wb + (uint64_t)j * kWave + lane;
                     const bool valid = t < c1;
                     const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
@@ -236,11 +237,11 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
                     uint32_t old = 0;
                     if (valid && before == 0) old = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(peers));
                     rank[j] = old;
-                    info[j - h * (kRounds / 2)] = (leader << 8) | before;
+                    info[j - h * (R / 2)] = (leader << 8) | before;
                 }
     #pragma unroll
-                for (int j = h * (kRounds / 2); j < (h + 1) * (kRounds / 2); ++j) {
-                    const uint32_t f = info[j - h * (kRounds / 2)];
+                for (int j = h * (R / 2); j < (h + 1) * (R / 2); ++j) {
+                    const uint32_t f = info[j - h * (R / 2)];
                     rank[j] = (uint32_t)__shfl((int)rank[j], (int)(f >> 8), kWave) + (f & 255u);
                 }
             }
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             // 64-bit keys: rank by one ballot per digit bit (fewer registers
             // than the table form, which spills with 64-bit keys)
     #pragma unroll
-            for (int j = 0; j < kRounds; ++j) {
+            for (int j = 0; j < R; ++j) {
                 const uint64_t t = wb + (uint64_t)j * kWave + lane;
                 const bool valid = t < c1;
                 const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < kRounds; ++j) {
+        for (int j = 0; j < R; ++j) {
             const uint64_t t = wb + (uint64_t)j * kWave + lane;
             if (t < c1) {
                 const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
@@ -426,7 +427,7 @@ void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, u
 namespace jas {
 
 namespace {
-template <class K>
+template <class K, int Rounds, bool Table>
 bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit, uint32_t width,
                    const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b, const char *name) {
     if (N <= 1 || hi_bit <= lo_bit) return true;
@@ -446,7 +447,7 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
     JAS_HIP(hipStreamSynchronize(s));
     for (uint32_t q = 0; q < npass; ++q)
         if (hm[q] >= (uint64_t)kValMask) return false;
-    const uint64_t ntiles = div_up(N, kOsTile);
+    const uint64_t ntiles = div_up(N, (uint64_t)kOsNT * Rounds);
     if (ntiles > 0xFFFFFFFFull) return false;
     // persistent blocks: two per CU (256 CUs) fit, never more than there are tiles
     const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 2);
@@ -465,7 +466,7 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
         check_launch("look-back reset");
         {
             JAS_TIMED(name, s);
-            k_radix_onesweep<K><<<grid, kOsNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
+            k_radix_onesweep<K, Rounds, Table><<<grid, kOsNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
                                                   ticket.p, (uint32_t)ntiles, err);
         }
         check_launch("radix scatter (look-back)");
@@ -476,16 +477,22 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
 }
 }  // namespace
 
+// 64-bit keys: 16 keys per lane, ballot ranking (the table form is no faster
+// for them and needs more registers); 32-bit pair words: table ranking.
+constexpr int kU64Rounds = 16;
+constexpr bool kU64Table = false;
+
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
                          uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
                          hipStream_t s, Budget *b) {
-    return onesweep_sort<uint64_t>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, "radix_onesweep");
+    return onesweep_sort<uint64_t, kU64Rounds, kU64Table>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b,
+                                                          "radix_onesweep");
 }
 
 bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,
                              uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
                              hipStream_t s, Budget *b) {
-    return onesweep_sort<uint32_t>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, "pair_sort");
+    return onesweep_sort<uint32_t, 16, true>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, "pair_sort");
 }
 
 }  // namespace jas
