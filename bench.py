@@ -34,7 +34,7 @@ def kernel_source_hash(kernel: str) -> str:
     src = {"radix_scatter": "radix.hip", "radix_onesweep": "radix.hip", "radix_hist": "radix.hip",
            "gram_popc": "gram.hip", "gram_mfma": "gram.hip", "list_pairs": "gram.hip",
            "pair_count": "gram.hip", "cls_count": "encode.hip", "cls_write": "encode.hip",
-           "local_cls": "encode.hip", "local_move": "encode.hip", "pair_emit": "encode.hip",
+           "local_cls": "encode.hip", "local_cls_wide": "encode.hip", "local_move": "encode.hip", "pair_emit": "encode.hip",
            "pair_sort": "radix.hip",
            "pack": "encode.hip", "build_keys": "encode.hip"}.get(kernel)
     if src is None:
@@ -58,7 +58,7 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
     if kernel == "cls_write":
         return ("hbm", (8.0 * N + 4.0 * stats["n_pairs"] + 16.0 * stats["n_shared_rows"]) / 1e9, "GB/s",
                 "8 B per key read + 4 B per shared pair + 16 B per shared row written")
-    if kernel == "local_cls":
+    if kernel in ("local_cls", "local_cls_wide"):
         shared = stats["n_pairs"] - (stats["n_rows"] - stats["n_shared_rows"])
         return ("hbm", (8.0 * N + 4.0 * shared + 16.0 * stats["n_shared_rows"]) / 1e9, "GB/s",
                 "8 B per key read + 4 B per shared pair + 16 B per shared row written")

@@ -333,18 +333,33 @@ __global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict
     }
 }
 
-__global__ void k_range_check(const uint64_t *rs, uint64_t nlc, uint32_t *err) {
-    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nlc; c += (uint64_t)gridDim.x * blockDim.x)
-        if (rs[c] == ~0ull || rs[c + 1] == ~0ull || rs[c + 1] < rs[c] || rs[c + 1] - rs[c] > kLocalCapKeys)
+// Checks every range (err |= 8 as above) and whether its keys fit 32 bits
+// once made relative to the range's first bucket: ((id - rbase) << sbits) |
+// sample, with rbase = first bucket << lowbits, needs lowbits + ceil_log2(the
+// number of bucket values spanned) + sbits bits; err |= 16 where that exceeds 32.
+__global__ void k_range_check(const uint64_t *__restrict__ K, const uint64_t *rs, uint64_t nlc, uint32_t bsh,
+                              uint32_t lowbits, uint32_t sbits, uint32_t *err) {
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nlc; c += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = rs[c], b = rs[c + 1];
+        if (a == ~0ull || b == ~0ull || b < a || b - a > kLocalCapKeys) {
             atomicOr(err, 8u);
+        } else if (b > a) {
+            const uint64_t bf = bucket_of(K[a], bsh), bl = bucket_of(K[b - 1], bsh);
+            if (lowbits + dev_ceil_log2(bl - bf + 1) + sbits > 32) atomicOr(err, 16u);
+        }
+    }
 }
 
-__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void k_local_cls(
+// KT is the LDS form of a key, relative to the range's first bucket:
+// uint32_t when every range fits 32 bits (k_range_check), else uint64_t.
+// The narrow form halves the LDS footprint, so three blocks share a CU.
+template <class KT>
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT) == 4 ? 6 : 4))) void k_local_cls(
     uint64_t *__restrict__ K, uint32_t sbits, uint64_t smask, uint32_t bsh, uint32_t lowbits,
     const uint64_t *__restrict__ rs, uint32_t nlc, uint32_t *__restrict__ cnt, int keep, uint32_t *__restrict__ Sg,
     uint64_t *__restrict__ rid_g, uint64_t *__restrict__ rptr_g, unsigned long long *__restrict__ dupc,
     unsigned long long *__restrict__ st) {
-    __shared__ uint64_t A[kLocalCapKeys];
+    __shared__ KT A[kLocalCapKeys];
     __shared__ uint32_t wcnt[kLWaves][256];
     __shared__ uint64_t T[kLWaves][256];  // per wave: lanes of the current round with digit d
     __shared__ uint32_t tdp[256];
@@ -356,7 +371,15 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
     for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&T[0][0])[i] = 0;
     const uint64_t s0 = rs[c], s1 = rs[c + 1];
     const uint32_t L = (uint32_t)(s1 - s0);  // <= kLocalCapKeys (k_range_check)
-    for (uint32_t i = tid; i < L; i += kLNT) A[i] = K[s0 + i];
+    // relative keys: key - kbase = ((id - rbase) << sbits) | sample < 2^(nb + sbits)
+    uint64_t kbase = 0;
+    uint32_t nb = 0;
+    if (L > 0) {
+        const uint64_t bf = bucket_of(K[s0], bsh), bl = bucket_of(K[s1 - 1], bsh);
+        kbase = (bf << lowbits) << sbits;  // bf > 0 only when lowbits < U <= 63
+        nb = lowbits + dev_ceil_log2(bl - bf + 1);
+    }
+    for (uint32_t i = tid; i < L; i += kLNT) A[i] = (KT)(K[s0 + i] - kbase);
     // wave w owns positions [w*seg, (w+1)*seg), 64 per round, in order
     const uint32_t seg = ((L + kLWaves - 1) / kLWaves + kWave - 1) / kWave * kWave;
     const uint32_t rounds = seg / kWave;
@@ -365,49 +388,63 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
 
     // --- finish the sort: stable LSD passes (8-bit digits) over the relative ID
     if (L > 1) {
-        const uint64_t bf = bucket_of(A[0], bsh), bl = bucket_of(A[L - 1], bsh);
-        const uint64_t rbase = bf << lowbits;  // bf > 0 only when lowbits < U <= 63
-        const uint32_t nb = lowbits + dev_ceil_log2(bl - bf + 1);  // relative IDs are < 2^nb
         for (uint32_t p = 0; p < nb; p += 8) {
+            const uint32_t dsh = sbits + p;
             for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&wcnt[0][0])[i] = 0;
-            uint64_t key[kLRounds];
-            uint32_t dig[kLRounds], rank[kLRounds], info[kLRounds];
+            KT key[kLRounds];
+            uint32_t rank[kLRounds];
 #pragma unroll
             for (uint32_t j = 0; j < kLRounds; ++j) {
                 const uint32_t t = wb + j * kWave + lane;
                 key[j] = (j < rounds && t < L) ? A[t] : 0;
-                dig[j] = (uint32_t)((((key[j] >> sbits) - rbase) >> p)) & 255u;
             }
             __syncthreads();
             // Rank within the wave: the lanes of a round with the same digit
             // find each other through T[w][d] (each ORs in its lane bit, reads
             // the set back, and clears it; one wave's LDS operations run in
-            // order), take consecutive slots after the digit's count so far,
-            // and the lowest of them adds the group to the count with one LDS
-            // atomic whose return its peers fetch later, so the rounds do not
-            // wait on each other.
+            // order, so the rounds of a half are issued back to back and
+            // their sets read afterwards), take consecutive slots after the
+            // digit's count so far, and the lowest of them adds the group to
+            // the count with one LDS atomic (in round order) whose return its
+            // peers fetch later.  rank[j] = that return | leader << 10 |
+            // lanes before << 16 until the fetch (counts per wave < 2^10).
+            constexpr uint32_t kHalf = (kLRounds + 1) / 2;
 #pragma unroll
-            for (uint32_t j = 0; j < kLRounds; ++j) {
-                if (j < rounds) {
-                    const bool valid = wb + j * kWave + lane < L;
-                    const uint32_t d = dig[j];
-                    uint64_t peers = 0;
-                    if (valid) {
+            for (uint32_t h = 0; h < 2; ++h) {
+                uint64_t peers[kHalf];
+#pragma unroll
+                for (uint32_t jj = 0; jj < kHalf; ++jj) {
+                    const uint32_t j = h * kHalf + jj;
+                    peers[jj] = 0;
+                    if (j < kLRounds && j < rounds && wb + j * kWave + lane < L) {
+                        const uint32_t d = (uint32_t)(key[j] >> dsh) & 255u;
                         atomicOr((unsigned long long *)&T[w][d], 1ull << lane);
-                        peers = __hip_atomic_load(&T[w][d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        peers[jj] = __hip_atomic_load(&T[w][d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         __hip_atomic_store(&T[w][d], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
-                    const uint32_t before = __popcll(peers & lt);
-                    const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : lane;
-                    uint32_t old = 0;
-                    if (valid && before == 0) old = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(peers));
-                    rank[j] = old;
-                    info[j] = (leader << 8) | before;
+                }
+#pragma unroll
+                for (uint32_t jj = 0; jj < kHalf; ++jj) {
+                    const uint32_t j = h * kHalf + jj;
+                    if (j < kLRounds && j < rounds) {
+                        const uint64_t pr = peers[jj];
+                        const uint32_t before = __popcll(pr & lt);
+                        const uint32_t leader = pr ? (uint32_t)__builtin_ctzll(pr) : lane;
+                        uint32_t old = 0;
+                        if (pr && before == 0) {
+                            const uint32_t d = (uint32_t)(key[j] >> dsh) & 255u;
+                            old = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(pr));
+                        }
+                        rank[j] = old | (leader << 10) | (before << 16);
+                    }
                 }
             }
 #pragma unroll
             for (uint32_t j = 0; j < kLRounds; ++j)
-                if (j < rounds) rank[j] = (uint32_t)__shfl((int)rank[j], (int)(info[j] >> 8), kWave) + (info[j] & 255u);
+                if (j < rounds) {
+                    const uint32_t f = rank[j];
+                    rank[j] = ((uint32_t)__shfl((int)f, (int)((f >> 10) & 63u), kWave) & 1023u) + (f >> 16);
+                }
             __syncthreads();
             uint32_t tc = 0;
             if (tid < 256)
@@ -426,7 +463,10 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
             __syncthreads();
 #pragma unroll
             for (uint32_t j = 0; j < kLRounds; ++j)
-                if (j < rounds && wb + j * kWave + lane < L) A[tdp[dig[j]] + wcnt[w][dig[j]] + rank[j]] = key[j];
+                if (j < rounds && wb + j * kWave + lane < L) {
+                    const uint32_t d = (uint32_t)(key[j] >> dsh) & 255u;
+                    A[tdp[d] + wcnt[w][d] + rank[j]] = key[j];
+                }
             __syncthreads();
         }
     }
@@ -439,7 +479,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
         const uint32_t t = wb + j * kWave + lane;
         bool d = false, sh_ = false, r = false;
         if (t < L) {
-            const uint64_t key = A[t], id = key >> sbits;
+            const KT key = A[t], id = key >> sbits;
             const bool first = t == 0 || A[t - 1] != key;
             const bool left = first && t > 0 && (A[t - 1] >> sbits) == id;
             bool right = false;
@@ -493,7 +533,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(4))) void 
         const bool d = (fD >> j) & 1u, sh_ = (fS >> j) & 1u, r = (fR >> j) & 1u;
         const uint64_t bd = __ballot(d), bs = __ballot(sh_), br = __ballot(r);
         if (d | sh_) {
-            const uint64_t key = A[wb + j * kWave + lane];
+            const uint64_t key = kbase + (uint64_t)A[wb + j * kWave + lane];
             const uint32_t posS = pS + __popcll(bs & lt);
             if (d && keep) K[s0 + pD + __popcll(bd & lt)] = key;
             if (sh_) Sg[s0 + posS] = (uint32_t)(key & smask);
@@ -858,13 +898,14 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         {
             JAS_TIMED("range_starts", s);
             k_range_starts<<<(uint32_t)div_up(nlc + 1, 256 / kWave), 256, 0, s>>>(keys.p, N, bsh, nlc, rs.p, errL);
-            k_range_check<<<(uint32_t)std::min<uint64_t>(div_up(nlc, 256), 4096), 256, 0, s>>>(rs.p, nlc, errL);
+            k_range_check<<<(uint32_t)std::min<uint64_t>(div_up(nlc, 256), 4096), 256, 0, s>>>(keys.p, rs.p, nlc, bsh,
+                                                                                               lowbits, sbits, errL);
         }
         check_launch("range starts");
         uint64_t herr = 0;
         JAS_HIP(hipMemcpyAsync(&herr, flags.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         JAS_HIP(hipStreamSynchronize(s));
-        if (herr == 0) {
+        if ((herr & 8u) == 0) {
             DevBuf<unsigned long long> dupc;
             DevBuf<uint32_t> cnt;
             DevBuf<uint64_t> rid_g, offD, offS, offR, stmp;
@@ -880,9 +921,15 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             uint32_t *Sg = reinterpret_cast<uint32_t *>(alt.p);
             uint64_t *rptr_g = alt.p + div_up(N, 2);
             {
-                JAS_TIMED("local_cls", s);
-                k_local_cls<<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p, (uint32_t)nlc,
-                                                           cnt.p, keep ? 1 : 0, Sg, rid_g.p, rptr_g, dupc.p, st.p);
+                JAS_TIMED(herr & 16u ? "local_cls_wide" : "local_cls", s);
+                if (herr & 16u)
+                    k_local_cls<uint64_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
+                                                                         (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
+                                                                         rid_g.p, rptr_g, dupc.p, st.p);
+                else
+                    k_local_cls<uint32_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
+                                                                         (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
+                                                                         rid_g.p, rptr_g, dupc.p, st.p);
             }
             check_launch("local classify");
             offD.alloc(nlc + 1, s, tb, true, "range offsets");

@@ -128,17 +128,19 @@ def csr(sets):
     return np.concatenate(sets).astype(np.uint64), off
 
 
-@pytest.mark.parametrize("case", ["uniform", "narrow_ids", "one_hot_id"])
+@pytest.mark.parametrize("case", ["uniform", "uniform_u24", "narrow_ids", "one_hot_id"])
 def test_bucket_ranges_and_fallback(case):
     """Keys are sorted on their top ID bits only and each range of whole buckets is
-    finished in LDS; a bucket too large for LDS (IDs crowded into a narrow range, or
-    one ID repeated many times) must take the full sort and give the same result."""
-    rng = np.random.default_rng({"uniform": 1, "narrow_ids": 2, "one_hot_id": 3}[case])
-    if case == "uniform":
-        U, n = 36, 90
-        core = rng.integers(0, 1 << 36, 4000, dtype=np.uint64)
+    finished in LDS (keys held in 32 bits relative to the range's first bucket when
+    they fit, as with U=24 here, else in 64); a bucket too large for LDS (IDs crowded
+    into a narrow range, or one ID repeated many times) must take the full sort and
+    give the same result."""
+    rng = np.random.default_rng({"uniform": 1, "uniform_u24": 4, "narrow_ids": 2, "one_hot_id": 3}[case])
+    if case.startswith("uniform"):
+        U, n = (36, 90) if case == "uniform" else (24, 90)
+        core = rng.integers(0, 1 << U, 4000, dtype=np.uint64)
         sets = [np.concatenate([rng.choice(core, int(rng.integers(0, 3000))),
-                                rng.integers(0, 1 << 36, int(rng.integers(0, 3000)), dtype=np.uint64)])
+                                rng.integers(0, 1 << U, int(rng.integers(0, 3000)), dtype=np.uint64)])
                 for _ in range(n)]
     elif case == "narrow_ids":
         U, n = 40, 60
@@ -154,22 +156,25 @@ def test_bucket_ranges_and_fallback(case):
     res, st, names = encode_timed(ids, off, U, dmin=0)
     assert_matches(res, ref)
     assert st["n_pairs"] == int(ref["card"].sum())
-    if case == "uniform":
-        assert "local_cls" in names and "host:classify_fallback" not in names
+    if case == "uniform":  # relative keys need 37 bits
+        assert "local_cls_wide" in names and "host:classify_fallback" not in names
+    elif case == "uniform_u24":  # relative keys fit 32 bits
+        assert "local_cls" in names and "local_cls_wide" not in names and "host:classify_fallback" not in names
     else:
         assert "host:classify_fallback" in names and "cls_write" in names
 
 
-@pytest.mark.parametrize("case", ["uniform", "narrow_ids"])
+@pytest.mark.parametrize("case", ["uniform", "uniform_u24", "narrow_ids"])
 def test_query_index_on_both_classification_paths(case):
     """With JAS_KEEP_IDS the distinct keys form the query index, whether the
-    ranges were finished in LDS or the full sort had to run."""
+    ranges were finished in LDS (keys held in 64 or in 32 bits there) or the
+    full sort had to run."""
     rng = np.random.default_rng(7)
-    if case == "uniform":
-        U, n = 36, 70
-        core = rng.integers(0, 1 << 36, 3000, dtype=np.uint64)
+    if case.startswith("uniform"):
+        U, n = (36, 70) if case == "uniform" else (24, 70)
+        core = rng.integers(0, 1 << U, 3000, dtype=np.uint64)
         sets = [np.concatenate([rng.choice(core, int(rng.integers(0, 2500))),
-                                rng.integers(0, 1 << 36, int(rng.integers(0, 2500)), dtype=np.uint64)])
+                                rng.integers(0, 1 << U, int(rng.integers(0, 2500)), dtype=np.uint64)])
                 for _ in range(n)]
     else:
         U, n = 40, 60
@@ -185,6 +190,7 @@ def test_query_index_on_both_classification_paths(case):
         names = set(cabi.jas_timing_report())
         cabi.jas_timing_enable(False)
     assert ("host:classify_fallback" in names) == (case == "narrow_ids")
+    assert ("local_cls_wide" in names) == (case == "uniform")
     qsets = [sets[3], sets[11][::2], np.concatenate([sets[20][:50], np.array([(1 << U) - 1], np.uint64)])]
     qi, qo = csr(qsets)
     out = jas.query(db, dev(qi), dev(qo))
