@@ -199,7 +199,7 @@ struct SortPlan {
 };
 constexpr uint64_t kBucketKeys = 512;
 constexpr int32_t kSampleMajorMaxN = 10240;  // LDS row of per-sample counters (6 bytes each); < 2^16
-constexpr uint32_t kLocalCapKeys = 6912;  // keys one LDS range can hold
+constexpr uint32_t kLocalCapKeys = 6144;  // keys one LDS range can hold
 SortPlan sort_plan(uint64_t N, uint32_t U);
 
 // Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;

@@ -164,6 +164,46 @@ def test_bucket_ranges_and_fallback(case):
         assert "host:classify_fallback" in names and "cls_write" in names
 
 
+def max_range_len(ids, off, U, stride):
+    """Longest range [first bucket edge >= c*stride, first edge >= (c+1)*stride)
+    of the keys sorted by their top ID bits, as the encoder forms them."""
+    n = off.size - 1
+    N = ids.size
+    sbits = max(1, int(np.ceil(np.log2(n))))
+    tb = min(U, int(np.ceil(np.log2(-(-N // 512)))))
+    bucket = np.sort(ids >> np.uint64(U - tb), kind="stable")
+    edges = np.flatnonzero(np.diff(bucket)) + 1
+    edges = np.concatenate([[0], edges, [N]])
+    starts = [edges[np.searchsorted(edges, min(c * stride, N))] for c in range(-(-N // stride) + 1)]
+    return int(np.max(np.diff(starts)))
+
+
+def test_shorter_ranges_when_a_bucket_is_large():
+    """Clusters of IDs make buckets of ~2500 keys: with 4096-key strides some
+    range exceeds the 6144 keys one block holds, so the encoder tries 3072 and
+    finishes in LDS all the same."""
+    rng = np.random.default_rng(11)
+    U, n = 36, 90
+    sets = []
+    for _ in range(n):
+        parts = [rng.integers(0, 1 << U, 2000, dtype=np.uint64)]
+        for k in range(8):
+            parts.append((np.uint64(k << 32) + rng.choice(1 << 20, 26, replace=False)).astype(np.uint64))
+        sets.append(np.concatenate(parts))
+    ids, off = csr(sets)
+    assert max_range_len(ids, off, U, 4096) > 6144 >= max_range_len(ids, off, U, 3072)
+    ref = oracle.all_pairs(ids, off)
+    cabi.jas_timing_report()
+    cabi.jas_timing_enable(True)
+    try:
+        res, st = gpu_all_pairs(ids, off, U)
+    finally:
+        rep = cabi.jas_timing_report()
+        cabi.jas_timing_enable(False)
+    assert_matches(res, ref)
+    assert rep["range_starts"][0] == 2 and "local_cls_wide" in rep and "host:classify_fallback" not in rep
+
+
 @pytest.mark.parametrize("case", ["uniform", "uniform_u24", "narrow_ids"])
 def test_query_index_on_both_classification_paths(case):
     """With JAS_KEEP_IDS the distinct keys form the query index, whether the
