@@ -271,46 +271,103 @@ __global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__
 }
 
 // Row-list pairs sorted by their smaller sample a: block g takes pairs
-// [g*kPairChunk, ...); for each run of one a in it, an LDS row cnt[b] counts the
+// [g*chunk, ...); for each run of one a in it, an LDS row cnt[b] counts the
 // rows holding both a and b, and each touched counter is added to row a of B
-// once (one atomic per touched pair instead of one per row and pair).
+// once (one atomic per touched pair and chunk instead of one per row and
+// pair).  Chunks of at least kPairChunk words, about kPairBlocks of them:
+// longer chunks split a sample's run fewer times, so fewer atomics.
 constexpr uint64_t kPairChunk = 16384;
+constexpr uint64_t kPairBlocks = 4096;
 
-__global__ __launch_bounds__(256) void k_pair_count(const uint32_t *__restrict__ pairs, uint64_t P, uint32_t n,
-                                                     int32_t *__restrict__ B, int upper) {
+__global__ __launch_bounds__(256) void k_pair_count(const uint32_t *__restrict__ pairs, uint64_t P, uint64_t chunk,
+                                                     uint32_t n, int32_t *__restrict__ B, int upper) {
     extern __shared__ uint32_t lds[];
     uint32_t *cnt = lds;                                         // n counters
     uint16_t *touched = reinterpret_cast<uint16_t *>(lds + n);  // n entries (n < 2^16)
     __shared__ uint32_t ntouched;
     __shared__ uint64_t seg_end;
-    const uint64_t lo = (uint64_t)blockIdx.x * kPairChunk, hi = min(P, lo + kPairChunk);
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk, hi = min(P, lo + chunk);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
     if (threadIdx.x == 0) ntouched = 0;
     __syncthreads();
     for (uint64_t s0 = lo; s0 < hi;) {
         const uint32_t a = pairs[s0] >> 16;
-        // end of the run of a inside the chunk (the chunk is sorted by a)
-        if (threadIdx.x == 0) {
-            uint64_t l = s0, h = hi;  // first position in [s0, hi) whose sample exceeds a
-            while (l < h) {
-                const uint64_t m = (l + h) >> 1;
-                if ((pairs[m] >> 16) <= a) l = m + 1;
-                else h = m;
+        // end of the run of a inside the chunk (the chunk is sorted by a): the
+        // first wave narrows [l, h] by 64 probes per step; positions before l
+        // hold samples <= a, positions from h on samples > a
+        if (threadIdx.x < kWave) {
+            const uint32_t lane = threadIdx.x;
+            uint64_t l = s0 + 1, h = hi;
+            while (h - l > kWave) {
+                const uint64_t step = (h - l) / kWave;  // >= 1; probe 64 is l + 64*step <= h
+                const uint64_t m = l + (lane + 1) * step;
+                const uint64_t gt = __ballot(m >= h || (pairs[m] >> 16) > a);
+                if (gt == 0) {
+                    l = l + kWave * step + 1;
+                } else {
+                    const uint32_t k = (uint32_t)__builtin_ctzll(gt);  // probe k+1 is the first above
+                    h = min(h, l + (k + 1) * step);
+                    if (k > 0) l = l + k * step + 1;
+                }
             }
-            seg_end = l;
+            const uint64_t m = l + lane;
+            const uint64_t gt = __ballot(m < h && (pairs[m] >> 16) > a);
+            if (lane == 0) seg_end = gt ? l + __builtin_ctzll(gt) : h;
         }
         __syncthreads();
         const uint64_t s1 = seg_end;
-        for (uint64_t p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
-            const uint32_t b = pairs[p] & 0xFFFFu;
-            if (atomicAdd(&cnt[b], 1u) == 0) touched[atomicAdd(&ntouched, 1u)] = (uint16_t)b;
+        // A long run (at least n/8 words) counts without return and then
+        // scans its whole LDS row; a short one keeps a list of the counters it
+        // touched.  Words are read 16 bytes at a time (four per thread in
+        // flight); the buffer is 16-byte aligned, the unaligned ends by word.
+        const bool long_run = (s1 - s0) * 8 >= n;  // block-uniform
+        auto count = [&](uint32_t w) {
+            const uint32_t b = w & 0xFFFFu;
+            if (long_run) {
+                __hip_atomic_fetch_add(&cnt[b], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else if (atomicAdd(&cnt[b], 1u) == 0) {
+                touched[atomicAdd(&ntouched, 1u)] = (uint16_t)b;
+            }
+        };
+        const uint64_t va = min(s1, (s0 + 3) & ~uint64_t(3));  // first aligned word (or s1)
+        const uint64_t vb = max(va, s1 & ~uint64_t(3));        // end of the aligned body
+        for (uint64_t p = s0 + threadIdx.x; p < va; p += blockDim.x) count(pairs[p]);
+        for (uint64_t p = vb + threadIdx.x; p < s1; p += blockDim.x) count(pairs[p]);
+        const uint4 *pv = reinterpret_cast<const uint4 *>(pairs);
+        const uint64_t q1 = vb / 4;
+        for (uint64_t q0 = va / 4; q0 < q1; q0 += 4 * (uint64_t)blockDim.x) {
+            uint4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t q = q0 + (uint64_t)u * blockDim.x + threadIdx.x;
+                if (q < q1) x[u] = pv[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (q0 + (uint64_t)u * blockDim.x + threadIdx.x < q1) {
+                    count(x[u].x);
+                    count(x[u].y);
+                    count(x[u].z);
+                    count(x[u].w);
+                }
+            }
         }
         __syncthreads();
-        const uint32_t nt = ntouched;
-        for (uint32_t k = threadIdx.x; k < nt; k += blockDim.x) {
-            const uint32_t b = touched[k];
-            atomicAdd(B + out_index(a, b, n, upper), (int32_t)cnt[b]);
-            cnt[b] = 0;
+        if (long_run) {
+            for (uint32_t b = a + 1 + threadIdx.x; b < n; b += blockDim.x) {
+                const uint32_t c = cnt[b];
+                if (c) {
+                    atomicAdd(B + out_index(a, b, n, upper), (int32_t)c);
+                    cnt[b] = 0;
+                }
+            }
+        } else {
+            const uint32_t nt = ntouched;
+            for (uint32_t k = threadIdx.x; k < nt; k += blockDim.x) {
+                const uint32_t b = touched[k];
+                atomicAdd(B + out_index(a, b, n, upper), (int32_t)cnt[b]);
+                cnt[b] = 0;
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) ntouched = 0;
@@ -449,12 +506,13 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         check_launch("gram");
     }
     if (db->n_list > 0 && db->n_lpairs > 0) {
-        const uint64_t blocks = div_up(db->n_lpairs, kPairChunk);
+        const uint64_t chunk = std::max<uint64_t>(kPairChunk, div_up(db->n_lpairs, kPairBlocks));
+        const uint64_t blocks = div_up(db->n_lpairs, chunk);
         if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "row lists too long");
         const size_t lds = (size_t)n * (sizeof(uint32_t) + sizeof(uint16_t));
         {
             JAS_TIMED("pair_count", s);
-            k_pair_count<<<(uint32_t)blocks, 256, lds, s>>>(db->pairs.p, db->n_lpairs, n, B, upper);
+            k_pair_count<<<(uint32_t)blocks, 256, lds, s>>>(db->pairs.p, db->n_lpairs, chunk, n, B, upper);
         }
         check_launch("row-list pairs");
     } else if (db->n_list > 0) {

@@ -246,12 +246,14 @@ def test_query_index_on_both_classification_paths(case):
 @pytest.mark.parametrize("n,dmin", [(300, 1000), (10300, 0)])
 def test_row_lists_by_sample_and_by_row(n, dmin):
     """Rows kept as lists are summed sample by sample (their pairs sorted by the
-    smaller sample, an LDS row of counters per sample, up to 10240 samples) or,
-    for more samples, pair by pair per row."""
+    smaller sample, an LDS row of counters per sample, up to 10240 samples; long
+    and short runs of one sample take different flushes) or, for more samples,
+    pair by pair per row."""
     rng = np.random.default_rng(n)
     pool = rng.choice(1 << 20, 3000, replace=False).astype(np.uint64)
     sets = [np.unique(rng.choice(pool, int(rng.integers(0, 7)))) for _ in range(n)]
     sets[5] = pool[:40].copy()  # one sample in many rows
+    sets[0] = pool[:2500].copy()  # a long run of pairs (0, b): counted without a touched list
     ids, off = csr(sets)
     ref = oracle.all_pairs(ids, off)
     res, st = gpu_all_pairs(ids, off, 20, 0, dmin)
