@@ -762,9 +762,33 @@ __global__ void k_list_npairs(const uint64_t *Lrow, const uint64_t *row_ptr, uin
 
 // One lane per row: a wave's 64 consecutive rows own one contiguous stretch of
 // the output, which is assembled in LDS and written out coalesced (written
-// directly when it exceeds the stage); per-block LDS totals of the sort
-// digits of a (digit q = bits [16 + width*q, 16 + width*(q+1)) of the word).
-constexpr uint32_t kEmitStage = 2048;  // words per wave
+// directly when it exceeds the stage).  The rows' samples are one span of the
+// sample array (the rows ascend), read into LDS with coalesced loads first
+// when it fits, so the pair loops wait on LDS rather than on memory.  Per-block
+// LDS totals of the sort digits of a (digit q = bits [16 + width*q, 16 +
+// width*(q+1)) of the word).
+// Stage sizes measured best of 256..3072: larger ones cost more occupancy
+// than they save in unstaged waves.
+constexpr uint32_t kEmitStage = 1024;  // output words per wave
+constexpr uint32_t kEmitIn = 512;      // sample entries per wave
+constexpr uint32_t kPairPasses = 2;   // 16 sample bits, 8-bit digits
+
+template <bool kStagedIn, bool kStagedOut>
+__device__ __forceinline__ void emit_row_pairs(const uint32_t *__restrict__ ls, const uint32_t *sin, uint64_t span0,
+                                               uint64_t e0, uint64_t e1, uint64_t o, uint32_t *st,
+                                               uint32_t *__restrict__ pairs, uint64_t base, uint32_t (*gh)[256],
+                                               uint32_t npass, uint32_t width, uint32_t dmask) {
+    for (uint64_t i = e0; i + 1 < e1; ++i) {
+        const uint32_t a = kStagedIn ? sin[i - span0] : ls[i];
+        const uint32_t m = (uint32_t)(e1 - i - 1);  // pairs with a as the smaller sample
+        for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(a >> (width * q)) & dmask], m);
+        for (uint64_t j = i + 1; j < e1; ++j, ++o) {
+            const uint32_t v = (a << 16) | (kStagedIn ? sin[j - span0] : ls[j]);
+            if (kStagedOut) st[o] = v;
+            else pairs[base + o] = v;
+        }
+    }
+}
 
 __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ Lrow,
                                                     const uint64_t *__restrict__ row_ptr,
@@ -772,17 +796,20 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
                                                     const uint64_t *__restrict__ po,
                                                     uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
                                                     unsigned long long *__restrict__ ghist) {
-    __shared__ uint32_t gh[kMaxPasses][256];
+    __shared__ uint32_t gh[kPairPasses][256];
     __shared__ uint32_t stg[256 / kWave][kEmitStage];
+    __shared__ uint32_t sinb[256 / kWave][kEmitIn];
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint32_t dmask = (1u << width) - 1u;
 #pragma unroll
-    for (int k = 0; k < kMaxPasses; ++k) gh[k][tid] = 0;
+    for (int k = 0; k < kPairPasses; ++k) gh[k][tid] = 0;
     __syncthreads();
     uint32_t *st = stg[w];
+    uint32_t *sin = sinb[w];
     for (uint64_t r0 = ((uint64_t)blockIdx.x * (256 / kWave) + w) * kWave; r0 < QL;
          r0 += (uint64_t)gridDim.x * 256) {
         const uint64_t r = r0 + lane;
+        const uint32_t last = (uint32_t)(min(r0 + kWave, QL) - 1 - r0);  // lane of the wave's last row
         uint64_t e0 = 0, e1 = 0;
         if (r < QL) {
             const uint64_t rr = Lrow[r];
@@ -792,21 +819,25 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
         const uint64_t base = po[r0];
         const uint64_t total = po[min(r0 + kWave, QL)] - base;
         const uint64_t my = r < QL ? po[r] - base : 0;
-        const bool staged = total <= kEmitStage;  // wave-uniform
-        uint64_t o = my;
-        for (uint64_t i = e0; i + 1 < e1; ++i) {
-            const uint32_t a = ls[i];
-            const uint32_t m = (uint32_t)(e1 - i - 1);  // pairs with a as the smaller sample
-            for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(a >> (width * q)) & dmask], m);
-            for (uint64_t j = i + 1; j < e1; ++j, ++o) {
-                const uint32_t v = (a << 16) | ls[j];
-                if (staged) st[o] = v;
-                else pairs[base + o] = v;
-            }
-        }
-        if (staged) {
+        const uint64_t span0 = __shfl(e0, 0, kWave), span1 = __shfl(e1, (int)last, kWave);
+        const bool staged_in = span1 - span0 <= kEmitIn;  // wave-uniform
+        const bool staged = total <= kEmitStage;          // wave-uniform
+        if (staged_in) {
+            for (uint64_t k = lane; k < span1 - span0; k += kWave) sin[k] = ls[span0 + k];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
+        }
+        if (staged_in && staged)
+            emit_row_pairs<true, true>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
+        else if (staged_in)
+            emit_row_pairs<true, false>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
+        else if (staged)
+            emit_row_pairs<false, true>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
+        else
+            emit_row_pairs<false, false>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (staged) {
             for (uint32_t k = lane; k < total; k += kWave) pairs[base + k] = st[k];
             __builtin_amdgcn_wave_barrier();
         }
@@ -1191,6 +1222,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         tmp2.release();
         const uint32_t sb = std::max<uint32_t>(1, ceil_log2_u64((uint64_t)n));
         const uint32_t npass = (sb + 7) / 8, width = (sb + npass - 1) / npass;
+        if (npass > kPairPasses) fail(JAS_EUNSUPPORTED, "row-list pairs: too many sample bits");
         DevBuf<uint32_t> pk, palt, perr;
         DevBuf<unsigned long long> gh;
         pk.alloc(P + 2, s, &db->budget, false, "row-list pairs");

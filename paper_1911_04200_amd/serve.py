@@ -164,14 +164,19 @@ class Server:
         t0 = time.perf_counter()
         workers = [threading.Thread(target=self._worker, args=(s, t0, finished), daemon=True)
                    for s in range(self.slots)]
+        if arrivals is None:  # the whole batch is queued before any slot takes work
+            for r in requests:
+                r.arrival = 0.0
+                self.queue.append(r)
         for w in workers:
             w.start()
-        for i, r in enumerate(requests):
-            r.arrival = 0.0 if arrivals is None else arrivals[i]
-            now = time.perf_counter() - t0
-            if r.arrival > now:
-                time.sleep(r.arrival - now)
-            self.submit(r)
+        if arrivals is not None:
+            for i, r in enumerate(requests):
+                r.arrival = arrivals[i]
+                now = time.perf_counter() - t0
+                if r.arrival > now:
+                    time.sleep(r.arrival - now)
+                self.submit(r)
         self.close()
         for w in workers:
             w.join()

@@ -72,14 +72,20 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
     for r in reqs:
         r.B = r.q_card = r.den = r.J = None
     mixed = serve.Server(db, slots=4, max_batch_sets=32)
-    done = mixed.run(reqs, serve.poisson_arrivals(len(reqs), 400.0, 1))
-    assert len(done) == len(reqs)
-    assert max(r.batch_size for r in reqs) > 1, "no request was batched with another"
-    for r in reqs:
-        B, qc, den, J = solo[r.rid]
-        assert np.array_equal(r.B, B) and np.array_equal(r.q_card, qc) and np.array_equal(r.den, den)
-        assert np.array_equal(r.J.view(np.uint64), J.view(np.uint64))
+    # Poisson arrivals (batching depends on timing), then a closed batch (all
+    # queued before the slots start, so calls take several requests)
+    for arrivals in (serve.poisson_arrivals(len(reqs), 400.0, 1), None):
+        done = mixed.run(reqs, arrivals)
+        assert len(done) == len(reqs)
+        if arrivals is None:
+            assert max(r.batch_size for r in reqs) > 1, "no request was batched with another"
+        for r in reqs:
+            B, qc, den, J = solo[r.rid]
+            assert np.array_equal(r.B, B) and np.array_equal(r.q_card, qc) and np.array_equal(r.den, den)
+            assert np.array_equal(r.J.view(np.uint64), J.view(np.uint64))
+            r.B = r.q_card = r.den = r.J = None
     # and against the oracle for a few requests
+    mixed.run(reqs[:3])
     for r in reqs[:3]:
         ref = oracle.cross(r.ids, r.offsets, ids, off)
         assert np.array_equal(r.B, ref["inter"]) and np.array_equal(r.J, ref["J"])
