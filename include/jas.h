@@ -54,6 +54,8 @@ typedef enum {
 #define JAS_FORCE_POPCOUNT 0x20u /* jas_gram: every packed tile on the AND+popcount kernel */
 #define JAS_FORCE_MFMA 0x40u    /* jas_gram: every packed tile on the int8 MFMA kernel */
 #define JAS_TUNE 0x80u          /* jas_gram: time the MFMA tile variants on this db first (see jas_gram) */
+/* jas_gram: run MFMA tile variant v, 0 <= v < jas_gram_variants() (bits 16..23 hold v + 1) */
+#define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)
 
 typedef struct jas_db jas_db; /* opaque, library-owned, device-resident encoding of A */
 
@@ -114,7 +116,7 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
  *  J     double, same layout as B: C_ij == 0 ? 1.0 : (double)B_ij / (double)C_ij,
  *        IEEE binary64 round-to-nearest; may be NULL.
  *  flags JAS_UPPER, JAS_FORCE_POPCOUNT / JAS_FORCE_MFMA (at most one), JAS_HOST_PTRS,
- *        JAS_TUNE.
+ *        JAS_TUNE, JAS_GRAM_VARIANT(v) (not with JAS_TUNE or JAS_FORCE_POPCOUNT).
  * The result does not depend on flags other than the layout: every tile path
  * is exact.  Does not synchronise unless JAS_HOST_PTRS or JAS_TUNE is given.
  * JAS_TUNE (autotuner): before the product, the MFMA Gram runs once in each of
@@ -122,10 +124,15 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
  * events on the stream (synchronising); the fastest is kept, in this process,
  * for every later db on the device with the same n and the same power of two
  * of word rows, and is used by later calls without the flag.  Not capturable
- * in a HIP graph; calls without it are.
+ * in a HIP graph; calls without it are.  JAS_GRAM_VARIANT(v) runs variant v
+ * instead of the kept or default choice (EINVAL for v out of range).
  */
 jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t *B, int64_t *card, int64_t *den,
                     double *J);
+
+/* Number of MFMA tile variants jas_gram can run (tile shape, word rows per
+ * step, K split); variant indices are stable within one build of the library. */
+int32_t jas_gram_variants(void);
 
 /*
  * jas_query -- similarity of nq query sets against every encoded sample:

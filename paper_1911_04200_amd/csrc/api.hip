@@ -92,6 +92,8 @@ const char *jas_version(void) { return "jas 0.1 (gfx950)"; }
 
 int32_t jas_db_size(const jas_db *db) { return db ? db->n : -1; }
 
+int32_t jas_gram_variants(void) { return jas::gram_variants(); }
+
 jas_status jas_db_stats(const jas_db *db, jas_encode_stats *stats) {
     return guard([&] {
         if (!db || !stats) fail(JAS_EINVAL, "jas_db_stats: null argument");
@@ -231,6 +233,9 @@ jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t 
         if (!B && db->n > 0) fail(JAS_EINVAL, "jas_gram: B is NULL");
         if ((flags & JAS_FORCE_POPCOUNT) && (flags & JAS_FORCE_MFMA))
             fail(JAS_EINVAL, "jas_gram: JAS_FORCE_POPCOUNT and JAS_FORCE_MFMA are exclusive");
+        const uint32_t var = (flags >> 16) & 0xFFu;
+        if (var && (var > (uint32_t)gram_variants() || (flags & (JAS_TUNE | JAS_FORCE_POPCOUNT))))
+            fail(JAS_EINVAL, "jas_gram: bad JAS_GRAM_VARIANT");
         hipStream_t s = (hipStream_t)hip_stream;
         const uint64_t n = (uint64_t)db->n;
         const uint64_t len = (flags & JAS_UPPER) ? n * (n + 1) / 2 : n * n;

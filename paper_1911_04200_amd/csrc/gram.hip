@@ -258,6 +258,111 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WP
             }
 }
 
+// 256 x 256 tiles: four waves (2 x 2), each a 128 x 128 block of 16 MFMA
+// tiles with its accumulators in the AGPRs (one wave per SIMD).  Against the
+// 128 x 128 kernel this halves the words loaded per multiply (each column
+// slab feeds twice the tiles) and expands 8 operands per 16 MFMAs instead of
+// 6 per 8.  Columns at or past ldw (n rounded to 128) are clamped to a valid
+// column; their products land outside j < n and are dropped.
+constexpr int kWideT = 256;
+constexpr int kWideNT = 256;
+
+template <int STEP>
+__global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gram_mfma_wide(
+    const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
+    int32_t *__restrict__ B, int upper) {
+    __shared__ unsigned long long lut[256];
+    const uint64_t split = blockIdx.y;
+    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    while (p >= rowlen) {
+        p -= rowlen;
+        ++I;
+        --rowlen;
+    }
+    const uint32_t Jt = I + p;
+    const uint64_t k0 = split * kper;
+    const uint64_t k1 = min(H, k0 + kper);
+    if (k0 >= k1) return;
+    fill_byte_lut(lut);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t lm = lane & 31, lg = lane >> 5;
+    const uint32_t I0 = I * kWideT + 128 * (wv >> 1), J0 = Jt * kWideT + 128 * (wv & 1);
+    if (I0 >= J0 + 128) return;  // the wave's block lies below the diagonal (no syncs follow)
+    v16i acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0;
+    uint64_t ca[4], cb[4];  // this lane's columns, clamped below ldw
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        ca[x] = min<uint64_t>(I0 + lm + 32 * x, ldw - 1);
+        cb[x] = min<uint64_t>(J0 + lm + 32 * x, ldw - 1);
+    }
+    uint64_t a[STEP][4], b[STEP][4];
+#pragma unroll
+    for (int u = 0; u < STEP; ++u) {
+        const uint64_t ku = min(k0 + u, k1 - 1);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            a[u][x] = W[ku * ldw + ca[x]];
+            b[u][x] = W[ku * ldw + cb[x]];
+        }
+    }
+    for (uint64_t k = k0; k < k1; k += STEP) {
+        uint64_t na[STEP][4], nb[STEP][4];
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+            const uint64_t kn = min(k + STEP + u, k1 - 1);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                na[u][x] = W[kn * ldw + ca[x]];
+                nb[u][x] = W[kn * ldw + cb[x]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+            if (k + u >= k1) break;  // wave-uniform: the tail of the range
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t sh = 32 * h + 16 * lg;
+                v4i va[4], vb[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) va[x] = bits16_lut(lut, (uint32_t)(a[u][x] >> sh));
+#pragma unroll
+                for (int y = 0; y < 4; ++y) vb[y] = bits16_lut(lut, (uint32_t)(b[u][y] >> sh));
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(va[x], vb[y], acc[x][y], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < STEP; ++u)
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                a[u][x] = na[u][x];
+                b[u][x] = nb[u][x];
+            }
+    }
+    // accumulator r of lane (lg, lm) holds row 8*(r/4) + 4*lg + r%4, column lm of each 32 x 32 tile
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t i = I0 + 32 * x + 8 * (r >> 2) + 4 * lg + (r & 3);
+                const uint32_t j = J0 + 32 * y + lm;
+                const int32_t v = acc[x][y][r];
+                if (v && i < j && j < n) atomicAdd(B + out_index(i, j, n, upper), v);
+            }
+}
+
 // Row lists: one thread per row, every pair of its (ascending) samples.
 __global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls, uint64_t nl,
                              uint32_t n, int32_t *__restrict__ B, int upper) {
@@ -408,8 +513,12 @@ __global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ 
 struct GramVariant {
     int step;
     uint64_t want_blocks;
+    bool wide;  // 256 x 256 tiles (k_gram_mfma_wide)
 };
-constexpr GramVariant kVariants[] = {{4, 2048}, {2, 2048}, {4, 1024}, {4, 4096}, {2, 4096}, {2, 1024}};
+// (wide variants with 2 word rows per step or at most 2048 blocks measured
+// slower on both dense workloads and are not listed)
+constexpr GramVariant kVariants[] = {{4, 2048, false}, {2, 2048, false}, {4, 1024, false}, {4, 4096, false},
+                                     {2, 4096, false}, {2, 1024, false}, {4, 4096, true},   {4, 8192, true}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 std::mutex g_tune_mu;
@@ -430,6 +539,16 @@ void k_split(uint64_t H, uint64_t np, uint64_t want, uint64_t &kper, uint64_t &s
 
 void launch_mfma(const jas_db *db, int v, hipStream_t s, int32_t *B, bool upper) {
     const uint32_t n = (uint32_t)db->n;
+    if (kVariants[v].wide) {
+        const uint32_t nt = (uint32_t)div_up(n, kWideT);
+        const uint64_t np = (uint64_t)nt * (nt + 1) / 2;
+        uint64_t kper, splits;
+        k_split(db->H, np, kVariants[v].want_blocks, kper, splits);
+        const uint64_t ldw = div_up(n, 128) * 128;
+        dim3 grid((uint32_t)np, (uint32_t)splits);
+        k_gram_mfma_wide<4><<<grid, kWideNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);  // 4 rows per step
+        return;
+    }
     const uint32_t nt = (uint32_t)div_up(n, kT);
     const uint64_t np = (uint64_t)nt * (nt + 1) / 2;
     uint64_t kper, splits;
@@ -443,6 +562,8 @@ void launch_mfma(const jas_db *db, int v, hipStream_t s, int32_t *B, bool upper)
 }
 
 }  // namespace
+
+int32_t gram_variants() { return kNumVariants; }
 
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J) {
     const uint32_t n = (uint32_t)db->n;
@@ -467,7 +588,10 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         } else {
             const auto key = std::make_tuple(db->device, n, ceil_log2_u64(db->H));
             int v = 0;
-            if (flags & JAS_TUNE) {
+            const uint32_t forced = (flags >> 16) & 0xFFu;  // JAS_GRAM_VARIANT(v): v + 1
+            if (forced) {
+                v = (int)forced - 1;
+            } else if (flags & JAS_TUNE) {
                 // time every variant on this db (each adds into B, which is cleared again after)
                 JAS_HOST_TIMED("gram_tune");
                 hipEvent_t e0, e1;

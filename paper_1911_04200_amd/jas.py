@@ -24,12 +24,18 @@ JAS_FORCE_POPCOUNT = 0x20
 JAS_FORCE_MFMA = 0x40
 JAS_TUNE = 0x80
 
+
+def JAS_GRAM_VARIANT(v: int) -> int:
+    """jas_gram flag: run MFMA tile variant v (0 <= v < jas_gram_variants())."""
+    return (int(v) + 1) << 16
+
 STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERFLOW", -4: "JAS_EDEVICE",
                 -6: "JAS_EUNSUPPORTED"}
 
 # Every symbol include/jas.h declares.
-EXPORTS = sorted(["jas_encode", "jas_gram", "jas_query", "jas_query_workspace_bytes", "jas_db_size", "jas_db_stats",
-                  "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable", "jas_timing_report", "jas_trim"])
+EXPORTS = sorted(["jas_encode", "jas_gram", "jas_gram_variants", "jas_query", "jas_query_workspace_bytes",
+                  "jas_db_size", "jas_db_stats", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
+                  "jas_timing_report", "jas_trim"])
 
 
 class JasError(RuntimeError):
@@ -84,6 +90,8 @@ def load(path: str = LIB_PATH):
     lib.jas_query_workspace_bytes.restype = u64
     lib.jas_db_size.argtypes = [vp]
     lib.jas_db_size.restype = i32
+    lib.jas_gram_variants.argtypes = []
+    lib.jas_gram_variants.restype = i32
     lib.jas_db_stats.argtypes = [vp, ctypes.POINTER(jas_encode_stats)]
     lib.jas_db_stats.restype = ctypes.c_int
     lib.jas_db_free.argtypes = [vp]
@@ -182,6 +190,10 @@ def jas_query_workspace_bytes(db, nq: int, n_q_ids: int) -> int:
 
 def jas_db_size(db) -> int:
     return int(load().jas_db_size(_h(db)))
+
+
+def jas_gram_variants() -> int:
+    return int(load().jas_gram_variants())
 
 
 def jas_db_stats(db) -> dict:

@@ -36,6 +36,13 @@ def test_flag_and_status_values_match_the_header():
         assert getattr(jas, name) == int(value), name
 
 
+def test_gram_variant_flag_matches_the_header():
+    text = open(os.path.join(ROOT, "include", "jas.h")).read()
+    assert "#define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)" in text
+    assert jas.JAS_GRAM_VARIANT(0) == 1 << 16 and jas.JAS_GRAM_VARIANT(9) == 10 << 16
+    assert jas.jas_gram_variants() >= 2
+
+
 def test_version():
     assert "gfx950" in jas.jas_version()
 

@@ -382,6 +382,27 @@ def test_gram_autotuner_keeps_results_exact():
     assert_matches({k: v.cpu().numpy() for k, v in tuned.items()}, ref, upper=True)
 
 
+@pytest.mark.parametrize("n", [130, 300, 513])
+def test_every_mfma_tile_variant_is_exact(n):
+    """Each MFMA tile variant (128 x 128 and 256 x 256 tiles, word rows per
+    step, K split) gives the oracle's B, C and J, with ragged column tiles."""
+    spec = synth.scaled(synth.workload("precision"), n=n, size_scale=0.01, pool_scale=0.01)
+    ids, off = synth.generate(spec)
+    db, st = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, dense_min_degree=2)
+    assert st["n_word_rows"] > 0
+    ref = oracle.all_pairs(ids, off)
+    nv = cabi.jas_gram_variants()
+    assert nv >= 2
+    for v in range(nv):
+        for upper in (False, True):
+            out = jas.gram(db, upper=upper, flags=cabi.JAS_GRAM_VARIANT(v))
+            torch.cuda.synchronize()
+            assert_matches({k: x.cpu().numpy() for k, x in out.items()}, ref, upper=upper)
+    with pytest.raises(cabi.JasError):
+        jas.gram(db, flags=cabi.JAS_GRAM_VARIANT(nv))
+    db.close()
+
+
 def test_repeat_runs_are_identical():
     spec = synth.scaled(synth.workload("precision"), n=300, size_scale=0.01, pool_scale=0.01)
     ids, off = synth.generate(spec)
