@@ -605,14 +605,13 @@ __global__ __launch_bounds__(kNT) void k_deg_hist(const uint64_t *row_ptr, uint6
 
 // Rows: degree split.
 __global__ __launch_bounds__(kNT) void k_row_flags(const uint64_t *row_ptr, uint64_t R, uint32_t dmin,
-                                                    uint32_t *fDense, uint32_t *fList, unsigned long long *st) {
+                                                    uint32_t *fDense, unsigned long long *st) {
     __shared__ uint64_t sh[kWaves];
     uint64_t lp = 0;
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t d = row_ptr[r + 1] - row_ptr[r];
         const bool dense = d >= dmin;
         fDense[r] = dense;
-        fList[r] = !dense;
         if (!dense) lp += d * (d - 1) / 2;
     }
     uint64_t tot;
@@ -620,11 +619,13 @@ __global__ __launch_bounds__(kNT) void k_row_flags(const uint64_t *row_ptr, uint
     if (threadIdx.x == 0 && tot) atomicAdd(&st[ST_LISTPAIRS], (unsigned long long)tot);
 }
 
-__global__ void k_row_compact(uint64_t R, const uint32_t *fDense, const uint64_t *pDense, const uint64_t *pList,
-                              uint64_t *Drow, uint64_t *Lrow) {
+// A list row's position is r minus the packed rows before it.
+__global__ void k_row_compact(uint64_t R, const uint32_t *fDense, const uint64_t *pDense, uint64_t *Drow,
+                              uint64_t *Lrow) {
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
-        if (fDense[r]) Drow[pDense[r]] = r;
-        else Lrow[pList[r]] = r;
+        const uint64_t pd = pDense[r];
+        if (fDense[r]) Drow[pd] = r;
+        else Lrow[r - pd] = r;
     }
 }
 
@@ -1114,22 +1115,19 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     }
     db->stats.dense_min_degree = db->dmin;
     if (R > 0) {
-        DevBuf<uint32_t> fDense, fList;
-        DevBuf<uint64_t> pDense, pList, tmp;
+        DevBuf<uint32_t> fDense;
+        DevBuf<uint64_t> pDense, tmp;
         fDense.alloc(R, s, tb, true, "row flags");
-        fList.alloc(R, s, tb, true, "row flags");
         launch_1d(R, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("row_flags", st_);
-                k_row_flags<<<b, 256, 0, st_>>>(rptrp, R, db->dmin, fDense.p, fList.p, st.p);
+                k_row_flags<<<b, 256, 0, st_>>>(rptrp, R, db->dmin, fDense.p, st.p);
             }
         });
         check_launch("row flags");
         pDense.alloc(R + 1, s, tb, true, "row scan");
-        pList.alloc(R + 1, s, tb, true, "row scan");
         tmp.alloc(scan_tmp_elems(R), s, tb, true, "scan scratch");
         scan_excl_u32(fDense.p, pDense.p, R, tmp.p, s);
-        scan_excl_u32(fList.p, pList.p, R, tmp.p, s);
         QD = to_host_u64(pDense.p + R, s);
         QL = R - QD;
         Drow.alloc(QD, s, tb, true, "packed rows");
@@ -1137,7 +1135,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         launch_1d(R, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("row_compact", st_);
-                k_row_compact<<<b, 256, 0, st_>>>(R, fDense.p, pDense.p, pList.p, Drow.p, Lrow.p);
+                k_row_compact<<<b, 256, 0, st_>>>(R, fDense.p, pDense.p, Drow.p, Lrow.p);
             }
         });
         check_launch("row compact");
