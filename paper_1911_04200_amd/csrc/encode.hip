@@ -697,16 +697,30 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
             for (uint32_t i = tid; i < cn; i += kNT) lw[i] = 0;
             __syncthreads();
             const uint64_t P = rstart[kWave];
-            for (uint64_t p = tid; p < P; p += kNT) {
-                // row t of the word: largest t with rstart[t] <= p
-                uint32_t lo = 0, hi = kWave - 1;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (rstart[mid] <= p) lo = mid;
-                    else hi = mid - 1;
+            if (P >= (uint64_t)kWave * kWave) {
+                // long rows (64 samples or more on average): the lanes of a
+                // wave walk one row at a time
+                const uint32_t wv = tid / kWave;
+                for (uint32_t t = wv; t < kWave; t += kNT / kWave) {
+                    const uint64_t rb = rbase[t], dg = rstart[t + 1] - rstart[t];
+                    for (uint64_t e = lane; e < dg; e += kWave) {
+                        const uint64_t s = S[rb + e];
+                        if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], 1ull << t);
+                    }
                 }
-                const uint64_t s = S[rbase[lo] + (p - rstart[lo])];
-                if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], 1ull << lo);
+            } else {
+                // short rows: one thread per entry, its row found by binary search
+                for (uint64_t p = tid; p < P; p += kNT) {
+                    // row t of the word: largest t with rstart[t] <= p
+                    uint32_t lo = 0, hi = kWave - 1;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (rstart[mid] <= p) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const uint64_t s = S[rbase[lo] + (p - rstart[lo])];
+                    if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], 1ull << lo);
+                }
             }
             __syncthreads();
             uint32_t z = 0;

@@ -243,6 +243,23 @@ def test_query_index_on_both_classification_paths(case):
     assert np.array_equal(res["J"].view(np.uint64), ref["J"].view(np.uint64))
 
 
+def test_pack_long_and_short_rows():
+    """Word rows whose 64 rows hold 64 samples or more on average are packed a
+    row per wave, the others an entry per thread; both must give the oracle."""
+    rng = np.random.default_rng(21)
+    n = 200
+    core = rng.choice(1 << 30, 700, replace=False).astype(np.uint64)  # rows of degree ~150-200
+    sets = [np.concatenate([rng.choice(core, int(rng.integers(500, 700)), replace=False),
+                            rng.integers(0, 1 << 30, int(rng.integers(0, 400)), dtype=np.uint64)])
+            for _ in range(n)]
+    ids, off = csr(sets)
+    ref = oracle.all_pairs(ids, off)
+    for dmin in (2, 100):
+        res, st = gpu_all_pairs(ids, off, 30, 0, dmin)
+        assert st["n_packed_rows"] > 0
+        assert_matches(res, ref)
+
+
 @pytest.mark.parametrize("n,dmin", [(300, 1000), (10300, 0)])
 def test_row_lists_by_sample_and_by_row(n, dmin):
     """Rows kept as lists are summed sample by sample (their pairs sorted by the
