@@ -604,28 +604,61 @@ __global__ __launch_bounds__(kNT) void k_deg_hist(const uint64_t *row_ptr, uint6
 }
 
 // Rows: degree split.
-__global__ __launch_bounds__(kNT) void k_row_flags(const uint64_t *row_ptr, uint64_t R, uint32_t dmin,
-                                                    uint32_t *fDense, unsigned long long *st) {
+// Row split by degree in two passes over tiles of kSplitTile rows (8
+// consecutive rows per thread): k_row_count counts each tile's packed rows
+// (degree >= dmin) and the list rows' pairs; after a scan of the tile counts
+// k_row_split places every row: packed row r at its tile's offset plus the
+// packed rows before it in the tile, list row r at r minus the packed rows
+// before it.
+constexpr uint32_t kSplitPer = 8;
+constexpr uint64_t kSplitTile = (uint64_t)kNT * kSplitPer;
+
+__global__ __launch_bounds__(kNT) void k_row_count(const uint64_t *__restrict__ row_ptr, uint64_t R, uint32_t dmin,
+                                                    uint32_t *__restrict__ tcnt, unsigned long long *st) {
     __shared__ uint64_t sh[kWaves];
-    uint64_t lp = 0;
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t d = row_ptr[r + 1] - row_ptr[r];
-        const bool dense = d >= dmin;
-        fDense[r] = dense;
-        if (!dense) lp += d * (d - 1) / 2;
+    const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
+    uint64_t nd = 0, lp = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kSplitPer; ++k) {
+        const uint64_t r = r0 + k;
+        if (r < R) {
+            const uint64_t d = row_ptr[r + 1] - row_ptr[r];
+            if (d >= dmin) ++nd;
+            else lp += d * (d - 1) / 2;
+        }
     }
-    uint64_t tot;
-    block_excl_scan<kNT>(lp, sh, &tot);
-    if (threadIdx.x == 0 && tot) atomicAdd(&st[ST_LISTPAIRS], (unsigned long long)tot);
+    uint64_t tot_d, tot_p;
+    block_excl_scan<kNT>(nd, sh, &tot_d);
+    block_excl_scan<kNT>(lp, sh, &tot_p);
+    if (threadIdx.x == 0) {
+        tcnt[blockIdx.x] = (uint32_t)tot_d;
+        if (tot_p) atomicAdd(&st[ST_LISTPAIRS], (unsigned long long)tot_p);
+    }
 }
 
-// A list row's position is r minus the packed rows before it.
-__global__ void k_row_compact(uint64_t R, const uint32_t *fDense, const uint64_t *pDense, uint64_t *Drow,
-                              uint64_t *Lrow) {
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t pd = pDense[r];
-        if (fDense[r]) Drow[pd] = r;
-        else Lrow[r - pd] = r;
+__global__ __launch_bounds__(kNT) void k_row_split(const uint64_t *__restrict__ row_ptr, uint64_t R, uint32_t dmin,
+                                                    const uint64_t *__restrict__ toff, uint64_t *__restrict__ Drow,
+                                                    uint64_t *__restrict__ Lrow) {
+    __shared__ uint64_t sh[kWaves];
+    const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
+    uint32_t flags = 0, nd = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kSplitPer; ++k) {
+        const uint64_t r = r0 + k;
+        if (r < R && row_ptr[r + 1] - row_ptr[r] >= dmin) {
+            flags |= 1u << k;
+            ++nd;
+        }
+    }
+    uint64_t tot;
+    uint64_t pd = toff[blockIdx.x] + block_excl_scan<kNT>(nd, sh, &tot);  // packed rows before r0
+#pragma unroll
+    for (uint32_t k = 0; k < kSplitPer; ++k) {
+        const uint64_t r = r0 + k;
+        if (r < R) {
+            if ((flags >> k) & 1u) Drow[pd++] = r;
+            else Lrow[r - pd] = r;
+        }
     }
 }
 
@@ -1129,30 +1162,28 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     }
     db->stats.dense_min_degree = db->dmin;
     if (R > 0) {
-        DevBuf<uint32_t> fDense;
-        DevBuf<uint64_t> pDense, tmp;
-        fDense.alloc(R, s, tb, true, "row flags");
-        launch_1d(R, s, [&](uint32_t b, hipStream_t st_) {
-            {
-                JAS_TIMED("row_flags", st_);
-                k_row_flags<<<b, 256, 0, st_>>>(rptrp, R, db->dmin, fDense.p, st.p);
-            }
-        });
-        check_launch("row flags");
-        pDense.alloc(R + 1, s, tb, true, "row scan");
-        tmp.alloc(scan_tmp_elems(R), s, tb, true, "scan scratch");
-        scan_excl_u32(fDense.p, pDense.p, R, tmp.p, s);
-        QD = to_host_u64(pDense.p + R, s);
+        const uint64_t nt = div_up(R, kSplitTile);
+        if (nt > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many rows");
+        DevBuf<uint32_t> tcnt;
+        DevBuf<uint64_t> toff, tmp;
+        tcnt.alloc(nt, s, tb, true, "row tile counts");
+        toff.alloc(nt + 1, s, tb, true, "row tile offsets");
+        tmp.alloc(scan_tmp_elems(nt), s, tb, true, "scan scratch");
+        {
+            JAS_TIMED("row_count", s);
+            k_row_count<<<(uint32_t)nt, kNT, 0, s>>>(rptrp, R, db->dmin, tcnt.p, st.p);
+        }
+        check_launch("row count");
+        scan_excl_u32(tcnt.p, toff.p, nt, tmp.p, s);
+        QD = to_host_u64(toff.p + nt, s);
         QL = R - QD;
         Drow.alloc(QD, s, tb, true, "packed rows");
         Lrow.alloc(QL, s, tb, true, "list rows");
-        launch_1d(R, s, [&](uint32_t b, hipStream_t st_) {
-            {
-                JAS_TIMED("row_compact", st_);
-                k_row_compact<<<b, 256, 0, st_>>>(R, fDense.p, pDense.p, Drow.p, Lrow.p);
-            }
-        });
-        check_launch("row compact");
+        {
+            JAS_TIMED("row_split", s);
+            k_row_split<<<(uint32_t)nt, kNT, 0, s>>>(rptrp, R, db->dmin, toff.p, Drow.p, Lrow.p);
+        }
+        check_launch("row split");
     }
 
     // --- packed rows: batches, word rows, pack -------------------------------
