@@ -799,12 +799,22 @@ __global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, con
 // list row as the 32-bit word (a << 16) | b, then sorted by a (single-pass
 // scatters over the bits of a), so that the Gram step reads each sample's
 // pairs as one contiguous run (the row-by-row form of B = A^T A over the row
-// lists).
-__global__ void k_list_npairs(const uint64_t *Lrow, const uint64_t *row_ptr, uint64_t QL, uint64_t *np) {
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t r = Lrow[j];
-        const uint64_t d = row_ptr[r + 1] - row_ptr[r];
-        np[j] = d * (d - 1) / 2;
+// lists).  wnp[g] = pairs of list rows [64g, 64g + 64): one wave per group,
+// which is also one wave's share of the emission below.
+__global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint64_t *row_ptr, uint64_t QL, uint64_t *wnp) {
+    const uint64_t nw = (QL + kWave - 1) / kWave;
+    const uint32_t lane = lane_id();
+    for (uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g < nw;
+         g += ((uint64_t)gridDim.x * blockDim.x) / kWave) {
+        const uint64_t j = g * kWave + lane;
+        uint64_t np = 0;
+        if (j < QL) {
+            const uint64_t r = Lrow[j];
+            const uint64_t d = row_ptr[r + 1] - row_ptr[r];
+            np = d * (d - 1) / 2;
+        }
+        const uint64_t inc = wave_incl_scan(np);
+        if (lane == kWave - 1) wnp[g] = inc;
     }
 }
 
@@ -841,7 +851,7 @@ __device__ __forceinline__ void emit_row_pairs(const uint32_t *__restrict__ ls, 
 __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ Lrow,
                                                     const uint64_t *__restrict__ row_ptr,
                                                     const uint32_t *__restrict__ ls, uint64_t QL,
-                                                    const uint64_t *__restrict__ po,
+                                                    const uint64_t *__restrict__ wpo,
                                                     uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
                                                     unsigned long long *__restrict__ ghist) {
     __shared__ uint32_t gh[kPairPasses][256];
@@ -864,9 +874,13 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
             e0 = row_ptr[rr];
             e1 = row_ptr[rr + 1];
         }
-        const uint64_t base = po[r0];
-        const uint64_t total = po[min(r0 + kWave, QL)] - base;
-        const uint64_t my = r < QL ? po[r] - base : 0;
+        // the wave's first pair (wpo: scan of the 64-row groups' pair counts)
+        // and this row's pairs before it within the group
+        const uint64_t base = wpo[r0 / kWave];
+        const uint64_t np = (e1 - e0) * (e1 - e0 - (e1 > e0 ? 1 : 0)) / 2;
+        const uint64_t incl = wave_incl_scan(np);
+        const uint64_t total = __shfl(incl, kWave - 1, kWave);
+        const uint64_t my = incl - np;
         const uint64_t span0 = __shfl(e0, 0, kWave), span1 = __shfl(e1, (int)last, kWave);
         const bool staged_in = span1 - span0 <= kEmitIn;  // wave-uniform
         const bool staged = total <= kEmitStage;          // wave-uniform
@@ -1248,19 +1262,21 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     db->n_list = QL;
     bool pairs_done = false;
     if (QL > 0 && n <= kSampleMajorMaxN) {
+        // pairs per group of 64 list rows (one wave of the emission), scanned
+        const uint64_t nw = div_up(QL, (uint64_t)kWave);
         DevBuf<uint64_t> np, npo, tmp2;
-        np.alloc(QL, s, tb, true, "row pair counts");
+        np.alloc(nw, s, tb, true, "row group pair counts");
         launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("list_npairs", st_);
-                k_list_npairs<<<b, 256, 0, st_>>>(Lrow.p, rptrp, QL, np.p);
+                k_list_wave_pairs<<<b, 256, 0, st_>>>(Lrow.p, rptrp, QL, np.p);
             }
         });
         check_launch("row pair counts");
-        npo.alloc(QL + 1, s, tb, true, "row pair offsets");
-        tmp2.alloc(scan_tmp_elems(QL), s, tb, true, "scan scratch");
-        scan_excl_u64(np.p, npo.p, QL, tmp2.p, s);
-        const uint64_t P = to_host_u64(npo.p + QL, s);
+        npo.alloc(nw + 1, s, tb, true, "row group pair offsets");
+        tmp2.alloc(scan_tmp_elems(nw), s, tb, true, "scan scratch");
+        scan_excl_u64(np.p, npo.p, nw, tmp2.p, s);
+        const uint64_t P = to_host_u64(npo.p + nw, s);
         np.release();
         tmp2.release();
         const uint32_t sb = std::max<uint32_t>(1, ceil_log2_u64((uint64_t)n));
