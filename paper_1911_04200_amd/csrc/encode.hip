@@ -557,14 +557,14 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
 // Packs the rows k_local_cls wrote per range (and, for the query index, the
 // distinct keys): one block per range (grid-stride).  The shared pairs stay
 // where the range wrote them (from its start, with gaps between ranges), so
-// a row is [row_ptr, row_end) of that array.
+// a row is row_deg entries of that array from row_ptr.
 __global__ __launch_bounds__(256) void k_local_move(const uint64_t *__restrict__ rs, uint64_t nlc,
                                                      const uint64_t *__restrict__ oD, const uint64_t *__restrict__ oS,
                                                      const uint64_t *__restrict__ oR, const uint64_t *__restrict__ K,
                                                      const uint64_t *__restrict__ rid_g,
                                                      const uint64_t *__restrict__ rptr_g, uint64_t *__restrict__ Dk,
                                                      uint64_t *__restrict__ row_id, uint64_t *__restrict__ row_ptr,
-                                                     uint64_t *__restrict__ row_end) {
+                                                     uint32_t *__restrict__ row_deg) {
     for (uint64_t c = blockIdx.x; c < nlc; c += gridDim.x) {
         const uint64_t s0 = rs[c], r0 = s0 / 2;
         const uint64_t d0 = oD[c], nd = oD[c + 1] - d0;
@@ -572,12 +572,19 @@ __global__ __launch_bounds__(256) void k_local_move(const uint64_t *__restrict__
         const uint64_t w0 = oR[c], nr = oR[c + 1] - w0;
         for (uint64_t i = threadIdx.x; i < nr; i += blockDim.x) {
             row_id[w0 + i] = rid_g[r0 + i];
-            row_ptr[w0 + i] = s0 + rptr_g[r0 + i];
-            row_end[w0 + i] = s0 + (i + 1 < nr ? rptr_g[r0 + i + 1] : ns);
+            const uint64_t a = rptr_g[r0 + i];
+            row_ptr[w0 + i] = s0 + a;
+            row_deg[w0 + i] = (uint32_t)((i + 1 < nr ? rptr_g[r0 + i + 1] : ns) - a);
         }
         if (Dk)
             for (uint64_t i = threadIdx.x; i < nd; i += blockDim.x) Dk[d0 + i] = K[s0 + i];
     }
+}
+
+// Degrees of contiguous rows: row_deg[r] = row_ptr[r + 1] - row_ptr[r].
+__global__ void k_row_deg(const uint64_t *row_ptr, uint64_t R, uint32_t *row_deg) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x)
+        row_deg[r] = (uint32_t)(row_ptr[r + 1] - row_ptr[r]);
 }
 
 // |X_i| = entries of sample i minus its repeated (ID, sample) entries.
@@ -588,15 +595,14 @@ __global__ void k_card_from_dups(const uint64_t *off, const unsigned long long *
 }
 
 // Row degree histogram (degrees are <= n): input of the degree threshold choice.
-__global__ __launch_bounds__(kNT) void k_deg_hist(const uint64_t *row_ptr, const uint64_t *row_end, uint64_t R,
-                                                   uint32_t nb,
+__global__ __launch_bounds__(kNT) void k_deg_hist(const uint32_t *row_deg, uint64_t R, uint32_t nb,
                                                    int lds, unsigned long long *hist) {
     extern __shared__ uint32_t h[];
     if (lds)
         for (uint32_t i = threadIdx.x; i < nb; i += kNT) h[i] = 0;
     __syncthreads();
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t d = min(row_end[r] - row_ptr[r], (uint64_t)(nb - 1));
+        const uint64_t d = min((uint64_t)row_deg[r], (uint64_t)(nb - 1));
         if (lds) atomicAdd(&h[d], 1u);
         else atomicAdd(&hist[d], 1ull);
     }
@@ -616,8 +622,7 @@ __global__ __launch_bounds__(kNT) void k_deg_hist(const uint64_t *row_ptr, const
 constexpr uint32_t kSplitPer = 8;
 constexpr uint64_t kSplitTile = (uint64_t)kNT * kSplitPer;
 
-__global__ __launch_bounds__(kNT) void k_row_count(const uint64_t *__restrict__ row_ptr,
-                                                    const uint64_t *__restrict__ row_end, uint64_t R, uint32_t dmin,
+__global__ __launch_bounds__(kNT) void k_row_count(const uint32_t *__restrict__ row_deg, uint64_t R, uint32_t dmin,
                                                     uint32_t *__restrict__ tcnt, unsigned long long *st) {
     __shared__ uint64_t sh[kWaves];
     const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
@@ -626,7 +631,7 @@ __global__ __launch_bounds__(kNT) void k_row_count(const uint64_t *__restrict__ 
     for (uint32_t k = 0; k < kSplitPer; ++k) {
         const uint64_t r = r0 + k;
         if (r < R) {
-            const uint64_t d = row_end[r] - row_ptr[r];
+            const uint64_t d = row_deg[r];
             if (d >= dmin) ++nd;
             else lp += d * (d - 1) / 2;
         }
@@ -640,8 +645,7 @@ __global__ __launch_bounds__(kNT) void k_row_count(const uint64_t *__restrict__ 
     }
 }
 
-__global__ __launch_bounds__(kNT) void k_row_split(const uint64_t *__restrict__ row_ptr,
-                                                    const uint64_t *__restrict__ row_end, uint64_t R, uint32_t dmin,
+__global__ __launch_bounds__(kNT) void k_row_split(const uint32_t *__restrict__ row_deg, uint64_t R, uint32_t dmin,
                                                     const uint64_t *__restrict__ toff, uint64_t *__restrict__ Drow,
                                                     uint64_t *__restrict__ Lrow) {
     __shared__ uint64_t sh[kWaves];
@@ -650,7 +654,7 @@ __global__ __launch_bounds__(kNT) void k_row_split(const uint64_t *__restrict__ 
 #pragma unroll
     for (uint32_t k = 0; k < kSplitPer; ++k) {
         const uint64_t r = r0 + k;
-        if (r < R && row_end[r] - row_ptr[r] >= dmin) {
+        if (r < R && row_deg[r] >= dmin) {
             flags |= 1u << k;
             ++nd;
         }
@@ -707,7 +711,7 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
                                                const uint64_t *__restrict__ wq0, const uint64_t *__restrict__ wq1,
                                                const uint64_t *__restrict__ Drow,
                                                const uint64_t *__restrict__ row_ptr,
-                                               const uint64_t *__restrict__ row_end,
+                                               const uint32_t *__restrict__ row_deg,
                                                const uint32_t *__restrict__ S, uint32_t cols,
                                                unsigned long long *st) {
     extern __shared__ unsigned long long lw[];
@@ -723,7 +727,7 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
             if (q0 + lane < q1) {
                 const uint64_t r = Drow[q0 + lane];
                 base = row_ptr[r];
-                deg = row_end[r] - base;
+                deg = row_deg[r];
             }
             const uint64_t inc = wave_incl_scan(deg);
             rstart[lane + 1] = inc;
@@ -785,19 +789,18 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
 }
 
 // Row lists: CSR of the rows of degree 2..dmin-1.
-__global__ void k_list_deg(const uint64_t *Lrow, const uint64_t *row_ptr, const uint64_t *row_end, uint64_t QL,
-                           uint64_t *deg) {
+__global__ void k_list_deg(const uint64_t *Lrow, const uint32_t *row_deg, uint64_t QL, uint64_t *deg) {
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t r = Lrow[j];
-        deg[j] = row_end[r] - row_ptr[r];
+        deg[j] = row_deg[r];
     }
 }
 
-__global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, const uint64_t *row_end, const uint32_t *S,
+__global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, const uint32_t *row_deg, const uint32_t *S,
                               const uint64_t *lptr, uint64_t QL, uint32_t *lsmp) {
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t r = Lrow[j];
-        const uint64_t a0 = row_ptr[r], d = row_end[r] - a0, o = lptr[j];
+        const uint64_t a0 = row_ptr[r], d = row_deg[r], o = lptr[j];
         for (uint64_t k = 0; k < d; ++k) lsmp[o + k] = S[a0 + k];
     }
 }
@@ -808,8 +811,7 @@ __global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, con
 // pairs as one contiguous run (the row-by-row form of B = A^T A over the row
 // lists).  wnp[g] = pairs of list rows [64g, 64g + 64): one wave per group,
 // which is also one wave's share of the emission below.
-__global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint64_t *row_ptr, const uint64_t *row_end, uint64_t QL,
-                                  uint64_t *wnp) {
+__global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint32_t *row_deg, uint64_t QL, uint64_t *wnp) {
     const uint64_t nw = (QL + kWave - 1) / kWave;
     const uint32_t lane = lane_id();
     for (uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g < nw;
@@ -818,7 +820,7 @@ __global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint64_t *row_ptr,
         uint64_t np = 0;
         if (j < QL) {
             const uint64_t r = Lrow[j];
-            const uint64_t d = row_end[r] - row_ptr[r];
+            const uint64_t d = row_deg[r];
             np = d * (d - 1) / 2;
         }
         const uint64_t inc = wave_incl_scan(np);
@@ -858,7 +860,7 @@ __device__ __forceinline__ void emit_row_pairs(const uint32_t *__restrict__ ls, 
 
 __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ Lrow,
                                                     const uint64_t *__restrict__ row_ptr,
-                                                    const uint64_t *__restrict__ row_end,
+                                                    const uint32_t *__restrict__ row_deg,
                                                     const uint32_t *__restrict__ ls, uint64_t QL,
                                                     const uint64_t *__restrict__ wpo,
                                                     uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
@@ -881,7 +883,7 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
         if (r < QL) {
             const uint64_t rr = Lrow[r];
             e0 = row_ptr[rr];
-            e1 = row_end[rr];
+            e1 = e0 + row_deg[rr];
         }
         // the wave's first pair (wpo: scan of the 64-row groups' pair counts)
         // and this row's pairs before it within the group
@@ -1005,10 +1007,12 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     // Outputs of the classification: distinct keys (query index), shared
     // pairs S in row order, and per shared row its ID and first pair.
     uint64_t NDk = 0, NS = 0, R = 0;
-    DevBuf<uint64_t> Dk, rid_own, rptr_own, rend_own;
+    DevBuf<uint64_t> Dk, rid_own, rptr_own;
+    DevBuf<uint32_t> rdeg_own;
     DevBuf<uint32_t> S_own;
     uint32_t *Sp = nullptr;
-    uint64_t *ridp = nullptr, *rptrp = nullptr, *rendp = nullptr;
+    uint64_t *ridp = nullptr, *rptrp = nullptr;
+    uint32_t *rdegp = nullptr;
     bool done = N == 0;
 
     // --- classify each range of whole buckets in LDS ------------------------
@@ -1084,16 +1088,16 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             if (keep) Dk.alloc(NDk, s, &db->budget, false, "query index keys");
             rid_own.alloc(R, s, tb, true, "row ids");
             rptr_own.alloc(R + 1, s, tb, true, "row pointers");
-            rend_own.alloc(R + 1, s, tb, true, "row ends");
+            rdeg_own.alloc(R + 1, s, tb, true, "row degrees");
             Sp = Sg;  // the shared pairs stay in the ranges' stretches
             ridp = rid_own.p;
             rptrp = rptr_own.p;
-            rendp = rend_own.p;
+            rdegp = rdeg_own.p;
             {
                 JAS_TIMED("local_move", s);
                 k_local_move<<<(uint32_t)std::min<uint64_t>(nlc, 65536), 256, 0, s>>>(
                     rs.p, nlc, offD.p, offS.p, offR.p, keys.p, rid_g.p, rptr_g, keep ? Dk.p : nullptr, ridp, rptrp,
-                    rendp);
+                    rdegp);
             }
             check_launch("local move");
             {
@@ -1148,7 +1152,6 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         Sp = S_own.p;
         ridp = rid_own.p;
         rptrp = rptr_own.p;
-        rendp = rptrp + 1;  // compact: a row ends where the next begins (row_ptr[R] = NS below)
         {
             JAS_TIMED("cls_write", s);
             k_cls_write<<<(uint32_t)nch, kNT, 0, s>>>(K, N, sbits, smask, offD.p, offS.p, offR.p,
@@ -1161,6 +1164,15 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         k_fill_u64<<<1, 1, 0, s>>>(rptrp + R, 1, NS);
     }
     check_launch("fill");
+    if (!rdegp) {  // the global classification wrote the rows contiguously
+        rdeg_own.alloc(R + 1, s, tb, true, "row degrees");
+        rdegp = rdeg_own.p;
+        launch_1d(std::max<uint64_t>(R, 1), s, [&](uint32_t b, hipStream_t st_) {
+            JAS_TIMED("row_deg", st_);
+            k_row_deg<<<b, 256, 0, st_>>>(rptrp, R, rdegp);
+        });
+        check_launch("row degrees");
+    }
 
     // column sums -> |X_i| (int32 B needs every |X_i| < 2^31)
     db->card.alloc(std::max<int32_t>(n, 1), s, &db->budget, false, "card");
@@ -1190,7 +1202,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(div_up(R, 256), 2048);
         {
             JAS_TIMED("deg_hist", s);
-            k_deg_hist<<<blocks, kNT, lds ? nb * sizeof(uint32_t) : 0, s>>>(rptrp, rendp, R, nb, lds, hist.p);
+            k_deg_hist<<<blocks, kNT, lds ? nb * sizeof(uint32_t) : 0, s>>>(rdegp, R, nb, lds, hist.p);
         }
         check_launch("degree histogram");
         std::vector<uint64_t> hh(nb);
@@ -1218,7 +1230,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         tmp.alloc(scan_tmp_elems(nt), s, tb, true, "scan scratch");
         {
             JAS_TIMED("row_count", s);
-            k_row_count<<<(uint32_t)nt, kNT, 0, s>>>(rptrp, rendp, R, db->dmin, tcnt.p, st.p);
+            k_row_count<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, tcnt.p, st.p);
         }
         check_launch("row count");
         scan_excl_u32(tcnt.p, toff.p, nt, tmp.p, s);
@@ -1228,7 +1240,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         Lrow.alloc(QL, s, tb, true, "list rows");
         {
             JAS_TIMED("row_split", s);
-            k_row_split<<<(uint32_t)nt, kNT, 0, s>>>(rptrp, rendp, R, db->dmin, toff.p, Drow.p, Lrow.p);
+            k_row_split<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, toff.p, Drow.p, Lrow.p);
         }
         check_launch("row split");
     }
@@ -1282,7 +1294,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         {
             JAS_TIMED("pack", s);
             k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, wq0.p, wq1.p, Drow.p, rptrp,
-                                                                        rendp, Sp, cols, st.p);
+                                                                        rdegp, Sp, cols, st.p);
         }
         check_launch("pack");
     }
@@ -1302,7 +1314,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("list_npairs", st_);
-                k_list_wave_pairs<<<b, 256, 0, st_>>>(Lrow.p, rptrp, rendp, QL, np.p);
+                k_list_wave_pairs<<<b, 256, 0, st_>>>(Lrow.p, rdegp, QL, np.p);
             }
         });
         check_launch("row pair counts");
@@ -1329,7 +1341,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         {
             JAS_TIMED("pair_emit", s);
             k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 8192), 256, 0, s>>>(
-                Lrow.p, rptrp, rendp, Sp, QL, npo.p, pk.p, npass, width, gh.p);
+                Lrow.p, rptrp, rdegp, Sp, QL, npo.p, pk.p, npass, width, gh.p);
         }
         check_launch("pair emit");
         const bool ok = radix_sort_onesweep_u32(pk, palt, P, 16, 16 + sb, width, gh.p, perr.p, s, tb);
@@ -1346,7 +1358,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         db->list_ptr.alloc(QL + 1, s, &db->budget, false, "row list pointers");
         DevBuf<uint64_t> deg, tmp;
         deg.alloc(QL, s, tb, true, "row list degrees");
-        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("list_deg", st_); k_list_deg<<<b, 256, 0, st_>>>(Lrow.p, rptrp, rendp, QL, deg.p); } });
+        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("list_deg", st_); k_list_deg<<<b, 256, 0, st_>>>(Lrow.p, rdegp, QL, deg.p); } });
         check_launch("list degrees");
         tmp.alloc(scan_tmp_elems(QL), s, tb, true, "scan scratch");
         scan_excl_u64(deg.p, db->list_ptr.p, QL, tmp.p, s);
@@ -1355,7 +1367,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("list_gather", st_);
-                k_list_gather<<<b, 256, 0, st_>>>(Lrow.p, rptrp, rendp, Sp, db->list_ptr.p, QL, db->list_smp.p);
+                k_list_gather<<<b, 256, 0, st_>>>(Lrow.p, rptrp, rdegp, Sp, db->list_ptr.p, QL, db->list_smp.p);
             }
         });
         check_launch("list gather");
