@@ -42,6 +42,10 @@ constexpr int32_t kHistMax = 16384;        // LDS column histogram up to this n
 constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass
 
 enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
+// Counters that many blocks add to are spread over kStatReplicas slots (one
+// counter would serialise an atomic from every block) and summed into st by
+// k_sum_replicas.
+constexpr uint32_t kStatReplicas = 64;
 
 // ---------------------------------------------------------------------------
 // Keys of one chunk (kChunk entries) per block, and the totals of every digit
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
     uint64_t *__restrict__ K, uint32_t sbits, uint64_t smask, uint32_t bsh, uint32_t lowbits,
     const uint64_t *__restrict__ rs, uint32_t nlc, uint32_t *__restrict__ cnt, int keep, uint32_t *__restrict__ Sg,
     uint64_t *__restrict__ rid_g, uint64_t *__restrict__ rptr_g, unsigned long long *__restrict__ dupc,
-    unsigned long long *__restrict__ st) {
+    unsigned long long *__restrict__ rows_rep) {
     __shared__ KT A[kLocalCapKeys];
     __shared__ uint32_t wcnt[kLWaves][256];
     __shared__ uint64_t T[kLWaves][256];  // per wave: lanes of the current round with digit d
@@ -523,7 +527,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
         cnt[c] = tD;
         cnt[nlc + c] = tS;
         cnt[2 * (uint64_t)nlc + c] = tR;
-        if (all_rows) atomicAdd(&st[ST_ROWS], (unsigned long long)all_rows);
+        if (all_rows) atomicAdd(&rows_rep[c % kStatReplicas], (unsigned long long)all_rows);
     }
 
     // --- ordered writes at the range's own position (every read of the range is done)
@@ -622,26 +626,60 @@ __global__ __launch_bounds__(kNT) void k_deg_hist(const uint32_t *row_deg, uint6
 constexpr uint32_t kSplitPer = 8;
 constexpr uint64_t kSplitTile = (uint64_t)kNT * kSplitPer;
 
+// The 8 degrees of rows [r0, r0 + 8) (two 16-byte loads when all exist; r0 is a
+// multiple of 8, so they are aligned); rows past R read as degree 0.
+__device__ __forceinline__ void load_degrees(const uint32_t *__restrict__ row_deg, uint64_t r0, uint64_t R,
+                                             uint32_t (&d)[kSplitPer]) {
+    if (r0 + kSplitPer <= R) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(row_deg + r0);
+        const uint4 b = *reinterpret_cast<const uint4 *>(row_deg + r0 + 4);
+        d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w;
+        d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < kSplitPer; ++k) d[k] = r0 + k < R ? row_deg[r0 + k] : 0u;
+    }
+}
+
 __global__ __launch_bounds__(kNT) void k_row_count(const uint32_t *__restrict__ row_deg, uint64_t R, uint32_t dmin,
-                                                    uint32_t *__restrict__ tcnt, unsigned long long *st) {
-    __shared__ uint64_t sh[kWaves];
+                                                    uint32_t *__restrict__ tcnt, unsigned long long *lp_rep) {
+    __shared__ uint64_t sh[kWaves], sh2[kWaves];
     const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
     uint64_t nd = 0, lp = 0;
+    uint32_t dg[kSplitPer];
+    load_degrees(row_deg, r0, R, dg);
 #pragma unroll
     for (uint32_t k = 0; k < kSplitPer; ++k) {
-        const uint64_t r = r0 + k;
-        if (r < R) {
-            const uint64_t d = row_deg[r];
+        if (r0 + k < R) {
+            const uint64_t d = dg[k];
             if (d >= dmin) ++nd;
             else lp += d * (d - 1) / 2;
         }
     }
-    uint64_t tot_d, tot_p;
-    block_excl_scan<kNT>(nd, sh, &tot_d);
-    block_excl_scan<kNT>(lp, sh, &tot_p);
+    // block sums of both (one pass: wave sums, then thread 0)
+    const uint64_t wd = wave_incl_scan(nd), wp = wave_incl_scan(lp);
+    if (lane_id() == kWave - 1) {
+        sh[threadIdx.x / kWave] = wd;
+        sh2[threadIdx.x / kWave] = wp;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        uint64_t tot_d = 0, tot_p = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            tot_d += sh[k];
+            tot_p += sh2[k];
+        }
         tcnt[blockIdx.x] = (uint32_t)tot_d;
-        if (tot_p) atomicAdd(&st[ST_LISTPAIRS], (unsigned long long)tot_p);
+        if (tot_p) atomicAdd(&lp_rep[blockIdx.x % kStatReplicas], (unsigned long long)tot_p);
+    }
+}
+
+__global__ void k_sum_replicas(const unsigned long long *rep, uint32_t nrep, unsigned long long *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        unsigned long long t = 0;
+        for (uint32_t k = 0; k < nrep; ++k) t += rep[k];
+        *dst += t;
     }
 }
 
@@ -651,10 +689,11 @@ __global__ __launch_bounds__(kNT) void k_row_split(const uint32_t *__restrict__ 
     __shared__ uint64_t sh[kWaves];
     const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
     uint32_t flags = 0, nd = 0;
+    uint32_t dg[kSplitPer];
+    load_degrees(row_deg, r0, R, dg);
 #pragma unroll
     for (uint32_t k = 0; k < kSplitPer; ++k) {
-        const uint64_t r = r0 + k;
-        if (r < R && row_deg[r] >= dmin) {
+        if (r0 + k < R && dg[k] >= dmin) {
             flags |= 1u << k;
             ++nd;
         }
@@ -1047,12 +1086,15 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             DevBuf<unsigned long long> dupc;
             DevBuf<uint32_t> cnt;
             DevBuf<uint64_t> rid_g, offD, offS, offR, stmp;
-            dupc.alloc(std::max<int32_t>(n, 1), s, tb, true, "repeat counts");
+            // repeat counts per sample, then the row counters (kStatReplicas)
+            const uint64_t ndup = (uint64_t)std::max<int32_t>(n, 1);
+            dupc.alloc(ndup + kStatReplicas, s, tb, true, "repeat counts");
+            unsigned long long *rowsrep = dupc.p + ndup;
             cnt.alloc(3 * nlc, s, tb, true, "range counts");
             rid_g.alloc(N / 2 + 1, s, tb, true, "row ids (by range)");
             {
                 JAS_TIMED("fill_u64", s);
-                k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)dupc.p, (uint64_t)std::max<int32_t>(n, 1), 0);
+                k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)dupc.p, ndup + kStatReplicas, 0);
             }
             // shared pairs at the range starts in the first half of the free sort
             // buffer, row pointers (relative to the range) after it
@@ -1063,11 +1105,12 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
                 if (herr & 16u)
                     k_local_cls<uint64_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
                                                                          (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
-                                                                         rid_g.p, rptr_g, dupc.p, st.p);
+                                                                         rid_g.p, rptr_g, dupc.p, rowsrep);
                 else
                     k_local_cls<uint32_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
                                                                          (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
-                                                                         rid_g.p, rptr_g, dupc.p, st.p);
+                                                                         rid_g.p, rptr_g, dupc.p, rowsrep);
+                k_sum_replicas<<<1, 64, 0, s>>>(rowsrep, kStatReplicas, st.p + ST_ROWS);
             }
             check_launch("local classify");
             offD.alloc(nlc + 1, s, tb, true, "range offsets");
@@ -1224,13 +1267,21 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         const uint64_t nt = div_up(R, kSplitTile);
         if (nt > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many rows");
         DevBuf<uint32_t> tcnt;
-        DevBuf<uint64_t> toff, tmp;
+        DevBuf<uint64_t> toff, tmp, lprep;
         tcnt.alloc(nt, s, tb, true, "row tile counts");
+        lprep.alloc(kStatReplicas, s, tb, true, "list pair counters");
+        {
+            JAS_TIMED("fill_u64", s);
+            k_fill_u64<<<1, 64, 0, s>>>(lprep.p, kStatReplicas, 0);
+        }
         toff.alloc(nt + 1, s, tb, true, "row tile offsets");
         tmp.alloc(scan_tmp_elems(nt), s, tb, true, "scan scratch");
         {
             JAS_TIMED("row_count", s);
-            k_row_count<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, tcnt.p, st.p);
+            k_row_count<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, tcnt.p,
+                                                      reinterpret_cast<unsigned long long *>(lprep.p));
+            k_sum_replicas<<<1, 64, 0, s>>>(reinterpret_cast<const unsigned long long *>(lprep.p), kStatReplicas,
+                                            st.p + ST_LISTPAIRS);
         }
         check_launch("row count");
         scan_excl_u32(tcnt.p, toff.p, nt, tmp.p, s);
