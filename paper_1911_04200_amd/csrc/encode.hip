@@ -346,17 +346,22 @@ __global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict
 // once made relative to the range's first bucket: ((id - rbase) << sbits) |
 // sample, with rbase = first bucket << lowbits, needs lowbits + ceil_log2(the
 // number of bucket values spanned) + sbits bits; err |= 16 where that exceeds 32.
+// The flags of a thread's ranges are gathered first and set with one atomic
+// per wave (every range may set bit 16).
 __global__ void k_range_check(const uint64_t *__restrict__ K, const uint64_t *rs, uint64_t nlc, uint32_t bsh,
                               uint32_t lowbits, uint32_t sbits, uint32_t *err) {
+    uint32_t f = 0;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nlc; c += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t a = rs[c], b = rs[c + 1];
         if (a == ~0ull || b == ~0ull || b < a || b - a > kLocalCapKeys) {
-            atomicOr(err, 8u);
+            f |= 8u;
         } else if (b > a) {
             const uint64_t bf = bucket_of(K[a], bsh), bl = bucket_of(K[b - 1], bsh);
-            if (lowbits + dev_ceil_log2(bl - bf + 1) + sbits > 32) atomicOr(err, 16u);
+            if (lowbits + dev_ceil_log2(bl - bf + 1) + sbits > 32) f |= 16u;
         }
     }
+    const uint64_t m8 = __ballot((f & 8u) != 0), m16 = __ballot((f & 16u) != 0);
+    if (lane_id() == 0 && (m8 | m16)) atomicOr(err, (m8 ? 8u : 0u) | (m16 ? 16u : 0u));
 }
 
 // KT is the LDS form of a key, relative to the range's first bucket:
