@@ -393,7 +393,20 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
         kbase = (bf << lowbits) << sbits;  // bf > 0 only when lowbits < U <= 63
         nb = lowbits + dev_ceil_log2(bl - bf + 1);
     }
-    for (uint32_t i = tid; i < L; i += kLNT) A[i] = (KT)(K[s0 + i] - kbase);
+    {
+        // every load of the range in flight at once, then the LDS stores
+        uint64_t v[kLRounds];
+#pragma unroll
+        for (uint32_t j = 0; j < kLRounds; ++j) {
+            const uint32_t i = tid + j * kLNT;
+            v[j] = i < L ? K[s0 + i] : 0;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kLRounds; ++j) {
+            const uint32_t i = tid + j * kLNT;
+            if (i < L) A[i] = (KT)(v[j] - kbase);
+        }
+    }
     // wave w owns positions [w*seg, (w+1)*seg), 64 per round, in order
     const uint32_t seg = ((L + kLWaves - 1) / kLWaves + kWave - 1) / kWave * kWave;
     const uint32_t rounds = seg / kWave;
