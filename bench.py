@@ -63,9 +63,9 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
         return ("hbm", (8.0 * N + 4.0 * shared + 16.0 * stats["n_shared_rows"]) / 1e9, "GB/s",
                 "8 B per key read + 4 B per shared pair + 16 B per shared row written")
     if kernel == "local_move":
-        shared = stats["n_pairs"] - (stats["n_rows"] - stats["n_shared_rows"])
-        return ("hbm", (8.0 * shared + 32.0 * stats["n_shared_rows"]) / 1e9, "GB/s",
-                "4 B per shared pair and 16 B per shared row, each read and written once")
+        return ("hbm", 44.0 * stats["n_shared_rows"] / 1e9, "GB/s",
+                "per shared row: its ID, start and the next start read (24 B), its ID, start and degree written "
+                "(20 B); the ranges' offsets are not counted")
     if kernel == "pair_sort":
         return "hbm", 8.0 * stats["list_pairs"] / 1e9, "GB/s", "8 B per 32-bit pair word per pass (read 4 + write 4)"
     if kernel == "pair_emit":
