@@ -168,8 +168,6 @@ __device__ __forceinline__ uint32_t status_load(const uint32_t *p) {
 // One tile = kOsNT threads x R keys; threads tid < kRadix also own digit tid.
 constexpr int kOsNT = 512;  // 512 x 16 keys measured best of 512 x 8/12/16 and 1024 x 16 (one block per CU)
 constexpr int kOsWaves = kOsNT / kWave;
-constexpr int kOsMaxRounds = 16;
-constexpr uint32_t kOsMaxTile = kOsNT * kOsMaxRounds;  // 8192 keys
 
 template <class K, int R, bool kTable>
 __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(
@@ -189,14 +187,15 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
     const uint64_t gs = digit ? gstart[tid] : 0;
     // while ranking, the first kOsWaves*256 words of stage are per-wave tables
     // of the lanes of the current round that have digit d
-    static_assert(kOsWaves * kRadix * sizeof(uint64_t) <= (kOsNT * R) * sizeof(K), "match tables fit the stage");
+    static_assert(!kTable || kOsWaves * kRadix * sizeof(uint64_t) <= (kOsNT * R) * sizeof(K),
+                  "match tables fit the stage");
     uint64_t *T = reinterpret_cast<uint64_t *>(stage) + w * kRadix;
     // persistent: take tiles in ticket order until none is left
     for (;;) {
         if (tid == 0) tile_sh = atomicAdd(ticket, 1u);
         for (uint32_t i = tid; i < kOsWaves * kRadix; i += kOsNT) {
             (&wcnt[0][0])[i] = 0;
-            if constexpr (sizeof(K) == 4) reinterpret_cast<uint64_t *>(stage)[i] = 0;
+            if constexpr (kTable) reinterpret_cast<uint64_t *>(stage)[i] = 0;
         }
         __syncthreads();
         const uint32_t tile = tile_sh;
@@ -211,7 +210,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             const uint64_t t = wb + (uint64_t)j * kWave + lane;
             key[j] = t < c1 ? in[t] : 0;
         }
-        if constexpr (sizeof(K) == 4) {
+        if constexpr (kTable) {
             // Rank within the wave: lanes of a round with the same digit find each
             // other through T[d] (each ORs in its lane bit, reads the set back and
             // clears it; one wave's LDS operations run in order), take consecutive
