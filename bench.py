@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
 MFMA_I8_PEAK_TOPS = 5000.0     # dense int8 MFMA, TOP/s
+MFMA_FP4_PEAK_TOPS = 10100.0   # dense fp4 MFMA, TFLOP/s
 
 
 def log(msg):
@@ -32,7 +33,7 @@ def log(msg):
 
 def kernel_source_hash(kernel: str) -> str:
     src = {"radix_scatter": "radix.hip", "radix_onesweep": "radix.hip", "radix_hist": "radix.hip",
-           "gram_popc": "gram.hip", "gram_mfma": "gram.hip", "list_pairs": "gram.hip",
+           "gram_popc": "gram.hip", "gram_mfma": "gram.hip", "gram_fp4": "gram.hip", "list_pairs": "gram.hip",
            "pair_count": "gram.hip", "cls_count": "encode.hip", "cls_write": "encode.hip",
            "local_cls": "encode.hip", "local_cls_wide": "encode.hip", "local_move": "encode.hip", "pair_emit": "encode.hip",
            "pair_sort": "radix.hip",
@@ -83,6 +84,11 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
         nt = math.ceil(n / 128)
         macs = stats["n_word_rows"] * 64 * (nt * (nt + 1) // 2) * 128 * 128
         return "mfma", 2.0 * macs / 1e12, "TOP/s", "2 int8 ops per bit pair of every packed word pair (MACs x 2)"
+    if kernel == "gram_fp4":
+        nt = math.ceil(n / 128)
+        macs = stats["n_word_rows"] * 64 * (nt * (nt + 1) // 2) * 128 * 128
+        return ("mfma_fp4", 2.0 * macs / 1e12, "TFLOP/s",
+                "2 fp4 flops per bit pair of every packed word pair (MACs x 2; each bit a 0/1 e2m1 value)")
     if kernel == "gram_popc":
         nt = math.ceil(n / 128)
         wp = stats["n_word_rows"] * (nt * (nt + 1) // 2) * 128 * 128
@@ -291,7 +297,10 @@ def main():
             bound, amount, unit, desc = alg
             avg_s = ms / c / 1e3
             achieved = amount / avg_s
-            peak = {"hbm": HBM_PEAK_GBS, "alu": VALU_PEAK_TOPS, "mfma": MFMA_I8_PEAK_TOPS}[bound]
+            peak = {"hbm": HBM_PEAK_GBS, "alu": VALU_PEAK_TOPS, "mfma": MFMA_I8_PEAK_TOPS,
+                    "mfma_fp4": MFMA_FP4_PEAK_TOPS}[bound]
+            if bound == "mfma_fp4":
+                bound = "mfma"  # against the fp4 peak
             traffic = None
             tf = os.path.join(ROOT, "profiles", "traffic.json")
             if os.path.exists(tf):
@@ -302,7 +311,8 @@ def main():
                     "frac": achieved / peak, "traffic": traffic, "per_launch": desc,
                     "avg_launch_ms": ms / c}
     # word-pair rates of the popcount Gram
-    gram_ms = (kt.get("gram_popc", (0, 0.0))[1] + kt.get("gram_mfma", (0, 0.0))[1]) / max(args.steps, 1)
+    gram_ms = (kt.get("gram_popc", (0, 0.0))[1] + kt.get("gram_mfma", (0, 0.0))[1] +
+               kt.get("gram_fp4", (0, 0.0))[1]) / max(args.steps, 1)
     nt = math.ceil(n / 128)
     executed = st["n_word_rows"] * (nt * (nt + 1) // 2) * 128 * 128
     extra = {"gram_ms": gram_ms, "gram_autotune_ms": tune_ms,

@@ -52,7 +52,7 @@ typedef enum {
 #define JAS_KEEP_IDS 0x2u       /* jas_encode: keep the row index needed by jas_query */
 #define JAS_UPPER 0x10u         /* jas_gram: outputs in the packed upper layout (j >= i) */
 #define JAS_FORCE_POPCOUNT 0x20u /* jas_gram: every packed tile on the AND+popcount kernel */
-#define JAS_FORCE_MFMA 0x40u    /* jas_gram: every packed tile on the int8 MFMA kernel */
+#define JAS_FORCE_MFMA 0x40u    /* jas_gram: every packed tile on an MFMA kernel (int8, or fp4 with exact float sums) */
 #define JAS_TUNE 0x80u          /* jas_gram: time the MFMA tile variants on this db first (see jas_gram) */
 /* jas_gram: run MFMA tile variant v, 0 <= v < jas_gram_variants() (bits 16..23 hold v + 1) */
 #define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)
@@ -120,7 +120,9 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
  * The result does not depend on flags other than the layout: every tile path
  * is exact.  Does not synchronise unless JAS_HOST_PTRS or JAS_TUNE is given.
  * JAS_TUNE (autotuner): before the product, the MFMA Gram runs once in each of
- * its tile variants (word rows per step, K split) on this db, timed with HIP
+ * its variants (tile, number format: int8 or fp4 (e2m1, each bit 0 or 1.0, the
+ * float32 sums of a block kept below 2^24 so they are exact), word rows per
+ * step, K split) on this db, timed with HIP
  * events on the stream (synchronising); the fastest is kept, in this process,
  * for every later db on the device with the same n and the same power of two
  * of word rows, and is used by later calls without the flag.  Not capturable

@@ -363,6 +363,216 @@ __global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
             }
 }
 
+// The same 128 x 128 tiles on the fp4 form of the scaled MFMA
+// (V_MFMA_F32_32X32X64_F8F6F4, both operands e2m1): a bit becomes the nibble
+// 0b0010 (1.0) or 0, so one 64-bit word is one K = 64 step (32 bits per lane
+// group) and a table of 256 dwords turns 8 bits into 8 nibbles.  The lanes'
+// k order is the same for both operands, so the dot product is the popcount
+// of the AND.  Products are 0 or 1 and the float32 sums stay below 2^24
+// (at most kFp4MaxK word rows per block), so every count is exact.
+constexpr uint64_t kFp4MaxK = (1u << 24) / 64 - 1;
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void fill_nibble_lut(uint32_t *lut) {
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+        uint32_t d = 0;
+        for (int b = 0; b < 8; ++b) d |= ((i >> b) & 1u) << (4 * b + 1);
+        lut[i] = d;
+    }
+}
+
+__device__ __forceinline__ v8i bits32_fp4(const uint32_t *lut, uint32_t x) {
+    v8i r = {0, 0, 0, 0, 0, 0, 0, 0};
+    r[0] = (int)lut[x & 255u];
+    r[1] = (int)lut[(x >> 8) & 255u];
+    r[2] = (int)lut[(x >> 16) & 255u];
+    r[3] = (int)lut[x >> 24];
+    return r;
+}
+
+template <int WPE, int STEP>
+__global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gram_fp4(
+    const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
+    int32_t *__restrict__ B, int upper) {
+    __shared__ uint32_t lut[256];
+    const uint64_t split = blockIdx.y;
+    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    while (p >= rowlen) {
+        p -= rowlen;
+        ++I;
+        --rowlen;
+    }
+    const uint32_t Jt = I + p;
+    const uint64_t k0 = split * kper;
+    const uint64_t k1 = min(H, k0 + kper);
+    if (k0 >= k1) return;
+    fill_nibble_lut(lut);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, wc = threadIdx.x >> 6;
+    const uint32_t lm = lane & 31, lg = lane >> 5;
+    const uint32_t I0 = I * kT, J0 = Jt * kT + 64 * wc;
+    v16f acc[4][2];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
+    const uint64_t *pa = W + I0 + lm;
+    const uint64_t *pb = W + J0 + lm;
+    uint64_t a[STEP][4], b[STEP][2];
+#pragma unroll
+    for (int u = 0; u < STEP; ++u) {
+        const uint64_t ku = min(k0 + u, k1 - 1);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) a[u][x] = pa[ku * ldw + 32 * x];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) b[u][y] = pb[ku * ldw + 32 * y];
+    }
+    const uint32_t sh = 32 * lg;  // this lane group's half of the word
+    for (uint64_t k = k0; k < k1; k += STEP) {
+        uint64_t na[STEP][4], nb[STEP][2];
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+            const uint64_t kn = min(k + STEP + u, k1 - 1);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) na[u][x] = pa[kn * ldw + 32 * x];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) nb[u][y] = pb[kn * ldw + 32 * y];
+        }
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+            if (k + u >= k1) break;  // wave-uniform: the tail of the range
+            v8i va[4], vb[2];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) va[x] = bits32_fp4(lut, (uint32_t)(a[u][x] >> sh));
+#pragma unroll
+            for (int y = 0; y < 2; ++y) vb[y] = bits32_fp4(lut, (uint32_t)(b[u][y] >> sh));
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va[x], vb[y], acc[x][y], 4, 4, 0, 0,
+                                                                              0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[u][x] = na[u][x];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) b[u][y] = nb[u][y];
+        }
+    }
+    // accumulator r of lane (lg, lm) holds row 8*(r/4) + 4*lg + r%4, column lm of each 32 x 32 tile
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t i = I0 + 32 * x + 8 * (r >> 2) + 4 * lg + (r & 3);
+                const uint32_t j = J0 + 32 * y + lm;
+                const int32_t v = (int32_t)acc[x][y][r];  // an exact integer below 2^24
+                if (v && i < j && j < n) atomicAdd(B + out_index(i, j, n, upper), v);
+            }
+}
+
+// fp4 on 256 x 256 tiles: the four waves of k_gram_mfma_wide, each 128 x
+// 128, with the fp4 step of k_gram_fp4 (one word per MFMA).
+template <int STEP>
+__global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gram_fp4_wide(
+    const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
+    int32_t *__restrict__ B, int upper) {
+    __shared__ uint32_t lut[256];
+    const uint64_t split = blockIdx.y;
+    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    while (p >= rowlen) {
+        p -= rowlen;
+        ++I;
+        --rowlen;
+    }
+    const uint32_t Jt = I + p;
+    const uint64_t k0 = split * kper;
+    const uint64_t k1 = min(H, k0 + kper);
+    if (k0 >= k1) return;
+    fill_nibble_lut(lut);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t lm = lane & 31, lg = lane >> 5;
+    const uint32_t I0 = I * kWideT + 128 * (wv >> 1), J0 = Jt * kWideT + 128 * (wv & 1);
+    if (I0 >= J0 + 128) return;  // the wave's block lies below the diagonal (no syncs follow)
+    v16f acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
+    uint64_t ca[4], cb[4];  // this lane's columns, clamped below ldw
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        ca[x] = min<uint64_t>(I0 + lm + 32 * x, ldw - 1);
+        cb[x] = min<uint64_t>(J0 + lm + 32 * x, ldw - 1);
+    }
+    uint64_t a[STEP][4], b[STEP][4];
+#pragma unroll
+    for (int u = 0; u < STEP; ++u) {
+        const uint64_t ku = min(k0 + u, k1 - 1);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            a[u][x] = W[ku * ldw + ca[x]];
+            b[u][x] = W[ku * ldw + cb[x]];
+        }
+    }
+    const uint32_t sh = 32 * lg;
+    for (uint64_t k = k0; k < k1; k += STEP) {
+        uint64_t na[STEP][4], nb[STEP][4];
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+            const uint64_t kn = min(k + STEP + u, k1 - 1);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                na[u][x] = W[kn * ldw + ca[x]];
+                nb[u][x] = W[kn * ldw + cb[x]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < STEP; ++u) {
+            if (k + u >= k1) break;  // wave-uniform: the tail of the range
+            v8i va[4], vb[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) va[x] = bits32_fp4(lut, (uint32_t)(a[u][x] >> sh));
+#pragma unroll
+            for (int y = 0; y < 4; ++y) vb[y] = bits32_fp4(lut, (uint32_t)(b[u][y] >> sh));
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va[x], vb[y], acc[x][y], 4, 4, 0, 0,
+                                                                              0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < STEP; ++u)
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                a[u][x] = na[u][x];
+                b[u][x] = nb[u][x];
+            }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t i = I0 + 32 * x + 8 * (r >> 2) + 4 * lg + (r & 3);
+                const uint32_t j = J0 + 32 * y + lm;
+                const int32_t v = (int32_t)acc[x][y][r];  // an exact integer below 2^24
+                if (v && i < j && j < n) atomicAdd(B + out_index(i, j, n, upper), v);
+            }
+}
+
 // Row lists: one thread per row, every pair of its (ascending) samples.
 __global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__restrict__ ls, uint64_t nl,
                              uint32_t n, int32_t *__restrict__ B, int upper) {
@@ -510,15 +720,22 @@ __global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ 
 // Tile variants of the MFMA Gram: word rows per step of the K loop, and how
 // many blocks the K split aims for.  The autotuner (JAS_TUNE) times each on the
 // caller's db and keeps the fastest for dbs of the same shape.
+enum GramKind { kInt8 = 0, kInt8Wide = 1, kFp4 = 2, kFp4Wide = 3 };
 struct GramVariant {
     int step;
     uint64_t want_blocks;
-    bool wide;  // 256 x 256 tiles (k_gram_mfma_wide)
+    int kind;  // kInt8: k_gram_mfma; kInt8Wide: 256 x 256 tiles (k_gram_mfma_wide); kFp4: k_gram_fp4;
+               // kFp4Wide: k_gram_fp4_wide
 };
 // (wide variants with 2 word rows per step or at most 2048 blocks measured
 // slower on both dense workloads and are not listed)
-constexpr GramVariant kVariants[] = {{4, 2048, false}, {2, 2048, false}, {4, 1024, false}, {4, 4096, false},
-                                     {2, 4096, false}, {2, 1024, false}, {4, 4096, true},   {4, 8192, true}};
+// (int8 variants aimed at 1024 blocks, or with 2 rows per step at 2048, measured
+// slower everywhere and are not listed)
+constexpr GramVariant kVariants[] = {{4, 2048, kInt8},     {4, 4096, kInt8},     {2, 4096, kInt8},
+                                     {4, 4096, kInt8Wide}, {4, 8192, kInt8Wide}, {4, 2048, kFp4},
+                                     {2, 2048, kFp4},      {4, 4096, kFp4},      {2, 4096, kFp4},
+                                     {4, 8192, kFp4},      {2, 8192, kFp4},      {4, 4096, kFp4Wide},
+                                     {4, 8192, kFp4Wide},  {4, 16384, kFp4Wide}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 std::mutex g_tune_mu;
@@ -539,12 +756,22 @@ void k_split(uint64_t H, uint64_t np, uint64_t want, uint64_t &kper, uint64_t &s
 
 void launch_mfma(const jas_db *db, int v, hipStream_t s, int32_t *B, bool upper) {
     const uint32_t n = (uint32_t)db->n;
-    if (kVariants[v].wide) {
+    if (kVariants[v].kind == kInt8Wide || kVariants[v].kind == kFp4Wide) {
         const uint32_t nt = (uint32_t)div_up(n, kWideT);
         const uint64_t np = (uint64_t)nt * (nt + 1) / 2;
         uint64_t kper, splits;
         k_split(db->H, np, kVariants[v].want_blocks, kper, splits);
         const uint64_t ldw = div_up(n, 128) * 128;
+        if (kVariants[v].kind == kFp4Wide && kper > kFp4MaxK) {  // keep every block's float sums below 2^24
+            kper = kFp4MaxK / kKC * kKC;
+            splits = div_up(db->H, kper);
+        }
+        if (kVariants[v].kind == kFp4Wide && splits <= 65535) {
+            dim3 grid((uint32_t)np, (uint32_t)splits);
+            k_gram_fp4_wide<4><<<grid, kWideNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            return;
+        }
+        k_split(db->H, np, kVariants[v].want_blocks, kper, splits);
         dim3 grid((uint32_t)np, (uint32_t)splits);
         k_gram_mfma_wide<4><<<grid, kWideNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);  // 4 rows per step
         return;
@@ -554,6 +781,21 @@ void launch_mfma(const jas_db *db, int v, hipStream_t s, int32_t *B, bool upper)
     uint64_t kper, splits;
     k_split(db->H, np, kVariants[v].want_blocks, kper, splits);
     const uint64_t ldw = div_up(n, 128) * 128;
+    if (kVariants[v].kind == kFp4) {
+        if (kper > kFp4MaxK) {  // keep every block's float sums below 2^24
+            kper = kFp4MaxK / kKC * kKC;
+            splits = div_up(db->H, kper);
+        }
+        if (splits <= 65535) {
+            dim3 grid((uint32_t)np, (uint32_t)splits);
+            if (kVariants[v].step == 4)
+                k_gram_fp4<2, 4><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            else
+                k_gram_fp4<2, 2><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            return;
+        }
+        k_split(db->H, np, kVariants[v].want_blocks, kper, splits);  // too many blocks: the int8 kernel
+    }
     dim3 grid((uint32_t)np, (uint32_t)splits);
     if (kVariants[v].step == 4)
         k_gram_mfma<2, 4><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
@@ -624,7 +866,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
                 const auto it = g_tuned.find(key);
                 if (it != g_tuned.end()) v = it->second;
             }
-            JAS_TIMED("gram_mfma", s);
+            JAS_TIMED(kVariants[v].kind >= kFp4 ? "gram_fp4" : "gram_mfma", s);
             launch_mfma(db, v, s, B, upper);
         }
         check_launch("gram");
