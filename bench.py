@@ -4,7 +4,8 @@
 One step = jas_encode (stage/validate, sort + dedup, compaction, batches, pack,
 column sums) + jas_gram (packed-tile popcount Gram, row-list pairs, diagonal,
 unions, J) over one synthetic collection that is already resident in HBM.
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line: the pair rate, the roofline of the dominant kernel, the
+oracle's rate on a bounded sample, a serving run and per-kernel times.
 
   python bench.py [--steps K] [--warmup W] [--workload paperlike]
 """
@@ -180,7 +181,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="paperlike", choices=["tiny", "paperlike", "precision", "batching"])
+    ap.add_argument("--workload", default="paperlike",
+                    choices=["tiny", "paperlike", "precision", "batching", "bernoulli_p1e-4", "bernoulli_p1e-3",
+                             "bernoulli_p1e-2", "bernoulli_p1e-1"],
+                    help="bernoulli_p*: the paper's synthetic matrices (each entry 1 with probability p)")
     ap.add_argument("--dmin", type=int, default=0, help="dense_min_degree (0: library default)")
     ap.add_argument("--upper", action="store_true", help="packed upper-triangle outputs")
     ap.add_argument("--path", default="auto", choices=["auto", "popcount", "mfma"], help="Gram path for packed tiles")
@@ -338,7 +342,7 @@ def main():
     out = {"metric": "sample-pair intersections/s (exact B, C, J of all pairs i <= j)",
            "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "u64 keys / i32 counts / f64 J", "data": "synthetic (seeded generator, see DESIGN.md)",
+           "dtype": "u64 keys / i32 counts / f64 J", "data": "synthetic (seeded counter-based generator, synth/)",
            "config": {"workload": f"{args.workload}_n{n}_u{spec.universe_bits}", "n": n,
                       "universe_bits": spec.universe_bits, "batch_rows": f"2^{bb}", "ids": N,
                       "pairs_per_step": pairs, "layout": "upper" if args.upper else "full",

@@ -7,7 +7,9 @@ from here; neither shares anything else.
 Named workloads stand in for the paper's genome k-mer collections (Sec. V-A2,
 datasets not available): sizes, sharing structure, universe width and row
 batching follow the five configurations of this project (tiny, paper-like,
-precision, batching, serving).
+precision, batching, serving).  The ``bernoulli_*`` workloads are the paper's
+own synthetic indicator matrices (Sec. V-A2, Figs. 2e and 3): every entry of
+an m x n matrix is 1 with probability p, independently.
 """
 from __future__ import annotations
 
@@ -53,6 +55,8 @@ class _Spec(ctypes.Structure):
         ("dup_rate", ctypes.c_double),
         ("pool_start", ctypes.POINTER(ctypes.c_uint64)),
         ("pool_size", ctypes.POINTER(ctypes.c_uint64)),
+        ("density", ctypes.c_double),
+        ("rows", ctypes.c_uint64),
     ]
 
 
@@ -76,7 +80,8 @@ class Spec:
     """Parameters of one synthetic collection."""
     n: int
     universe_bits: int
-    size_kind: int            # 0 log-uniform [size_a, size_b]; 1 log-normal(median size_a, sigma size_b) clipped
+    size_kind: int            # 0 log-uniform [size_a, size_b]; 1 log-normal(median size_a, sigma size_b) clipped;
+                              # 2 Bernoulli: each of `rows` rows in each set with probability `density`
     size_a: float
     size_b: float
     share_lo: float
@@ -88,6 +93,8 @@ class Spec:
     size_lo: float = 0.0
     size_hi: float = 0.0
     dup_rate: float = 0.0
+    density: float = 0.0
+    rows: int = 0
 
     def replace(self, **kw) -> "Spec":
         return dataclasses.replace(self, **kw)
@@ -100,7 +107,8 @@ class Spec:
                   self.size_a, self.size_b, self.size_lo, self.size_hi,
                   self.share_lo, self.share_hi, self.dup_rate,
                   ctypes.cast(ps, ctypes.POINTER(ctypes.c_uint64)),
-                  ctypes.cast(pz, ctypes.POINTER(ctypes.c_uint64)))
+                  ctypes.cast(pz, ctypes.POINTER(ctypes.c_uint64)),
+                  self.density, self.rows)
         s._keep = (ps, pz)
         return s
 
@@ -109,11 +117,22 @@ def _u64p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
 
 
+_offsets_cache: dict = {}
+
+
 def offsets(spec: Spec) -> np.ndarray:
+    """CSR offsets (uint64[n+1]).  A Bernoulli set's size is known only by
+    drawing it, so those offsets are kept for the last few specs asked for."""
+    if spec.size_kind == 2 and spec in _offsets_cache:
+        return _offsets_cache[spec].copy()
     lib = _load()
     off = np.empty(spec.n + 1, dtype=np.uint64)
     cs = spec._c()
     lib.synth_offsets(ctypes.byref(cs), _u64p(off))
+    if spec.size_kind == 2:
+        while len(_offsets_cache) >= 4:
+            _offsets_cache.pop(next(iter(_offsets_cache)))
+        _offsets_cache[spec] = off.copy()
     return off
 
 
@@ -171,8 +190,27 @@ def _disjoint_pools(count: int, size: int):
     return tuple(c * size for c in range(count)), tuple(size for _ in range(count))
 
 
+def bernoulli(p: float, rows_log2: int = 25, n: int = 10000, seed: int = 0) -> Spec:
+    """Indicator matrix of 2^rows_log2 rows and n samples, each entry 1 with probability p.
+
+    IDs are the row indices, so the universe is exactly the rows (U = rows_log2)."""
+    return Spec(n=n, universe_bits=rows_log2, size_kind=2, size_a=0.0, size_b=0.0, share_lo=0.0, share_hi=0.0,
+                pool_start=(), pool_size=(), pool_seed=_SEED_BASE + 6, sample_seed=_SEED_BASE + 106 + seed,
+                density=float(p), rows=1 << rows_log2)
+
+
+# The density sweep: m = 2^25 (the paper's 32M rows), n = 10k, p = 1e-4 .. 1e-2;
+# at p = 0.1 the 3.4e10 IDs of m = 2^25 would not fit in HBM next to their
+# sort buffers, so that point takes m = 2^22.
+BERNOULLI = {"bernoulli_p1e-4": (1e-4, 25), "bernoulli_p1e-3": (1e-3, 25), "bernoulli_p1e-2": (1e-2, 25),
+             "bernoulli_p1e-1": (1e-1, 22)}
+
+
 def workload(name: str) -> Spec:
-    """The five configurations (full size)."""
+    """The five configurations (full size), and the Bernoulli density sweep."""
+    if name in BERNOULLI:
+        p, rl = BERNOULLI[name]
+        return bernoulli(p, rl)
     if name == "tiny":
         # n=32, universe 2^24, sizes log-uniform [1e3,1e5], share U[0,0.8] of one 2^16 pool
         return Spec(n=32, universe_bits=24, size_kind=0, size_a=1e3, size_b=1e5,
@@ -214,6 +252,7 @@ def query_spec(db: Spec, request: int, nq: int) -> Spec:
 
 # Batch rows (the paper's m~) used with each workload, as log2.
 BATCH_BITS = {"tiny": 24, "paperlike": 26, "precision": 32, "batching": 26, "serving_db": 26}
+BATCH_BITS.update({name: rl for name, (p, rl) in BERNOULLI.items()})  # one batch of all rows
 
 
 def scaled(spec: Spec, n: Optional[int] = None, size_scale: float = 1.0, pool_scale: float = 1.0,

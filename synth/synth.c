@@ -17,6 +17,14 @@
  * index space; pool index g maps to the ID perm_U(g), a keyed bijection on
  * U-bit integers, so pool IDs are distinct and spread over the universe.
  *
+ * Bernoulli collections (size_kind 2) follow the paper's synthetic indicator
+ * matrices (Sec. V-A2): each of `rows` row indices is in each set
+ * independently with probability `density`.  A set is drawn by geometric skips
+ * (the gap to the next present row is 1 + floor(ln(1-u) / ln(1-p)) for
+ * uniform u; Devroye, "Non-Uniform Random Variate Generation", 1986, Ch. X),
+ * so its cost is its size, not `rows`; its IDs come out in increasing order
+ * and its size is known only once it is drawn.
+ *
  * Randomness: SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom
  * number generators", OOPSLA 2014) used in counter mode: the k-th value of
  * stream `key` is mix(key + (k+1) * gamma).  Every element is a pure function
@@ -99,9 +107,40 @@ typedef struct {
     double dup_rate;
     const uint64_t *pool_start; /* n_pools entries */
     const uint64_t *pool_size;  /* n_pools entries */
+    double density;        /* size_kind 2: probability that a row is in a set */
+    uint64_t rows;         /* size_kind 2: row indices 0 .. rows-1 */
 } synth_spec;
 
-enum { TAG_PARAM = 1, TAG_POOLPERM = 2, TAG_PRIVATE = 3, TAG_DUP = 4, TAG_IDPERM = 5 };
+enum { TAG_PARAM = 1, TAG_POOLPERM = 2, TAG_PRIVATE = 3, TAG_DUP = 4, TAG_IDPERM = 5, TAG_BERNOULLI = 6 };
+
+enum { KIND_LOG_UNIFORM = 0, KIND_LOG_NORMAL = 1, KIND_BERNOULLI = 2 };
+
+/* Bernoulli set of sample i: writes its rows to dst (if not NULL) in
+ * increasing order and returns how many there are. */
+static uint64_t bernoulli_walk(const synth_spec *sp, int32_t i, uint64_t *dst)
+{
+    const uint64_t m = sp->rows;
+    const double p = sp->density;
+    if (!(p > 0.0) || m == 0) return 0;
+    if (p >= 1.0) {
+        if (dst)
+            for (uint64_t r = 0; r < m; ++r) dst[r] = r;
+        return m;
+    }
+    const uint64_t key = stream_key(sp->sample_seed, TAG_BERNOULLI, (uint64_t)i);
+    const double inv = 1.0 / log1p(-p); /* negative */
+    uint64_t count = 0, next = 0;       /* next: first row not yet passed */
+    for (uint64_t t = 0;; ++t) {
+        const double skip = floor(log1p(-u01(sm_at(key, t))) * inv); /* rows left out before the next one */
+        if (skip >= (double)(m - next)) break;
+        const uint64_t r = next + (uint64_t)skip;
+        if (dst) dst[count] = r;
+        ++count;
+        next = r + 1;
+        if (next >= m) break;
+    }
+    return count;
+}
 
 typedef struct {
     uint64_t size, pool_part, dups;
@@ -111,11 +150,17 @@ typedef struct {
 static sample_plan plan_sample(const synth_spec *sp, int32_t i)
 {
     sample_plan p;
+    if (sp->size_kind == KIND_BERNOULLI) {
+        p.size = bernoulli_walk(sp, i, NULL);
+        p.pool_part = p.dups = 0;
+        p.cluster = -1;
+        return p;
+    }
     const uint64_t key = stream_key(sp->sample_seed, TAG_PARAM, (uint64_t)i);
     const double u0 = u01(sm_at(key, 0)), u1 = u01(sm_at(key, 1));
     const double u2 = u01(sm_at(key, 2)), u3 = u01(sm_at(key, 3));
     double s;
-    if (sp->size_kind == 0) {
+    if (sp->size_kind == KIND_LOG_UNIFORM) {
         s = exp(log(sp->size_a) + u0 * (log(sp->size_b) - log(sp->size_a)));
     } else {
         /* Box-Muller normal from (u0, u1) */
@@ -141,10 +186,12 @@ static sample_plan plan_sample(const synth_spec *sp, int32_t i)
 int synth_offsets(const synth_spec *sp, uint64_t *offsets)
 {
     offsets[0] = 0;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t i = 0; i < sp->n; ++i) {
         const sample_plan p = plan_sample(sp, i);
-        offsets[i + 1] = offsets[i] + p.size + p.dups;
+        offsets[i + 1] = p.size + p.dups;
     }
+    for (int32_t i = 0; i < sp->n; ++i) offsets[i + 1] += offsets[i];
     return 0;
 }
 
@@ -161,6 +208,10 @@ int synth_plan(const synth_spec *sp, int32_t i, uint64_t *out4)
 
 static void fill_one(const synth_spec *sp, int32_t i, uint64_t *dst)
 {
+    if (sp->size_kind == KIND_BERNOULLI) {
+        bernoulli_walk(sp, i, dst);
+        return;
+    }
     const sample_plan p = plan_sample(sp, i);
     const uint32_t U = sp->universe_bits;
     const uint64_t mU = low_mask(U);

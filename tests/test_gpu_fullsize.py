@@ -81,7 +81,24 @@ def check_properties(res, n, upper):
     assert np.array_equal(B[d], ci[d]) and np.all(J[d] == 1.0)
 
 
-@pytest.mark.parametrize("name,upper", [("paperlike", False), ("precision", False), ("batching", True)])
+def check_bernoulli_means(res, spec, upper):
+    """Entries 1 with probability p, independently: off the diagonal B_ij has
+    mean m p^2 and J_ij about p / (2 - p); the sample sizes have mean m p."""
+    n, m, p = spec.n, spec.rows, spec.density
+    if upper:
+        i, j = np.triu_indices(n)
+        off_diag = i != j
+        B, J = res["B"][off_diag], res["J"][off_diag]
+    else:
+        mask = ~np.eye(n, dtype=bool)
+        B, J = res["B"].reshape(n, n)[mask], res["J"].reshape(n, n)[mask]
+    assert abs(res["card"].mean() / (m * p) - 1) < 1e-3
+    assert abs(B.mean() / (m * p * p) - 1) < 5e-3
+    assert abs(J.mean() / (p / (2 - p)) - 1) < 5e-3
+
+
+@pytest.mark.parametrize("name,upper", [("paperlike", False), ("precision", False), ("batching", True),
+                                        ("bernoulli_p1e-3", True), ("bernoulli_p1e-2", True)])
 def test_full_size_all_pairs(name, upper):
     spec = synth.workload(name)
     n = spec.n
@@ -105,6 +122,8 @@ def test_full_size_all_pairs(name, upper):
     pts, pairs = sample_pairs(n, sizes, rng)
     check_sampled(spec, res, pts, pairs, upper)
     check_properties(res, n, upper)
+    if spec.size_kind == 2:
+        check_bernoulli_means(res, spec, upper)
     # the popcount path gives the same bytes as the MFMA path on this db
     if not upper:
         B2 = torch.empty(length, dtype=torch.int32, device="cuda")

@@ -93,6 +93,28 @@ def test_scaled_workloads(name, dmin):
         assert st["dense_min_degree"] >= 2
 
 
+# The paper's synthetic indicator matrices (Sec. V-A2): each entry 1 with
+# probability p.  From rows of degree ~0.3 (row lists) to p = 1, where every
+# set holds every row (B = m, J = 1); one batch of all rows and 16 batches.
+BERNOULLI_CASES = [(1e-3, 16, 300), (1e-2, 14, 200), (0.1, 12, 150), (0.5, 10, 130), (1.0, 9, 70)]
+
+
+@pytest.mark.parametrize("p,rows_log2,n", BERNOULLI_CASES)
+@pytest.mark.parametrize("batches", [1, 16])
+@pytest.mark.parametrize("path", ["auto", "popcount"])
+def test_bernoulli_matrices(p, rows_log2, n, batches, path):
+    spec = synth.bernoulli(p, rows_log2, n, seed=batches)
+    ids, off = synth.generate(spec)
+    ref = oracle.all_pairs(ids, off)
+    flags = cabi.JAS_FORCE_POPCOUNT if path == "popcount" else 0
+    bb = rows_log2 - (batches.bit_length() - 1)
+    res, st = gpu_all_pairs(ids, off, rows_log2, bb, 0, flags=flags)
+    assert_matches(res, ref)
+    if p == 1.0:
+        assert np.all(res["B"] == 1 << rows_log2) and np.all(res["J"] == 1.0)
+        assert st["n_packed_rows"] == 1 << rows_log2
+
+
 def test_duplicates_and_empty_sets():
     spec = synth.scaled(synth.workload("tiny"), n=40, dup_rate=0.3)
     ids, off = synth.generate(spec)

@@ -51,3 +51,52 @@ def test_duplicates_injected():
         size, k, dups, c = synth.plan(s, i)
         assert x.size == size + dups and dups > 0
         assert np.unique(x).size <= size
+
+
+def _sets(ids, off):
+    return [ids[int(off[i]):int(off[i + 1])].astype(np.int64) for i in range(off.size - 1)]
+
+
+def test_bernoulli_sets_are_increasing_rows():
+    s = synth.bernoulli(0.02, rows_log2=14, n=64)
+    ids, off = synth.generate(s)
+    for x in _sets(ids, off):
+        assert x.size == 0 or (x.min() >= 0 and x.max() < (1 << 14))
+        assert np.all(np.diff(x) > 0)
+    c, co = synth.generate_samples(s, [5, 63, 0])
+    for k, i in enumerate([5, 63, 0]):
+        assert np.array_equal(c[int(co[k]):int(co[k + 1])], ids[int(off[i]):int(off[i + 1])])
+
+
+def test_bernoulli_entry_statistics():
+    # every entry present with probability p, independently (Sec. V-A2's synthetic matrices):
+    # set sizes have mean m p; a row follows a present row with probability p
+    # (a skip off by one makes that 0 or 1); the rows are spread evenly
+    m_log2, n, p = 16, 400, 0.01
+    m = 1 << m_log2
+    ids, off = synth.generate(synth.bernoulli(p, rows_log2=m_log2, n=n))
+    sizes = np.diff(off.astype(np.int64))
+    mean_sd = np.sqrt(m * p * (1 - p) / n)
+    assert abs(sizes.mean() - m * p) < 6 * mean_sd
+    assert abs(sizes.var() / (m * p * (1 - p)) - 1) < 0.25  # binomial variance
+    follow = sum(int(np.count_nonzero(np.diff(x) == 1)) for x in _sets(ids, off))
+    trials = int(sizes.sum()) - n
+    assert abs(follow / trials - p) < 6 * np.sqrt(p * (1 - p) / trials)
+    per_block = np.bincount(ids.astype(np.int64) >> (m_log2 - 4), minlength=16)
+    expect = n * (m / 16) * p
+    assert np.all(np.abs(per_block - expect) < 6 * np.sqrt(expect))
+
+
+def test_bernoulli_degenerate_densities():
+    ids, off = synth.generate(synth.bernoulli(1.0, rows_log2=10, n=3))
+    assert np.array_equal(off, np.arange(4, dtype=np.uint64) * 1024)
+    assert np.array_equal(ids, np.tile(np.arange(1024, dtype=np.uint64), 3))
+    ids, off = synth.generate(synth.bernoulli(0.0, rows_log2=10, n=3))
+    assert ids.size == 0 and np.all(off == 0)
+
+
+def test_bernoulli_sweep_sizes():
+    for name, (p, rl) in synth.BERNOULLI.items():
+        s = synth.workload(name)
+        assert s.n == 10000 and s.rows == 1 << rl and s.universe_bits == rl and synth.BATCH_BITS[name] == rl
+        assert s.density == p
