@@ -885,33 +885,84 @@ __global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint32_t *row_deg,
     }
 }
 
-// One lane per row: a wave's 64 consecutive rows own one contiguous stretch of
-// the output, which is assembled in LDS and written out coalesced (written
-// directly when it exceeds the stage).  The rows' samples are one span of the
+// A wave takes 64 consecutive rows; their pairs fill one contiguous stretch
+// of the output (the rows' pair counts scanned).  When the stretch fits an
+// LDS stage, each lane writes its own row's pairs there and the wave copies
+// the stage out coalesced.  Otherwise each lane produces output words
+// o = lane, lane + 64, ...: the row that holds o comes from a binary search
+// over the wave's row starts, the pair (i, j) inside the row from the inverse
+// of the triangular count P(i) = i (2d - i - 1) / 2 of the pairs whose smaller
+// entry comes before i, so consecutive lanes write consecutive words whatever
+// the row lengths (one lane per row would leave most lanes idle behind the
+// longest row and scatter the stores).  The rows' samples are one span of the
 // sample array (the rows ascend), read into LDS with coalesced loads first
-// when it fits, so the pair loops wait on LDS rather than on memory.  Per-block
-// LDS totals of the sort digits of a (digit q = bits [16 + width*q, 16 +
-// width*(q+1)) of the word).
-// Stage sizes measured best of 256..3072: larger ones cost more occupancy
-// than they save in unstaged waves.
+// when it fits (else only the rows' own entries, packed, when those fit), so
+// the pair loops read LDS rather than memory.  Per-block LDS totals of the
+// sort digits (digit q = bits [16 + width*q, 16 + width*(q+1)) of the word)
+// come from one pass over each row's entries.
+// Stage sizes measured best of 256..3072 for one-lane-per-row emission.
 constexpr uint32_t kEmitStage = 1024;  // output words per wave
 constexpr uint32_t kEmitIn = 512;      // sample entries per wave
 constexpr uint32_t kPairPasses = 2;   // 16 sample bits, 8-bit digits
 
-template <bool kStagedIn, bool kStagedOut>
-__device__ __forceinline__ void emit_row_pairs(const uint32_t *__restrict__ ls, const uint32_t *sin, uint64_t span0,
-                                               uint64_t e0, uint64_t e1, uint64_t o, uint32_t *st,
-                                               uint32_t *__restrict__ pairs, uint64_t base, uint32_t (*gh)[256],
-                                               uint32_t npass, uint32_t width, uint32_t dmask) {
-    for (uint64_t i = e0; i + 1 < e1; ++i) {
-        const uint32_t a = kStagedIn ? sin[i - span0] : ls[i];
-        const uint32_t m = (uint32_t)(e1 - i - 1);  // pairs with a as the smaller sample
-        for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(a >> (width * q)) & dmask], m);
-        for (uint64_t j = i + 1; j < e1; ++j, ++o) {
-            const uint32_t v = (a << 16) | (kStagedIn ? sin[j - span0] : ls[j]);
-            if (kStagedOut) st[o] = v;
-            else pairs[base + o] = v;
+// Largest i in [0, d-2] with P(i) <= k, for 0 <= k < d(d-1)/2 and 2 <= d <= 2^14:
+// the smaller root of i^2 - (2d-1) i + 2k = 0 in float, then corrected by
+// exact integer steps (the estimate is off by at most one).
+__device__ __forceinline__ uint32_t pair_first(uint32_t d, uint32_t k) {
+    const uint32_t b = 2 * d - 1;
+    const float disc = (float)(b * b - 8u * k);
+    int32_t i = (int32_t)(((float)b - sqrtf(disc)) * 0.5f);
+    i = max(0, min(i, (int32_t)d - 2));
+    const auto P = [d](int32_t x) { return (uint32_t)x * (2 * d - (uint32_t)x - 1) / 2; };
+    while (i + 1 <= (int32_t)d - 2 && P(i + 1) <= k) ++i;
+    while (i > 0 && P(i) > k) --i;
+    return (uint32_t)i;
+}
+
+// Digit totals of one row: entry i is the smaller sample of deg - 1 - i pairs.
+template <class Src>
+__device__ __forceinline__ void row_digit_totals(Src src, uint64_t sb, uint32_t deg, uint32_t (*gh)[256],
+                                                 uint32_t npass, uint32_t width, uint32_t dmask) {
+    for (uint32_t i = 0; i + 1 < deg; ++i) {
+        const uint32_t a = src[sb + i];
+        for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(a >> (width * q)) & dmask], deg - 1 - i);
+    }
+}
+
+// A wave whose pairs fit the stage: this lane's row's pairs, in order, at
+// stage word o onwards.
+template <class Src>
+__device__ __forceinline__ void stage_row_pairs(Src src, uint64_t sb, uint32_t deg, uint32_t o, uint32_t *st) {
+    for (uint32_t i = 0; i + 1 < deg; ++i) {
+        const uint32_t a = src[sb + i] << 16;
+        for (uint32_t j = i + 1; j < deg; ++j) st[o++] = a | src[sb + j];
+    }
+}
+
+// The wave's pairs from its rows' entries src[sb + i] (LDS or global), one
+// output word per lane at a time.  rst[0..64] are the rows' first words
+// (rst[64] = total); a lane's words ascend, so its row only moves forward.
+template <class Src>
+__device__ __forceinline__ void emit_wave_pairs(Src src, uint32_t total, uint32_t lane, const uint32_t *rst,
+                                                const uint32_t *rdg, const uint64_t *rsb,
+                                                uint32_t *__restrict__ out) {
+    uint32_t t = 0, d = rdg[0], k0 = 0;
+    uint64_t s0 = rsb[0];
+    for (uint32_t o = lane; o < total; o += kWave) {
+        // row t: the largest with rst[t] <= o (a row without pairs shares its
+        // successor's start, so it is never the largest)
+        if (rst[t + 1] <= o) {
+            do {
+                ++t;
+            } while (rst[t + 1] <= o);
+            d = rdg[t];
+            k0 = rst[t];
+            s0 = rsb[t];
         }
+        const uint32_t k = o - k0;
+        const uint32_t i = pair_first(d, k);
+        const uint32_t j = i + 1 + (k - i * (2 * d - i - 1) / 2);
+        out[o] = (src[s0 + i] << 16) | src[s0 + j];
     }
 }
 
@@ -923,15 +974,21 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
                                                     uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
                                                     unsigned long long *__restrict__ ghist) {
     __shared__ uint32_t gh[kPairPasses][256];
-    __shared__ uint32_t stg[256 / kWave][kEmitStage];
+    // per wave: the output stage, or (for waves whose pairs do not fit it)
+    // the rows' first output words, degrees and first entries
+    __shared__ uint64_t stgb[256 / kWave][kEmitStage / 2];
     __shared__ uint32_t sinb[256 / kWave][kEmitIn];
+    static_assert(2 * kWave + (kWave + 2) + kWave <= kEmitStage, "row tables exceed the stage");  // 32-bit words
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint32_t dmask = (1u << width) - 1u;
 #pragma unroll
     for (int k = 0; k < kPairPasses; ++k) gh[k][tid] = 0;
     __syncthreads();
-    uint32_t *st = stg[w];
     uint32_t *sin = sinb[w];
+    uint32_t *stg = reinterpret_cast<uint32_t *>(stgb[w]);
+    uint64_t *rsb = stgb[w];                                  // kWave entries
+    uint32_t *rst = reinterpret_cast<uint32_t *>(rsb + kWave);  // kWave + 1 entries
+    uint32_t *rdg = rst + kWave + 2;                          // kWave entries
     for (uint64_t r0 = ((uint64_t)blockIdx.x * (256 / kWave) + w) * kWave; r0 < QL;
          r0 += (uint64_t)gridDim.x * 256) {
         const uint64_t r = r0 + lane;
@@ -943,29 +1000,31 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
             e1 = e0 + row_deg[rr];
         }
         // the wave's first pair (wpo: scan of the 64-row groups' pair counts)
-        // and this row's pairs before it within the group
+        // and this row's pairs before it within the group; a list row has at
+        // most n <= kSampleMajorMaxN entries, so a wave's 64 rows hold fewer
+        // than 2^32 pairs
         const uint64_t base = wpo[r0 / kWave];
-        const uint64_t np = (e1 - e0) * (e1 - e0 - (e1 > e0 ? 1 : 0)) / 2;
-        const uint64_t incl = wave_incl_scan(np);
-        const uint64_t total = __shfl(incl, kWave - 1, kWave);
-        const uint64_t my = incl - np;
+        const uint32_t deg = (uint32_t)(e1 - e0);
+        const uint32_t np = deg * (deg - (deg ? 1u : 0u)) / 2;
+        const uint32_t incl = (uint32_t)wave_incl_scan((uint64_t)np);
+        const uint32_t total = __shfl(incl, kWave - 1, kWave);
         // the rows' samples in LDS: the whole span of the sample array when it
         // fits (coalesced), else only the rows' own entries packed one after
         // another (when the span has gaps: rows of other kinds or the ends of
-        // LDS ranges); sin[i - span0] is entry i of this lane's row
-        const uint64_t deg = e1 - e0;
-        const uint64_t dincl = wave_incl_scan(deg);
+        // LDS ranges)
+        const uint64_t dincl = wave_incl_scan((uint64_t)deg);
         const uint64_t dtot = __shfl(dincl, kWave - 1, kWave);
-        uint64_t span0 = __shfl(e0, 0, kWave);
+        const uint64_t span0 = __shfl(e0, 0, kWave);
         const uint64_t span1 = __shfl(e1, (int)last, kWave);
-        const bool whole = span1 - span0 <= kEmitIn;               // wave-uniform
-        const bool staged_in = whole || dtot <= kEmitIn;          // wave-uniform
-        const bool staged = total <= kEmitStage;                  // wave-uniform
+        const bool whole = span1 - span0 <= kEmitIn;       // wave-uniform
+        const bool staged_in = whole || dtot <= kEmitIn;  // wave-uniform
+        uint64_t sb = e0;                                  // entry i of this row: src[sb + i]
         if (whole) {
             for (uint64_t k = lane; k < span1 - span0; k += kWave) sin[k] = ls[span0 + k];
+            sb = e0 - span0;
         } else if (staged_in) {
-            const uint64_t off = dincl - deg;  // e0 >= off: the rows ascend without overlap
-            for (uint64_t k = 0; k < deg; k += 4) {
+            const uint64_t off = dincl - deg;
+            for (uint32_t k = 0; k < deg; k += 4) {
                 uint32_t v[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) v[u] = k + u < deg ? ls[e0 + k + u] : 0u;
@@ -973,26 +1032,32 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
                 for (int u = 0; u < 4; ++u)
                     if (k + u < deg) sin[off + k + u] = v[u];
             }
-            span0 = e0 - off;
+            sb = off;
         }
-        if (staged_in) {
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+        const bool fits = total <= kEmitStage;  // wave-uniform
+        if (!fits) {
+            rsb[lane] = sb;
+            rst[lane] = incl - np;
+            rdg[lane] = deg;
+            if (lane == 0) rst[kWave] = total;
         }
-        if (staged_in && staged)
-            emit_row_pairs<true, true>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
-        else if (staged_in)
-            emit_row_pairs<true, false>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
-        else if (staged)
-            emit_row_pairs<false, true>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
-        else
-            emit_row_pairs<false, false>(ls, sin, span0, e0, e1, my, st, pairs, base, gh, npass, width, dmask);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        if (staged) {
-            for (uint32_t k = lane; k < total; k += kWave) pairs[base + k] = st[k];
+        if (staged_in) row_digit_totals(sin, sb, deg, gh, npass, width, dmask);
+        else row_digit_totals(ls, sb, deg, gh, npass, width, dmask);
+        if (fits) {
+            if (staged_in) stage_row_pairs(sin, sb, deg, incl - np, stg);
+            else stage_row_pairs(ls, sb, deg, incl - np, stg);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            for (uint32_t k = lane; k < total; k += kWave) pairs[base + k] = stg[k];
+        } else if (staged_in) {
+            emit_wave_pairs(sin, total, lane, rst, rdg, rsb, pairs + base);
+        } else {
+            emit_wave_pairs(ls, total, lane, rst, rdg, rsb, pairs + base);
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     unsigned long long *g = ghist + (uint64_t)(blockIdx.x % kGhistReplicas) * kMaxPasses * 256;
