@@ -127,7 +127,9 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
  * for every later db on the device with the same n and the same power of two
  * of word rows, and is used by later calls without the flag.  Not capturable
  * in a HIP graph; calls without it are.  JAS_GRAM_VARIANT(v) runs variant v
- * instead of the kept or default choice (EINVAL for v out of range).
+ * instead of the kept or default choice (EINVAL for v out of range).  The
+ * default, with nothing kept, is fp4 with 128 x 128 tiles below n = 2048 and
+ * 256 x 256 tiles from there on.
  */
 jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t *B, int64_t *card, int64_t *den,
                     double *J);

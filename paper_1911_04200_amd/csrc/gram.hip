@@ -737,6 +737,12 @@ constexpr GramVariant kVariants[] = {{4, 2048, kInt8},     {4, 4096, kInt8},    
                                      {4, 8192, kFp4},      {2, 8192, kFp4},      {4, 4096, kFp4Wide},
                                      {4, 8192, kFp4Wide},  {4, 16384, kFp4Wide}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+// Untuned choice, from the tuner's timings on MI355X: 128 x 128 fp4 tiles
+// below n = 2048 (n = 1024: 6.5 ms against 10.6 for int8 tiles), 256 x 256 fp4
+// tiles from there on (n = 4096: 16.7 against 26.9 ms; n = 10000: 0.75 against
+// 1.09 s), each aimed at 8192 blocks.
+constexpr int kDefaultNarrow = 9, kDefaultWide = 12;
+static_assert(kVariants[kDefaultNarrow].kind == kFp4 && kVariants[kDefaultWide].kind == kFp4Wide, "defaults");
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, uint32_t, uint32_t>, int> g_tuned;  // (device, n, ceil(log2 H)) -> variant
@@ -829,7 +835,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
             k_gram_popc<<<grid, kNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
         } else {
             const auto key = std::make_tuple(db->device, n, ceil_log2_u64(db->H));
-            int v = 0;
+            int v = n >= 2048 ? kDefaultWide : kDefaultNarrow;
             const uint32_t forced = (flags >> 16) & 0xFFu;  // JAS_GRAM_VARIANT(v): v + 1
             if (forced) {
                 v = (int)forced - 1;

@@ -10,10 +10,10 @@
 //   time(t)   = pairs(t) / r_pair + rows(t) / r_row + words(t) * 128^2 T / r_word
 // The threshold t minimising time(t) is taken, among those whose packed matrix
 // (words(t) * 8 * ceil(n/128)*128 bytes) fits the memory cap.  The rates were
-// fitted on MI355X to the row-list kernels (7.4e10 pairs/s and 1.6e10 rows/s)
-// and to k_pack + k_gram_mfma (1.9e13 word pairs/s) over a sweep of
-// thresholds on the paper-like workload, whose measured optimum (t = 8) the
-// model reproduces.
+// fitted on MI355X to the row-list kernels (7.4e10 pairs/s and 1.6e10 rows/s,
+// over a sweep of thresholds on the paper-like workload) and to k_pack plus
+// the default fp4 Gram tiles (2.4e13 to 3.4e13 word pairs/s on n = 1024, 4096
+// and 10000; 2.6e13 taken).
 #include <algorithm>
 #include <cmath>
 
@@ -24,7 +24,7 @@ namespace jas {
 namespace {
 constexpr double kPairRate = 7.4e10;   // row-list pair counts per second
 constexpr double kRowRate = 1.6e10;    // row-list rows filed per second
-constexpr double kWordRate = 1.9e13;   // packed 64-bit word pairs per second (pack + MFMA kernel)
+constexpr double kWordRate = 2.6e13;   // packed 64-bit word pairs per second (pack + MFMA kernel)
 }  // namespace
 
 uint32_t choose_dense_min_degree(const std::vector<uint64_t> &h, uint32_t n, uint64_t nbatches,
