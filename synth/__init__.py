@@ -8,7 +8,7 @@ Named workloads stand in for the paper's genome k-mer collections (Sec. V-A2,
 datasets not available): sizes, sharing structure, universe width and row
 batching follow the five configurations of this project (tiny, paper-like,
 precision, batching, serving).  The ``bernoulli_*`` workloads are the paper's
-own synthetic indicator matrices (Sec. V-A2, Figs. 2e and 3): every entry of
+own synthetic indicator matrices (Sec. V-A3, swept over p in Sec. V-C): every entry of
 an m x n matrix is 1 with probability p, independently.
 """
 from __future__ import annotations

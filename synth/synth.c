@@ -18,7 +18,7 @@
  * U-bit integers, so pool IDs are distinct and spread over the universe.
  *
  * Bernoulli collections (size_kind 2) follow the paper's synthetic indicator
- * matrices (Sec. V-A2): each of `rows` row indices is in each set
+ * matrices (Sec. V-A3): each of `rows` row indices is in each set
  * independently with probability `density`.  A set is drawn by geometric skips
  * (the gap to the next present row is 1 + floor(ln(1-u) / ln(1-p)) for
  * uniform u; Devroye, "Non-Uniform Random Variate Generation", 1986, Ch. X),

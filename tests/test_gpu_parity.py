@@ -93,7 +93,7 @@ def test_scaled_workloads(name, dmin):
         assert st["dense_min_degree"] >= 2
 
 
-# The paper's synthetic indicator matrices (Sec. V-A2): each entry 1 with
+# The paper's synthetic indicator matrices (Sec. V-A3): each entry 1 with
 # probability p.  From rows of degree ~0.3 (row lists) to p = 1, where every
 # set holds every row (B = m, J = 1); one batch of all rows and 16 batches.
 BERNOULLI_CASES = [(1e-3, 16, 300), (1e-2, 14, 200), (0.1, 12, 150), (0.5, 10, 130), (1.0, 9, 70)]

@@ -69,7 +69,7 @@ def test_bernoulli_sets_are_increasing_rows():
 
 
 def test_bernoulli_entry_statistics():
-    # every entry present with probability p, independently (Sec. V-A2's synthetic matrices):
+    # every entry present with probability p, independently (Sec. V-A3's synthetic matrices):
     # set sizes have mean m p; a row follows a present row with probability p
     # (a skip off by one makes that 0 or 1); the rows are spread evenly
     m_log2, n, p = 16, 400, 0.01
