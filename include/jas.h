@@ -54,6 +54,7 @@ typedef enum {
 #define JAS_FORCE_POPCOUNT 0x20u /* jas_gram: every packed tile on the AND+popcount kernel */
 #define JAS_FORCE_MFMA 0x40u    /* jas_gram: every packed tile on an MFMA kernel (int8, or fp4 with exact float sums) */
 #define JAS_TUNE 0x80u          /* jas_gram: time the MFMA tile variants on this db first (see jas_gram) */
+#define JAS_ACCUMULATE 0x100u   /* jas_gram: add this db's counts into B and card (one row batch of many) */
 /* jas_gram: run MFMA tile variant v, 0 <= v < jas_gram_variants() (bits 16..23 hold v + 1) */
 #define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)
 
@@ -130,9 +131,35 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
  * instead of the kept or default choice (EINVAL for v out of range).  The
  * default, with nothing kept, is fp4 with 128 x 128 tiles below n = 2048 and
  * 256 x 256 tiles from there on.
+ * JAS_ACCUMULATE (row batches streamed one db at a time, the sum over batches
+ * l of Eq. (4)): B_ij (i < j) and card_i are added to instead of written, and
+ * nothing else is written: card is required, den and J must be NULL, and
+ * JAS_TUNE is refused.  The caller clears B and card before the first batch
+ * (torch's zero_() or a fill kernel; hipMemsetAsync where no graph is
+ * captured) and calls jas_finalize after the last one; until then the
+ * diagonal and, in the full layout, the lower triangle of B are undefined.
+ * The db of each batch must hold the same n samples; a row (ID) may appear in
+ * only one of them.
  */
 jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t *B, int64_t *card, int64_t *den,
                     double *J);
+
+/*
+ * jas_finalize -- the last step of a streamed product: from the summed
+ * intersections B (i < j entries, as left by jas_gram with JAS_ACCUMULATE) and
+ * the summed sizes card, write the diagonal B_ii = |X_i|, in the full layout
+ * the lower triangle B_ji = B_ij, and (where not NULL) the unions
+ * C_ij = |X_i| + |X_j| - B_ij and J_ij = B_ij / C_ij (1.0 where C_ij = 0),
+ * exactly as jas_gram does for one db (Sec. III-A, Eq. (2)).
+ *  n       number of samples, >= 0.
+ *  flags   JAS_UPPER (the layout B was accumulated in); device pointers only.
+ *  B       int32, device, n*n or n(n+1)/2 entries: read and completed.
+ *  card    int64[n], device: |X_i| summed over the batches.
+ *  den, J  as in jas_gram; may be NULL.
+ * Asynchronous on hip_stream.  EINVAL for n < 0, NULL B or card, other flags.
+ */
+jas_status jas_finalize(int32_t n, uint32_t flags, void *hip_stream, int32_t *B, const int64_t *card, int64_t *den,
+                        double *J);
 
 /* Number of MFMA tile variants jas_gram can run (tile shape, word rows per
  * step, K split); variant indices are stable within one build of the library. */

@@ -236,6 +236,11 @@ jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t 
         const uint32_t var = (flags >> 16) & 0xFFu;
         if (var && (var > (uint32_t)gram_variants() || (flags & (JAS_TUNE | JAS_FORCE_POPCOUNT))))
             fail(JAS_EINVAL, "jas_gram: bad JAS_GRAM_VARIANT");
+        if (flags & JAS_ACCUMULATE) {
+            if (!card && db->n > 0) fail(JAS_EINVAL, "jas_gram: JAS_ACCUMULATE needs card");
+            if (den || J) fail(JAS_EINVAL, "jas_gram: JAS_ACCUMULATE writes no den or J (see jas_finalize)");
+            if (flags & (JAS_TUNE | JAS_HOST_PTRS)) fail(JAS_EINVAL, "jas_gram: JAS_ACCUMULATE with JAS_TUNE or JAS_HOST_PTRS");
+        }
         hipStream_t s = (hipStream_t)hip_stream;
         const uint64_t n = (uint64_t)db->n;
         const uint64_t len = (flags & JAS_UPPER) ? n * (n + 1) / 2 : n * n;
@@ -257,6 +262,17 @@ jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t 
         if (den) JAS_HIP(hipMemcpyAsync(den, dD.p, len * 8, hipMemcpyDeviceToHost, s));
         if (J) JAS_HIP(hipMemcpyAsync(J, dJ.p, len * 8, hipMemcpyDeviceToHost, s));
         JAS_HIP(hipStreamSynchronize(s));
+    });
+}
+
+jas_status jas_finalize(int32_t n, uint32_t flags, void *hip_stream, int32_t *B, const int64_t *card, int64_t *den,
+                        double *J) {
+    return guard([&] {
+        if (n < 0) fail(JAS_EINVAL, "jas_finalize: n < 0");
+        if (flags & ~(uint32_t)JAS_UPPER) fail(JAS_EINVAL, "jas_finalize: only JAS_UPPER is accepted");
+        if (n > 0 && (!B || !card)) fail(JAS_EINVAL, "jas_finalize: B or card is NULL");
+        JAS_HOST_TIMED("jas_finalize");
+        finalize((uint32_t)n, flags & JAS_UPPER, (hipStream_t)hip_stream, B, card, den, J);
     });
 }
 

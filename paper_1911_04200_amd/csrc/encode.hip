@@ -39,7 +39,8 @@ constexpr int kRounds = 16;
 constexpr uint32_t kTile = kNT * kRounds;  // 4096
 constexpr uint64_t kChunk = 65536;         // elements per classify block
 constexpr int32_t kHistMax = 16384;        // LDS column histogram up to this n
-constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass
+constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass, at most
+constexpr uint32_t kPackLoads = 8;         // sample loads in flight per lane in k_pack
 
 enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
 // Counters that many blocks add to are spread over kStatReplicas slots (one
@@ -800,26 +801,44 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
             if (P >= (uint64_t)kWave * kWave) {
                 // long rows (64 samples or more on average): the lanes of a
                 // wave walk one row at a time
+                // (kPackLoads loads in flight per lane before their ORs; a
+                // sample of ~0u lies past every chunk)
                 const uint32_t wv = tid / kWave;
                 for (uint32_t t = wv; t < kWave; t += kNT / kWave) {
                     const uint64_t rb = rbase[t], dg = rstart[t + 1] - rstart[t];
-                    for (uint64_t e = lane; e < dg; e += kWave) {
-                        const uint64_t s = S[rb + e];
-                        if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], 1ull << t);
+                    for (uint64_t e0 = lane; e0 < dg; e0 += (uint64_t)kWave * kPackLoads) {
+                        uint32_t v[kPackLoads];
+#pragma unroll
+                        for (uint32_t u = 0; u < kPackLoads; ++u) {
+                            const uint64_t e = e0 + (uint64_t)u * kWave;
+                            v[u] = e < dg ? S[rb + e] : ~0u;
+                        }
+#pragma unroll
+                        for (uint32_t u = 0; u < kPackLoads; ++u)
+                            if (v[u] >= c0 && v[u] < c0 + cn) atomicOr(&lw[v[u] - c0], 1ull << t);
                     }
                 }
             } else {
-                // short rows: one thread per entry, its row found by binary search
-                for (uint64_t p = tid; p < P; p += kNT) {
-                    // row t of the word: largest t with rstart[t] <= p
-                    uint32_t lo = 0, hi = kWave - 1;
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi + 1) >> 1;
-                        if (rstart[mid] <= p) lo = mid;
-                        else hi = mid - 1;
+                // short rows: one thread per entry, its row found by binary
+                // search; kPackLoads entries per thread in flight
+                for (uint64_t p0 = tid; p0 < P; p0 += (uint64_t)kNT * kPackLoads) {
+                    uint32_t v[kPackLoads], row[kPackLoads];
+#pragma unroll
+                    for (uint32_t u = 0; u < kPackLoads; ++u) {
+                        const uint64_t p = p0 + (uint64_t)u * kNT;
+                        // row of entry p: largest t with rstart[t] <= p
+                        uint32_t lo = 0, hi = kWave - 1;
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi + 1) >> 1;
+                            if (rstart[mid] <= p) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        row[u] = lo;
+                        v[u] = p < P ? S[rbase[lo] + (p - rstart[lo])] : ~0u;
                     }
-                    const uint64_t s = S[rbase[lo] + (p - rstart[lo])];
-                    if (s >= c0 && s < c0 + cn) atomicOr(&lw[s - c0], 1ull << lo);
+#pragma unroll
+                    for (uint32_t u = 0; u < kPackLoads; ++u)
+                        if (v[u] >= c0 && v[u] < c0 + cn) atomicOr(&lw[v[u] - c0], 1ull << row[u]);
                 }
             }
             __syncthreads();
@@ -1423,7 +1442,10 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         });
         check_launch("word rows");
         db->W.alloc(H * ldw, s, &db->budget, false, "packed words");
-        const uint32_t cols = (uint32_t)std::min<uint64_t>(ldw, kPackCols);
+        // column chunks of equal size (multiples of 128): fewer LDS bytes per
+        // block than a full kPackCols chunk when ldw is not a multiple of it
+        const uint64_t nchunk = div_up(ldw, (uint64_t)kPackCols);
+        const uint32_t cols = (uint32_t)(div_up(div_up(ldw, nchunk), 128) * 128);
         const uint32_t grid = (uint32_t)std::min<uint64_t>(H, 4096);
         {
             JAS_TIMED("pack", s);

@@ -374,28 +374,38 @@ constexpr uint64_t kFp4MaxK = (1u << 24) / 64 - 1;
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
+// The table is held in COPIES copies, entry x of copy c at word COPIES x + c.
+// With 32 copies lane l reads copy l % 32, so the lanes of one read fall in
+// distinct banks whatever bytes they look up (with one copy, data-dependent
+// indices collide in the banks on dense words, but the extra address
+// arithmetic costs more than it saves on sparse words and in the 256 x 256
+// kernel, so both forms are tile variants).
+template <uint32_t COPIES>
 __device__ __forceinline__ void fill_nibble_lut(uint32_t *lut) {
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) {
+    for (uint32_t e = threadIdx.x; e < 256 * COPIES; e += blockDim.x) {
+        const uint32_t i = e / COPIES;
         uint32_t d = 0;
         for (int b = 0; b < 8; ++b) d |= ((i >> b) & 1u) << (4 * b + 1);
-        lut[i] = d;
+        lut[e] = d;
     }
 }
 
-__device__ __forceinline__ v8i bits32_fp4(const uint32_t *lut, uint32_t x) {
+// lutc: the table copy of this lane (lut + lane % 32 with 32 copies, else lut)
+template <uint32_t COPIES>
+__device__ __forceinline__ v8i bits32_fp4(const uint32_t *lutc, uint32_t x) {
     v8i r = {0, 0, 0, 0, 0, 0, 0, 0};
-    r[0] = (int)lut[x & 255u];
-    r[1] = (int)lut[(x >> 8) & 255u];
-    r[2] = (int)lut[(x >> 16) & 255u];
-    r[3] = (int)lut[x >> 24];
+    r[0] = (int)lutc[(x & 255u) * COPIES];
+    r[1] = (int)lutc[((x >> 8) & 255u) * COPIES];
+    r[2] = (int)lutc[((x >> 16) & 255u) * COPIES];
+    r[3] = (int)lutc[(x >> 24) * COPIES];
     return r;
 }
 
-template <int WPE, int STEP>
+template <int WPE, int STEP, uint32_t COPIES>
 __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_gram_fp4(
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
-    __shared__ uint32_t lut[256];
+    __shared__ uint32_t lut[256 * COPIES];
     const uint64_t split = blockIdx.y;
     uint32_t p = blockIdx.x, I = 0, rowlen = nt;
     while (p >= rowlen) {
@@ -407,10 +417,11 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WP
     const uint64_t k0 = split * kper;
     const uint64_t k1 = min(H, k0 + kper);
     if (k0 >= k1) return;
-    fill_nibble_lut(lut);
+    fill_nibble_lut<COPIES>(lut);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63, wc = threadIdx.x >> 6;
     const uint32_t lm = lane & 31, lg = lane >> 5;
+    const uint32_t *lutc = lut + (COPIES > 1 ? lm : 0);
     const uint32_t I0 = I * kT, J0 = Jt * kT + 64 * wc;
     v16f acc[4][2];
 #pragma unroll
@@ -446,9 +457,9 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WP
             if (k + u >= k1) break;  // wave-uniform: the tail of the range
             v8i va[4], vb[2];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) va[x] = bits32_fp4(lut, (uint32_t)(a[u][x] >> sh));
+            for (int x = 0; x < 4; ++x) va[x] = bits32_fp4<COPIES>(lutc, (uint32_t)(a[u][x] >> sh));
 #pragma unroll
-            for (int y = 0; y < 2; ++y) vb[y] = bits32_fp4(lut, (uint32_t)(b[u][y] >> sh));
+            for (int y = 0; y < 2; ++y) vb[y] = bits32_fp4<COPIES>(lutc, (uint32_t)(b[u][y] >> sh));
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -496,7 +507,7 @@ __global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
     const uint64_t k0 = split * kper;
     const uint64_t k1 = min(H, k0 + kper);
     if (k0 >= k1) return;
-    fill_nibble_lut(lut);
+    fill_nibble_lut<1>(lut);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t lm = lane & 31, lg = lane >> 5;
@@ -542,9 +553,9 @@ __global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
             if (k + u >= k1) break;  // wave-uniform: the tail of the range
             v8i va[4], vb[4];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) va[x] = bits32_fp4(lut, (uint32_t)(a[u][x] >> sh));
+            for (int x = 0; x < 4; ++x) va[x] = bits32_fp4<1>(lut, (uint32_t)(a[u][x] >> sh));
 #pragma unroll
-            for (int y = 0; y < 4; ++y) vb[y] = bits32_fp4(lut, (uint32_t)(b[u][y] >> sh));
+            for (int y = 0; y < 4; ++y) vb[y] = bits32_fp4<1>(lut, (uint32_t)(b[u][y] >> sh));
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -692,6 +703,12 @@ __global__ __launch_bounds__(256) void k_pair_count(const uint32_t *__restrict__
 }
 
 // Diagonal, mirror (full layout), unions and J.
+// dst[i] += src[i], i < n (the sample sizes of one row batch into the running sums).
+__global__ void k_add_i64(int64_t *__restrict__ dst, const int64_t *__restrict__ src, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] += src[i];
+}
+
 __global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ card, uint32_t n, int upper,
                            uint32_t jblocks, int64_t *__restrict__ den, double *__restrict__ J) {
     const uint32_t i = blockIdx.x / jblocks;
@@ -720,12 +737,12 @@ __global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ 
 // Tile variants of the MFMA Gram: word rows per step of the K loop, and how
 // many blocks the K split aims for.  The autotuner (JAS_TUNE) times each on the
 // caller's db and keeps the fastest for dbs of the same shape.
-enum GramKind { kInt8 = 0, kInt8Wide = 1, kFp4 = 2, kFp4Wide = 3 };
+enum GramKind { kInt8 = 0, kInt8Wide = 1, kFp4 = 2, kFp4Wide = 3, kFp4Rep = 4 };
 struct GramVariant {
     int step;
     uint64_t want_blocks;
     int kind;  // kInt8: k_gram_mfma; kInt8Wide: 256 x 256 tiles (k_gram_mfma_wide); kFp4: k_gram_fp4;
-               // kFp4Wide: k_gram_fp4_wide
+               // kFp4Wide: k_gram_fp4_wide; kFp4Rep: k_gram_fp4 with 32 copies of the nibble table
 };
 // (wide variants with 2 word rows per step or at most 2048 blocks measured
 // slower on both dense workloads and are not listed)
@@ -735,7 +752,8 @@ constexpr GramVariant kVariants[] = {{4, 2048, kInt8},     {4, 4096, kInt8},    
                                      {4, 4096, kInt8Wide}, {4, 8192, kInt8Wide}, {4, 2048, kFp4},
                                      {2, 2048, kFp4},      {4, 4096, kFp4},      {2, 4096, kFp4},
                                      {4, 8192, kFp4},      {2, 8192, kFp4},      {4, 4096, kFp4Wide},
-                                     {4, 8192, kFp4Wide},  {4, 16384, kFp4Wide}};
+                                     {4, 8192, kFp4Wide},  {4, 16384, kFp4Wide}, {4, 4096, kFp4Rep},
+                                     {4, 8192, kFp4Rep},   {2, 8192, kFp4Rep}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 // Untuned choice, from the tuner's timings on MI355X: 128 x 128 fp4 tiles
 // below n = 2048 (n = 1024: 6.5 ms against 10.6 for int8 tiles), 256 x 256 fp4
@@ -787,17 +805,22 @@ void launch_mfma(const jas_db *db, int v, hipStream_t s, int32_t *B, bool upper)
     uint64_t kper, splits;
     k_split(db->H, np, kVariants[v].want_blocks, kper, splits);
     const uint64_t ldw = div_up(n, 128) * 128;
-    if (kVariants[v].kind == kFp4) {
+    if (kVariants[v].kind == kFp4 || kVariants[v].kind == kFp4Rep) {
+        const bool rep = kVariants[v].kind == kFp4Rep;
         if (kper > kFp4MaxK) {  // keep every block's float sums below 2^24
             kper = kFp4MaxK / kKC * kKC;
             splits = div_up(db->H, kper);
         }
         if (splits <= 65535) {
             dim3 grid((uint32_t)np, (uint32_t)splits);
-            if (kVariants[v].step == 4)
-                k_gram_fp4<2, 4><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            if (kVariants[v].step == 4 && rep)
+                k_gram_fp4<2, 4, 32><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            else if (kVariants[v].step == 4)
+                k_gram_fp4<2, 4, 1><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+            else if (rep)
+                k_gram_fp4<2, 2, 32><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
             else
-                k_gram_fp4<2, 2><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
+                k_gram_fp4<2, 2, 1><<<grid, kMfmaNT, 0, s>>>(db->W.p, ldw, db->H, kper, nt, n, B, upper);
             return;
         }
         k_split(db->H, np, kVariants[v].want_blocks, kper, splits);  // too many blocks: the int8 kernel
@@ -813,12 +836,25 @@ void launch_mfma(const jas_db *db, int v, hipStream_t s, int32_t *B, bool upper)
 
 int32_t gram_variants() { return kNumVariants; }
 
+void finalize(uint32_t n, bool upper, hipStream_t s, int32_t *B, const int64_t *card, int64_t *den, double *J) {
+    if (n == 0) return;
+    const uint32_t jb = (uint32_t)div_up(n, 256);
+    const uint64_t fb = (uint64_t)n * jb;
+    if (fb > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "n too large for finalize grid");
+    {
+        JAS_TIMED("finalize", s);
+        k_finalize<<<(uint32_t)fb, 256, 0, s>>>(B, card, n, upper, jb, den, J);
+    }
+    check_launch("finalize");
+}
+
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J) {
     const uint32_t n = (uint32_t)db->n;
     const bool upper = flags & JAS_UPPER;
+    const bool accumulate = flags & JAS_ACCUMULATE;
     const uint64_t len = upper ? (uint64_t)n * (n + 1) / 2 : (uint64_t)n * n;
     if (n == 0) return;
-    {
+    if (!accumulate) {
         JAS_TIMED("fill_i32", s);
         k_fill_i32<<<(uint32_t)std::min<uint64_t>(div_up(len, 256), 65536), 256, 0, s>>>(B, len, 0);
     }
@@ -872,7 +908,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
                 const auto it = g_tuned.find(key);
                 if (it != g_tuned.end()) v = it->second;
             }
-            JAS_TIMED(kVariants[v].kind >= kFp4 ? "gram_fp4" : "gram_mfma", s);
+            JAS_TIMED(kVariants[v].kind >= kFp4 ? "gram_fp4" : "gram_mfma", s);  // kFp4, kFp4Wide, kFp4Rep
             launch_mfma(db, v, s, B, upper);
         }
         check_launch("gram");
@@ -895,14 +931,15 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         }
         check_launch("row list pairs");
     }
-    const uint32_t jb = (uint32_t)div_up(n, 256);
-    const uint64_t fb = (uint64_t)n * jb;
-    if (fb > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "n too large for finalize grid");
-    {
-        JAS_TIMED("finalize", s);
-        k_finalize<<<(uint32_t)fb, 256, 0, s>>>(B, db->card.p, n, upper, jb, den, J);
+    if (accumulate) {
+        {
+            JAS_TIMED("add_card", s);
+            k_add_i64<<<(uint32_t)div_up(n, 256), 256, 0, s>>>(card, db->card.p, n);
+        }
+        check_launch("add card");
+        return;
     }
-    check_launch("finalize");
+    finalize(n, upper, s, B, db->card.p, den, J);
     if (card) JAS_HIP(hipMemcpyAsync(card, db->card.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
 }
 

@@ -220,6 +220,7 @@ uint32_t choose_dense_min_degree(const std::vector<uint64_t> &deg_hist, uint32_t
 
 // Gram and finalize (see gram.hip).
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J);
+void finalize(uint32_t n, bool upper, hipStream_t s, int32_t *B, const int64_t *card, int64_t *den, double *J);
 int32_t gram_variants();
 
 // Query (see query.hip).

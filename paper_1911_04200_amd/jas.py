@@ -23,6 +23,7 @@ JAS_UPPER = 0x10
 JAS_FORCE_POPCOUNT = 0x20
 JAS_FORCE_MFMA = 0x40
 JAS_TUNE = 0x80
+JAS_ACCUMULATE = 0x100
 
 
 def JAS_GRAM_VARIANT(v: int) -> int:
@@ -33,7 +34,7 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
                 -6: "JAS_EUNSUPPORTED"}
 
 # Every symbol include/jas.h declares.
-EXPORTS = sorted(["jas_encode", "jas_gram", "jas_gram_variants", "jas_query", "jas_query_workspace_bytes",
+EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_gram_variants", "jas_query", "jas_query_workspace_bytes",
                   "jas_db_size", "jas_db_stats", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
                   "jas_timing_report", "jas_trim"])
 
@@ -83,6 +84,8 @@ def load(path: str = LIB_PATH):
                                ctypes.POINTER(jas_encode_stats)]
     lib.jas_encode.restype = ctypes.c_int
     lib.jas_gram.argtypes = [vp, u32, vp, vp, vp, vp, vp]
+    lib.jas_finalize.restype = i32
+    lib.jas_finalize.argtypes = [i32, u32, vp, vp, vp, vp, vp]
     lib.jas_gram.restype = ctypes.c_int
     lib.jas_query.argtypes = [vp, vp, vp, i32, u32, vp, vp, vp, vp, vp]
     lib.jas_query.restype = ctypes.c_int
@@ -175,6 +178,10 @@ def jas_gram(db, flags: int, stream, B, card=None, den=None, J=None):
     lib = load()
     s = None if (flags & JAS_HOST_PTRS and stream is None) else _stream(stream)
     _check(lib.jas_gram(_h(db), flags, s, _ptr(B), _ptr(card), _ptr(den), _ptr(J)))
+
+
+def jas_finalize(n: int, flags: int, stream, B, card, den=None, J=None):
+    _check(load().jas_finalize(n, flags, _stream(stream), _ptr(B), _ptr(card), _ptr(den), _ptr(J)))
 
 
 def jas_query(db, q_ids, q_offsets, nq: int, flags: int, stream, B, q_card=None, den=None, J=None):

@@ -71,6 +71,9 @@ def _load():
         lib.synth_fill.argtypes = [P(_Spec), ctypes.c_int32, ctypes.c_int32, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         lib.synth_fill_list.argtypes = [P(_Spec), ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_uint64),
                                         P(ctypes.c_uint64)]
+        lib.synth_rmat.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+        lib.synth_rmat.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -120,9 +123,11 @@ def _u64p(a: np.ndarray):
 _offsets_cache: dict = {}
 
 
-def offsets(spec: Spec) -> np.ndarray:
+def offsets(spec) -> np.ndarray:
     """CSR offsets (uint64[n+1]).  A Bernoulli set's size is known only by
     drawing it, so those offsets are kept for the last few specs asked for."""
+    if isinstance(spec, Graph):
+        return spec.off.copy()
     if spec.size_kind == 2 and spec in _offsets_cache:
         return _offsets_cache[spec].copy()
     lib = _load()
@@ -145,8 +150,13 @@ def plan(spec: Spec, i: int):
     return int(out[0]), int(out[1]), int(out[2]), int(out[3].astype(np.int64))
 
 
-def generate(spec: Spec, out: Optional[np.ndarray] = None):
+def generate(spec, out: Optional[np.ndarray] = None):
     """Whole collection: (ids uint64[N], offsets uint64[n+1])."""
+    if isinstance(spec, Graph):
+        if out is None:
+            return spec.ids.copy(), spec.off.copy()
+        out[:spec.ids.size] = spec.ids
+        return out[:spec.ids.size], spec.off.copy()
     lib = _load()
     off = offsets(spec)
     total = int(off[-1])
@@ -159,8 +169,14 @@ def generate(spec: Spec, out: Optional[np.ndarray] = None):
     return ids[:total], off
 
 
-def generate_samples(spec: Spec, idx: Sequence[int]):
+def generate_samples(spec, idx: Sequence[int]):
     """Only the listed samples, packed in list order: (ids, offsets[len(idx)+1])."""
+    if isinstance(spec, Graph):
+        idx = np.asarray(idx, dtype=np.int64)
+        parts = [spec.ids[int(spec.off[i]):int(spec.off[i + 1])] for i in idx]
+        off = np.zeros(idx.size + 1, dtype=np.uint64)
+        np.cumsum([x.size for x in parts], out=off[1:])
+        return (np.concatenate(parts) if parts else np.zeros(0, np.uint64)), off
     lib = _load()
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
     full = offsets(spec)
@@ -174,6 +190,40 @@ def generate_samples(spec: Spec, idx: Sequence[int]):
     if rc != 0:
         raise RuntimeError("synth_fill_list failed")
     return ids, off
+
+
+def rmat_graph(scale: int, edge_factor: int, seed: int = 0, a: float = 0.57, b: float = 0.19, c: float = 0.19):
+    """Neighbourhoods N(v), v < 2^scale, of an undirected R-MAT graph (power-law
+    degrees; Graph500's quadrant probabilities by default): (ids, offsets), each
+    set ascending without repeats, IDs < 2^scale."""
+    lib = _load()
+    nv = 1 << scale
+    off = np.empty(nv + 1, dtype=np.uint64)
+    ids = np.empty(2 * edge_factor * nv, dtype=np.uint64)
+    total = lib.synth_rmat(scale, edge_factor, (_SEED_BASE + 7 + seed) & 0xFFFFFFFFFFFFFFFF, a, b, c,
+                           _u64p(off), _u64p(ids))
+    if total < 0:
+        raise ValueError("bad R-MAT parameters")
+    return ids[:total].copy(), off
+
+
+class Graph:
+    """Neighbourhoods of a generated graph as a set collection (n = 2^scale
+    sets, IDs < 2^scale); offsets / generate / generate_samples accept it."""
+
+    def __init__(self, scale: int, edge_factor: int, seed: int = 0):
+        self.scale, self.edge_factor, self.seed = scale, edge_factor, seed
+        self.ids, self.off = rmat_graph(scale, edge_factor, seed)
+        self.n = 1 << scale
+        self.universe_bits = scale
+        self.size_kind = -1
+
+
+# Vertex similarity workloads: (scale, edge factor).  All pairs of the 8192
+# vertices of a scale-13 graph (within the row-list path's sample limit); a
+# scale-20 graph as a query database (link prediction: new vertices' sets
+# against every neighbourhood).
+GRAPHS = {"graph_s13_ef64": (13, 64), "graph_s20_ef16": (20, 16)}
 
 
 # ---------------------------------------------------------------------------
@@ -206,8 +256,11 @@ BERNOULLI = {"bernoulli_p1e-4": (1e-4, 25), "bernoulli_p1e-3": (1e-3, 25), "bern
              "bernoulli_p1e-1": (1e-1, 22)}
 
 
-def workload(name: str) -> Spec:
-    """The five configurations (full size), and the Bernoulli density sweep."""
+def workload(name: str):
+    """The five configurations (full size), the Bernoulli density sweep and the
+    vertex-similarity graphs (a Graph)."""
+    if name in GRAPHS:
+        return Graph(*GRAPHS[name])
     if name in BERNOULLI:
         p, rl = BERNOULLI[name]
         return bernoulli(p, rl)
@@ -253,6 +306,7 @@ def query_spec(db: Spec, request: int, nq: int) -> Spec:
 # Batch rows (the paper's m~) used with each workload, as log2.
 BATCH_BITS = {"tiny": 24, "paperlike": 26, "precision": 32, "batching": 26, "serving_db": 26}
 BATCH_BITS.update({name: rl for name, (p, rl) in BERNOULLI.items()})  # one batch of all rows
+BATCH_BITS.update({name: sc for name, (sc, ef) in GRAPHS.items()})
 
 
 def scaled(spec: Spec, n: Optional[int] = None, size_scale: float = 1.0, pool_scale: float = 1.0,

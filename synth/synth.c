@@ -259,3 +259,100 @@ int synth_fill_list(const synth_spec *sp, int32_t count, const int32_t *idx, con
     for (int32_t k = 0; k < count; ++k) fill_one(sp, idx[k], ids + dst_offsets[k]);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Power-law graphs for vertex similarity (the neighbourhood Jaccard of paper
+ * Sec. II-F, with the adjacency matrix as A, Sec. III-A).  R-MAT (Chakrabarti,
+ * Zhan, Faloutsos, "R-MAT: A Recursive Model for Graph Mining", SDM 2004):
+ * each of edge_factor * 2^scale draws picks one of the four quadrants of the
+ * adjacency matrix with probabilities (a, b, c, 1 - a - b - c) at each of the
+ * `scale` levels.  Vertex labels are scrambled by a keyed bijection so that
+ * the heavy vertices are spread over the ID range.  The graph is undirected:
+ * a draw (u, v) with u != v puts v in N(u) and u in N(v).  Output: the
+ * neighbourhoods N(0) .. N(2^scale - 1) in CSR, each ascending, repeats
+ * removed.  ids must hold 2 * edge_factor * 2^scale entries; returns the
+ * number written, or -1 for bad arguments.
+ */
+static int cmp_u64(const void *x, const void *y)
+{
+    const uint64_t a = *(const uint64_t *)x, b = *(const uint64_t *)y;
+    return a < b ? -1 : a > b;
+}
+
+static void rmat_edge(uint64_t key, uint64_t e, uint32_t scale, double a, double b, double c, uint64_t *u,
+                      uint64_t *v)
+{
+    uint64_t r = 0, s = 0;
+    for (uint32_t l = 0; l < scale; ++l) {
+        const double x = u01(sm_at(key, e * scale + l));
+        const uint64_t bit = 1ULL << (scale - 1 - l);
+        if (x < a) {
+        } else if (x < a + b) {
+            s |= bit;
+        } else if (x < a + b + c) {
+            r |= bit;
+        } else {
+            r |= bit;
+            s |= bit;
+        }
+    }
+    *u = r;
+    *v = s;
+}
+
+int64_t synth_rmat(uint32_t scale, uint64_t edge_factor, uint64_t seed, double a, double b, double c,
+                   uint64_t *offsets, uint64_t *ids)
+{
+    if (scale < 1 || scale > 30 || !(a >= 0 && b >= 0 && c >= 0 && a + b + c <= 1.0)) return -1;
+    const uint64_t nv = 1ULL << scale, E = edge_factor * nv;
+    const uint64_t key = stream_key(seed, TAG_PARAM, 0xE);
+    const uint64_t k0 = stream_key(seed, TAG_IDPERM, 0xE0), k1 = stream_key(seed, TAG_IDPERM, 0xE1);
+    uint64_t *cnt = (uint64_t *)calloc(nv + 1, sizeof(uint64_t));
+    if (!cnt) return -1;
+#pragma omp parallel for schedule(static)
+    for (uint64_t e = 0; e < E; ++e) {
+        uint64_t u, v;
+        rmat_edge(key, e, scale, a, b, c, &u, &v);
+        if (u == v) continue;
+        u = perm_bits(u, scale, k0, k1);
+        v = perm_bits(v, scale, k0, k1);
+        __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
+        __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
+    }
+    /* raw CSR (with repeats) in offsets, cursors in cnt */
+    offsets[0] = 0;
+    for (uint64_t i = 0; i < nv; ++i) offsets[i + 1] = offsets[i] + cnt[i];
+    for (uint64_t i = 0; i < nv; ++i) cnt[i] = offsets[i];
+#pragma omp parallel for schedule(static)
+    for (uint64_t e = 0; e < E; ++e) {
+        uint64_t u, v;
+        rmat_edge(key, e, scale, a, b, c, &u, &v);
+        if (u == v) continue;
+        u = perm_bits(u, scale, k0, k1);
+        v = perm_bits(v, scale, k0, k1);
+        ids[__atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED)] = v;
+        ids[__atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED)] = u;
+    }
+    /* sort each neighbourhood (the fill order above is not deterministic),
+     * drop repeats, and close the gaps */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (uint64_t i = 0; i < nv; ++i) {
+        uint64_t *x = ids + offsets[i];
+        const uint64_t len = offsets[i + 1] - offsets[i];
+        qsort(x, len, sizeof(uint64_t), cmp_u64);
+        uint64_t w = 0;
+        for (uint64_t t = 0; t < len; ++t)
+            if (w == 0 || x[t] != x[w - 1]) x[w++] = x[t];
+        cnt[i] = w;
+    }
+    uint64_t pos = 0;
+    for (uint64_t i = 0; i < nv; ++i) {
+        const uint64_t src = offsets[i], len = cnt[i];
+        memmove(ids + pos, ids + src, len * sizeof(uint64_t));
+        offsets[i] = pos;
+        pos += len;
+    }
+    offsets[nv] = pos;
+    free(cnt);
+    return (int64_t)pos;
+}

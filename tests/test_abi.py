@@ -102,3 +102,12 @@ def test_error_message_is_thread_local_and_reset():
     # a call that fails differently replaces the message
     assert lib.jas_db_stats(None, ctypes.byref(st)) == jas.JAS_EINVAL
     assert "jas_db_stats" in jas.jas_last_error()
+
+
+def test_finalize_argument_checks():
+    lib = jas.load()
+    assert lib.jas_finalize(-1, 0, None, None, None, None, None) == jas.JAS_EINVAL
+    assert lib.jas_finalize(4, jas.JAS_TUNE, None, None, None, None, None) == jas.JAS_EINVAL
+    assert "JAS_UPPER" in jas.jas_last_error()
+    assert lib.jas_finalize(4, 0, None, None, None, None, None) == jas.JAS_EINVAL
+    assert lib.jas_finalize(0, 0, None, None, None, None, None) == jas.JAS_OK

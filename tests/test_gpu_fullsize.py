@@ -98,7 +98,8 @@ def check_bernoulli_means(res, spec, upper):
 
 
 @pytest.mark.parametrize("name,upper", [("paperlike", False), ("precision", False), ("batching", True),
-                                        ("bernoulli_p1e-3", True), ("bernoulli_p1e-2", True)])
+                                        ("bernoulli_p1e-3", True), ("bernoulli_p1e-2", True),
+                                        ("graph_s13_ef64", False)])
 def test_full_size_all_pairs(name, upper):
     spec = synth.workload(name)
     n = spec.n
@@ -165,4 +166,68 @@ def test_full_size_serving_queries():
     assert np.array_equal(J[:, cols].view(np.uint64), ref["J"].view(np.uint64))
     # any size: bounds and the union identity over every column
     assert np.all(B >= 0) and np.all(B <= qc[:, None])
+    assert np.all((J >= 0) & (J <= 1))
+
+
+def test_full_size_streamed_bernoulli():
+    """The p = 1e-2 matrix (3.36e9 IDs) streamed from host memory in 8 parts of
+    2^22 rows: sampled pairs against the oracle, properties and model means."""
+    from paper_1911_04200_amd import stream
+    spec = synth.workload("bernoulli_p1e-2")
+    n = spec.n
+    ids, off = synth.generate(spec)
+    res = stream.all_pairs_streamed(ids, off, spec.universe_bits, 3, upper=True, check_sorted=False)
+    torch.cuda.synchronize()
+    out = {k: res[k].cpu().numpy() for k in ("B", "card", "den", "J")}
+    assert res["n_parts"] == 8 and sum(s["n_ids"] for s in res["parts"]) == ids.size
+    # each part's device footprint is about an eighth of the resident encoding's
+    assert max(s["device_bytes"] for s in res["parts"]) < 40 << 30
+    del res, ids
+    sizes = np.diff(off.astype(np.int64))
+    pts, pairs = sample_pairs(n, sizes, np.random.default_rng(3))
+    check_sampled(spec, out, pts, pairs, True)
+    check_properties(out, n, True)
+    check_bernoulli_means(out, spec, True)
+
+
+def test_full_size_graph_link_prediction():
+    """Neighbourhoods of the 2^20 vertices of a scale-20 R-MAT graph as the
+    database; queries are some vertices' neighbourhoods, with and without an
+    added edge: every column's bounds, sampled columns against the oracle."""
+    g = synth.workload("graph_s20_ef16")
+    n = g.n
+    ids_d, off_d, off = resident(g)
+    opts = cabi.jas_encode_opts(g.universe_bits, synth.BATCH_BITS["graph_s20_ef16"], 0, cabi.JAS_KEEP_IDS, 0)
+    db, st = cabi.jas_encode(ids_d, off_d, n, opts, None)
+    del ids_d
+    rng = np.random.default_rng(9)
+    deg = np.diff(off.astype(np.int64))
+    verts = [int(np.argmax(deg))] + [int(v) for v in rng.choice(np.flatnonzero(deg > 0), 14, replace=False)]
+    qs = [g.ids[int(off[v]):int(off[v + 1])] for v in verts]
+    qs.append(np.union1d(qs[1], rng.choice(n, 3, replace=False).astype(np.uint64)))
+    qo = np.zeros(len(qs) + 1, np.uint64)
+    qo[1:] = np.cumsum([q.size for q in qs])
+    qi = np.concatenate(qs).astype(np.uint64)
+    nq = len(qs)
+    B = torch.empty((nq, n), dtype=torch.int32, device="cuda")
+    qc = torch.empty(nq, dtype=torch.int64, device="cuda")
+    den = torch.empty((nq, n), dtype=torch.int64, device="cuda")
+    J = torch.empty((nq, n), dtype=torch.float64, device="cuda")
+    cabi.jas_query(db, torch.from_numpy(qi.view(np.int64)).cuda(), torch.from_numpy(qo.view(np.int64)).cuda(), nq,
+                   0, None, B, qc, den, J)
+    torch.cuda.synchronize()
+    B, qc, den, J = B.cpu().numpy(), qc.cpu().numpy(), den.cpu().numpy(), J.cpu().numpy()
+    db.close()
+    cabi.jas_trim()
+    cols = np.unique(np.concatenate([np.array(verts), rng.choice(n, 40, replace=False)]))
+    xs, xo = synth.generate_samples(g, cols)
+    ref = oracle.cross(qi, qo, xs, xo)
+    assert np.array_equal(qc, ref["q_card"])
+    assert np.array_equal(B[:, cols], ref["inter"])
+    assert np.array_equal(den[:, cols], ref["union"])
+    assert np.array_equal(J[:, cols].view(np.uint64), ref["J"].view(np.uint64))
+    # a vertex's own neighbourhood: J = 1 with its own column
+    for k, v in enumerate(verts):
+        assert J[k, v] == 1.0
+    assert np.all(B >= 0) and np.all(B <= qc[:, None]) and np.all(B <= deg[None, :])
     assert np.all((J >= 0) & (J <= 1))

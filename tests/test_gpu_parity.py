@@ -115,6 +115,36 @@ def test_bernoulli_matrices(p, rows_log2, n, batches, path):
         assert st["n_packed_rows"] == 1 << rows_log2
 
 
+# Vertex similarity (Sec. II-F): the sets are the neighbourhoods of an R-MAT
+# graph (hubs of degree ~ n/5 next to isolated vertices), A its adjacency.
+@pytest.mark.parametrize("dmin", [0, 2, 1 << 20])
+def test_graph_neighbourhood_similarity(dmin):
+    ids, off = synth.rmat_graph(10, 16, seed=2)
+    ref = oracle.all_pairs(ids, off)
+    res, st = gpu_all_pairs(ids, off, 10, 10, dmin)
+    assert_matches(res, ref)
+
+
+def test_graph_link_prediction_queries():
+    ids, off = synth.rmat_graph(12, 8, seed=3)
+    n = off.size - 1
+    db, _ = jas.encode(dev(ids), dev(off), universe_bits=12, batch_bits=12, keep_ids=True)
+    # queries: neighbourhoods of some vertices, one with an edge added, and an empty set
+    qs = [ids[int(off[v]):int(off[v + 1])] for v in (0, 17, 4095)]
+    qs.append(np.union1d(qs[1], np.array([5], np.uint64)))
+    qs.append(np.zeros(0, np.uint64))
+    qo = np.zeros(len(qs) + 1, np.uint64)
+    qo[1:] = np.cumsum([q.size for q in qs])
+    qi = np.concatenate(qs).astype(np.uint64)
+    out = jas.query(db, dev(qi), dev(qo))
+    torch.cuda.synchronize()
+    ref = oracle.cross(qi, qo, ids, off)
+    assert np.array_equal(out["B"].cpu().numpy(), ref["inter"])
+    assert np.array_equal(out["den"].cpu().numpy(), ref["union"])
+    assert np.array_equal(out["J"].cpu().numpy().view(np.uint64), ref["J"].view(np.uint64))
+    db.close()
+
+
 def test_duplicates_and_empty_sets():
     spec = synth.scaled(synth.workload("tiny"), n=40, dup_rate=0.3)
     ids, off = synth.generate(spec)

@@ -100,3 +100,28 @@ def test_bernoulli_sweep_sizes():
         s = synth.workload(name)
         assert s.n == 10000 and s.rows == 1 << rl and s.universe_bits == rl and synth.BATCH_BITS[name] == rl
         assert s.density == p
+
+
+def test_rmat_neighbourhoods_form_an_undirected_simple_graph():
+    ids, off = synth.rmat_graph(10, 16, seed=1)
+    n = 1 << 10
+    assert off.size == n + 1 and ids.max() < n
+    edges = set()
+    for v in range(n):
+        nb = ids[int(off[v]):int(off[v + 1])].astype(np.int64)
+        assert np.all(np.diff(nb) > 0) and v not in nb  # ascending, no repeats, no self loop
+        edges.update((v, int(u)) for u in nb)
+    assert all((u, v) in edges for v, u in edges)  # u in N(v) <=> v in N(u)
+    deg = np.diff(off.astype(np.int64))
+    assert deg.max() > 10 * deg.mean() and (deg == 0).any()  # R-MAT's skew: hubs and isolated vertices
+    a, ao = synth.rmat_graph(10, 16, seed=1)
+    assert np.array_equal(a, ids) and np.array_equal(ao, off)
+
+
+def test_graph_collections_behave_like_specs():
+    g = synth.workload("graph_s13_ef64")
+    assert g.n == 8192 and g.universe_bits == 13 and synth.BATCH_BITS["graph_s13_ef64"] == 13
+    ids, off = synth.generate(g)
+    c, co = synth.generate_samples(g, [9, 2])
+    assert np.array_equal(c[:int(co[1])], ids[int(off[9]):int(off[10])])
+    assert np.array_equal(synth.offsets(g), off)
