@@ -55,6 +55,7 @@ typedef enum {
 #define JAS_FORCE_MFMA 0x40u    /* jas_gram: every packed tile on an MFMA kernel (int8, or fp4 with exact float sums) */
 #define JAS_TUNE 0x80u          /* jas_gram: time the MFMA tile variants on this db first (see jas_gram) */
 #define JAS_ACCUMULATE 0x100u   /* jas_gram: add this db's counts into B and card (one row batch of many) */
+#define JAS_CANONICAL 0x200u    /* jas_kmers: each k-mer as the smaller of itself and its reverse complement */
 /* jas_gram: run MFMA tile variant v, 0 <= v < jas_gram_variants() (bits 16..23 hold v + 1) */
 #define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)
 
@@ -160,6 +161,38 @@ jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t 
  */
 jas_status jas_finalize(int32_t n, uint32_t flags, void *hip_stream, int32_t *B, const int64_t *card, int64_t *den,
                         double *J);
+
+/*
+ * jas_kmer_offsets / jas_kmers -- the k-mer sets of n samples from their
+ * sequences: the step before jas_encode.  A k-mer is a length-k substring of
+ * a sequence (Sec. II-B); sample i's set is the k-mers of its sequences.
+ * The ID of a k-mer is its bases read as a base-4 number, first base most
+ * significant (A = 0, C = 1, G = 2, T = 3), so IDs are below 2^(2k) and
+ * jas_encode takes universe_bits = 2k.  JAS_CANONICAL replaces each by the
+ * smaller of it and its reverse complement (strand-independent k-mers; an
+ * odd k has no palindromes, Sec. V-A2).  Repeated k-mers are left in; the
+ * encoding removes them.
+ *
+ *  seq_off  uint64[n_seq+1], host: sequence s is bases seq_off[s] ..
+ *           seq_off[s+1]-1 of the packed base array (0 first, non-decreasing).
+ *  smp_off  uint64[n+1], host: sample i owns sequences smp_off[i] ..
+ *           smp_off[i+1]-1 (0 first, non-decreasing, smp_off[n] = n_seq).
+ *  k        1..31.
+ *  ids_off  uint64[n+1], host output of jas_kmer_offsets: sample i's k-mers
+ *           are ids[ids_off[i] .. ids_off[i+1]) (a sequence of length L
+ *           holds L - k + 1 of them, none if L < k); ids_off[n] is the size
+ *           of ids.  Host arithmetic only, no device call.
+ *  seq      uint64 words, device: every base in 2 bits, base b at bits
+ *           2 (b mod 32) of word b / 32; ceil(seq_off[n_seq] / 32) words.
+ *  ids      uint64[ids_off[n]], device output of jas_kmers, in sequence and
+ *           position order.
+ * jas_kmers runs on hip_stream and returns after its work is done (it reads
+ * seq_off from the host).  EINVAL for bad offsets, k or flags.
+ */
+jas_status jas_kmer_offsets(const uint64_t *seq_off, int64_t n_seq, const uint64_t *smp_off, int32_t n, uint32_t k,
+                            uint64_t *ids_off);
+jas_status jas_kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t k, uint32_t flags,
+                     void *hip_stream, uint64_t *ids);
 
 /* Number of MFMA tile variants jas_gram can run (tile shape, word rows per
  * step, K split); variant indices are stable within one build of the library. */

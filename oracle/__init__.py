@@ -3,9 +3,10 @@
 A plain C implementation (``oracle.c``) of the definitions in Sec. II-A of the
 paper: sets are normalised (sorted, repeats dropped), intersections and unions
 are counted by walking two sorted lists, and J = |X cap Y| / |X cup Y| in
-binary64 with J(empty, empty) = 1.  It shares no code with the GPU library and
-is loaded only by the tests, the smoke check and the benchmark's CPU-baseline
-leg.
+binary64 with J(empty, empty) = 1.  ``kmers`` writes out the k-mer
+definition of Sec. II-B in numpy (base-4 digits, reverse complement).  It
+shares no code with the GPU library and is loaded only by the tests, the smoke
+check and the benchmark's CPU-baseline leg.
 """
 from __future__ import annotations
 
@@ -151,3 +152,31 @@ def pairs_normalized(qs, qo, xs, xo, qi, xi, lib=None):
     if rc != 0:
         raise ValueError("oracle_pairs: index out of range")
     return inter, uni, jac
+
+
+# ---------------------------------------------------------------------------
+# k-mers (Sec. II-B: the length-k substrings of a sequence).  A k-mer's ID is
+# its bases (A = 0, C = 1, G = 2, T = 3) read as a base-4 number, first base
+# most significant; canonical: the smaller of it and its reverse complement
+# (the complement of each base, 3 - x, in reverse order).
+def kmers(seq, k: int, canonical: bool = False) -> np.ndarray:
+    """IDs of the k-mers of one sequence (uint8 base codes), in position order."""
+    x = np.asarray(seq, dtype=np.uint64)
+    npos = x.size - k + 1
+    if npos <= 0:
+        return np.zeros(0, dtype=np.uint64)
+    fwd = np.zeros(npos, dtype=np.uint64)
+    rev = np.zeros(npos, dtype=np.uint64)
+    for j in range(k):  # digit j of the k-mer at position i is base i + j
+        fwd = fwd * np.uint64(4) + x[j:j + npos]
+        rev = rev * np.uint64(4) + (np.uint64(3) - x[k - 1 - j:k - 1 - j + npos])
+    return np.minimum(fwd, rev) if canonical else fwd
+
+
+def kmer_sets(samples, k: int, canonical: bool = False):
+    """CSR (ids, offsets) of every sample's k-mers (sample = list of sequences)."""
+    per = [np.concatenate([kmers(s, k, canonical) for s in seqs]) if seqs else np.zeros(0, np.uint64)
+           for seqs in samples]
+    off = np.zeros(len(per) + 1, dtype=np.uint64)
+    np.cumsum([p.size for p in per], out=off[1:])
+    return (np.concatenate(per) if per else np.zeros(0, np.uint64)), off

@@ -276,6 +276,46 @@ jas_status jas_finalize(int32_t n, uint32_t flags, void *hip_stream, int32_t *B,
     });
 }
 
+namespace {
+void check_seq_off(const uint64_t *seq_off, int64_t n_seq, uint32_t k, const char *what) {
+    if (n_seq < 0) fail(JAS_EINVAL, std::string(what) + ": n_seq < 0");
+    if (!seq_off) fail(JAS_EINVAL, std::string(what) + ": seq_off is NULL");
+    if (k < 1 || k > 31) fail(JAS_EINVAL, std::string(what) + ": k must be 1..31");
+    if (seq_off[0] != 0) fail(JAS_EINVAL, std::string(what) + ": seq_off[0] must be 0");
+    for (int64_t s = 0; s < n_seq; ++s)
+        if (seq_off[s + 1] < seq_off[s])
+            fail(JAS_EINVAL, std::string(what) + ": seq_off decreases at sequence " + std::to_string(s));
+}
+}  // namespace
+
+jas_status jas_kmer_offsets(const uint64_t *seq_off, int64_t n_seq, const uint64_t *smp_off, int32_t n, uint32_t k,
+                            uint64_t *ids_off) {
+    return guard([&] {
+        check_seq_off(seq_off, n_seq, k, "jas_kmer_offsets");
+        if (n < 0 || !smp_off || !ids_off) fail(JAS_EINVAL, "jas_kmer_offsets: n < 0 or NULL smp_off / ids_off");
+        if (smp_off[0] != 0 || smp_off[n] != (uint64_t)n_seq)
+            fail(JAS_EINVAL, "jas_kmer_offsets: smp_off must run from 0 to n_seq");
+        for (int32_t i = 0; i < n; ++i)
+            if (smp_off[i + 1] < smp_off[i]) fail(JAS_EINVAL, "jas_kmer_offsets: smp_off decreases");
+        std::vector<uint64_t> kb;
+        kmer_starts(seq_off, n_seq, k, kb);
+        for (int32_t i = 0; i <= n; ++i) ids_off[i] = kb[smp_off[i]];
+    });
+}
+
+jas_status jas_kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t k, uint32_t flags,
+                     void *hip_stream, uint64_t *ids) {
+    return guard([&] {
+        check_seq_off(seq_off, n_seq, k, "jas_kmers");
+        if (flags & ~(uint32_t)JAS_CANONICAL) fail(JAS_EINVAL, "jas_kmers: only JAS_CANONICAL is accepted");
+        std::vector<uint64_t> kb;
+        if (kmer_starts(seq_off, n_seq, k, kb) == 0) return;
+        if (!seq || !ids) fail(JAS_EINVAL, "jas_kmers: seq or ids is NULL");
+        JAS_HOST_TIMED("jas_kmers");
+        kmers(seq, seq_off, n_seq, k, flags & JAS_CANONICAL, (hipStream_t)hip_stream, ids);
+    });
+}
+
 jas_status jas_query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint32_t flags,
                      void *hip_stream, int32_t *B, int64_t *q_card, int64_t *den, double *J) {
     return guard([&] {

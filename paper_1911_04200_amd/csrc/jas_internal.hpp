@@ -221,6 +221,9 @@ uint32_t choose_dense_min_degree(const std::vector<uint64_t> &deg_hist, uint32_t
 // Gram and finalize (see gram.hip).
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J);
 void finalize(uint32_t n, bool upper, hipStream_t s, int32_t *B, const int64_t *card, int64_t *den, double *J);
+uint64_t kmer_starts(const uint64_t *seq_off, int64_t n_seq, uint32_t k, std::vector<uint64_t> &kbase);
+void kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t k, bool canonical, hipStream_t s,
+           uint64_t *ids);
 int32_t gram_variants();
 
 // Query (see query.hip).

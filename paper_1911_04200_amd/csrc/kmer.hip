@@ -1,0 +1,89 @@
+// k-mer sets from 2-bit packed sequences: the step before the encoding.
+//
+// A k-mer is a length-k substring of a sequence (Sec. II-B); a sample's set is
+// the k-mers of its sequences.  Each k-mer becomes one ID: the bases read as a
+// base-4 number, first base most significant (A = 0, C = 1, G = 2, T = 3), so
+// IDs are below 4^k = 2^(2k).  With JAS_CANONICAL the ID is the smaller of the
+// k-mer and its reverse complement (the strand-independent form; odd k has
+// no k-mer equal to its own reverse complement, Sec. V-A2).
+//
+// One thread per output k-mer: the sequence holding it comes from a binary
+// search over the per-sequence k-mer starts, its bases from two 64-bit words
+// of the packed array.  Bases sit least significant first in the words (base b
+// at bits 2(b mod 32) of word b / 32), so a window read out of the words has
+// the first base in its low bits: the reverse complement is then the
+// complement of that window (3 - x per base is ~x on 2 bits), and the
+// most-significant-first value is the window with its 2-bit groups reversed.
+#include "jas_internal.hpp"
+
+namespace jas {
+namespace {
+
+// Reverse the order of the 2-bit groups of a 64-bit word.
+__device__ __forceinline__ uint64_t reverse_pairs(uint64_t y) {
+    y = __builtin_bitreverse64(y);
+    return ((y >> 1) & 0x5555555555555555ull) | ((y & 0x5555555555555555ull) << 1);
+}
+
+__global__ void k_kmers(const uint64_t *__restrict__ seq, const uint64_t *__restrict__ seq_off,
+                        const uint64_t *__restrict__ kbase, uint64_t n_seq, uint64_t total, uint32_t k,
+                        int canonical, uint64_t *__restrict__ ids) {
+    const uint64_t mask = (k == 32) ? ~0ull : ((1ull << (2 * k)) - 1);
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        // sequence s: the largest with kbase[s] <= t (sequences without k-mers
+        // share their successor's start and are never the largest)
+        uint64_t lo = 0, hi = n_seq - 1;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) >> 1;
+            if (kbase[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint64_t b = seq_off[lo] + (t - kbase[lo]);  // first base of the k-mer
+        const uint64_t w = b >> 5, sh = 2 * (b & 31);
+        uint64_t win = seq[w] >> sh;
+        if (sh + 2 * k > 64) win |= seq[w + 1] << (64 - sh);  // only a word that holds bases of the k-mer
+        win &= mask;                                               // first base in the low bits
+        const uint64_t fwd = reverse_pairs(win) >> (64 - 2 * k);  // first base most significant
+        uint64_t id = fwd;
+        if (canonical) {
+            const uint64_t rc = ~win & mask;  // reverse complement, first base most significant
+            id = rc < fwd ? rc : fwd;
+        }
+        ids[t] = id;
+    }
+}
+
+}  // namespace
+
+uint64_t kmer_starts(const uint64_t *seq_off, int64_t n_seq, uint32_t k, std::vector<uint64_t> &kbase) {
+    kbase.assign((size_t)n_seq + 1, 0);
+    for (int64_t s = 0; s < n_seq; ++s) {
+        const uint64_t len = seq_off[s + 1] - seq_off[s];
+        kbase[s + 1] = kbase[s] + (len >= k ? len - k + 1 : 0);
+    }
+    return kbase[n_seq];
+}
+
+void kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t k, bool canonical, hipStream_t s,
+           uint64_t *ids) {
+    std::vector<uint64_t> kb;
+    const uint64_t total = kmer_starts(seq_off, n_seq, k, kb);
+    if (total == 0) return;
+    DevBuf<uint64_t> dkb, doff;
+    dkb.alloc(kb.size(), s, nullptr, true, "k-mer starts");
+    doff.alloc((size_t)n_seq + 1, s, nullptr, true, "sequence offsets");
+    JAS_HIP(hipMemcpyAsync(dkb.p, kb.data(), kb.size() * 8, hipMemcpyHostToDevice, s));
+    JAS_HIP(hipMemcpyAsync(doff.p, seq_off, ((size_t)n_seq + 1) * 8, hipMemcpyHostToDevice, s));
+    const uint64_t blocks = std::min<uint64_t>(div_up(total, 256), 65536);
+    {
+        JAS_TIMED("kmers", s);
+        k_kmers<<<(uint32_t)blocks, 256, 0, s>>>(seq, doff.p, dkb.p, (uint64_t)n_seq, total, k, canonical ? 1 : 0,
+                                                  ids);
+    }
+    check_launch("k-mers");
+    // the host arrays above are read by the copies before this call returns
+    JAS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace jas

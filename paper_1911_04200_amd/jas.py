@@ -24,6 +24,7 @@ JAS_FORCE_POPCOUNT = 0x20
 JAS_FORCE_MFMA = 0x40
 JAS_TUNE = 0x80
 JAS_ACCUMULATE = 0x100
+JAS_CANONICAL = 0x200
 
 
 def JAS_GRAM_VARIANT(v: int) -> int:
@@ -34,7 +35,7 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
                 -6: "JAS_EUNSUPPORTED"}
 
 # Every symbol include/jas.h declares.
-EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_gram_variants", "jas_query", "jas_query_workspace_bytes",
+EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_gram_variants", "jas_query", "jas_query_workspace_bytes",
                   "jas_db_size", "jas_db_stats", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
                   "jas_timing_report", "jas_trim"])
 
@@ -84,6 +85,10 @@ def load(path: str = LIB_PATH):
                                ctypes.POINTER(jas_encode_stats)]
     lib.jas_encode.restype = ctypes.c_int
     lib.jas_gram.argtypes = [vp, u32, vp, vp, vp, vp, vp]
+    lib.jas_kmer_offsets.restype = i32
+    lib.jas_kmer_offsets.argtypes = [vp, ctypes.c_int64, vp, i32, u32, vp]
+    lib.jas_kmers.restype = i32
+    lib.jas_kmers.argtypes = [vp, vp, ctypes.c_int64, u32, u32, vp, vp]
     lib.jas_finalize.restype = i32
     lib.jas_finalize.argtypes = [i32, u32, vp, vp, vp, vp, vp]
     lib.jas_gram.restype = ctypes.c_int
@@ -182,6 +187,22 @@ def jas_gram(db, flags: int, stream, B, card=None, den=None, J=None):
 
 def jas_finalize(n: int, flags: int, stream, B, card, den=None, J=None):
     _check(load().jas_finalize(n, flags, _stream(stream), _ptr(B), _ptr(card), _ptr(den), _ptr(J)))
+
+
+def jas_kmer_offsets(seq_off: np.ndarray, smp_off: np.ndarray, k: int) -> np.ndarray:
+    """Host: the CSR offsets (uint64[n+1]) of the samples' k-mers."""
+    seq_off = np.ascontiguousarray(seq_off, dtype=np.uint64)
+    smp_off = np.ascontiguousarray(smp_off, dtype=np.uint64)
+    out = np.empty(smp_off.size, dtype=np.uint64)
+    _check(load().jas_kmer_offsets(seq_off.ctypes.data, seq_off.size - 1, smp_off.ctypes.data, smp_off.size - 1, k,
+                                   out.ctypes.data))
+    return out
+
+
+def jas_kmers(seq, seq_off: np.ndarray, k: int, flags: int, stream, ids):
+    """Device: the k-mer IDs of every sequence into ids (seq_off on the host)."""
+    seq_off = np.ascontiguousarray(seq_off, dtype=np.uint64)
+    _check(load().jas_kmers(_ptr(seq), seq_off.ctypes.data, seq_off.size - 1, k, flags, _stream(stream), _ptr(ids)))
 
 
 def jas_query(db, q_ids, q_offsets, nq: int, flags: int, stream, B, q_card=None, den=None, J=None):

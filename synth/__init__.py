@@ -322,3 +322,43 @@ def scaled(spec: Spec, n: Optional[int] = None, size_scale: float = 1.0, pool_sc
     if dup_rate is not None:
         kw["dup_rate"] = dup_rate
     return spec.replace(**kw)
+
+
+# ---------------------------------------------------------------------------
+# Sequences (inputs of the k-mer front end): base codes A = 0, C = 1, G = 2,
+# T = 3, and their 2-bit packed form.
+def random_genomes(n: int, length: int, n_refs: int = 4, mutation: float = 0.01, seqs_per_sample: int = 1,
+                   seed: int = 0):
+    """n samples, each `seqs_per_sample` sequences of about `length` bases: a
+    copy of one of n_refs random reference genomes (cut into pieces) with each
+    base substituted with probability `mutation`.  Returns a list (per sample)
+    of lists of uint8 base-code arrays."""
+    rng = np.random.default_rng((_SEED_BASE + 8 + seed) & 0xFFFFFFFF)
+    refs = [rng.integers(0, 4, size=length, dtype=np.uint8) for _ in range(n_refs)]
+    out = []
+    for i in range(n):
+        g = refs[int(rng.integers(0, n_refs))].copy()
+        hit = rng.choice(length, size=int(rng.binomial(length, mutation)), replace=False)  # substituted bases
+        g[hit] = (g[hit] + rng.integers(1, 4, size=hit.size, dtype=np.uint8)) % 4
+        cuts = np.sort(rng.choice(np.arange(1, length), size=seqs_per_sample - 1, replace=False)) \
+            if seqs_per_sample > 1 else np.zeros(0, np.int64)
+        out.append(np.split(g, cuts))
+    return out
+
+
+def pack_2bit(seqs):
+    """Sequences (uint8 base codes) -> (words uint64, seq_off uint64[len+1]):
+    base b of the concatenation at bits 2 (b mod 32) of word b / 32."""
+    lens = np.array([s.size for s in seqs], dtype=np.uint64)
+    off = np.zeros(len(seqs) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=off[1:])
+    L = int(off[-1])
+    nw = max(1, (L + 31) // 32)
+    bases = np.zeros(nw * 32, dtype=np.uint8)
+    if L:
+        bases[:L] = np.concatenate(seqs)
+    b = bases.reshape(nw, 32)
+    words = np.zeros(nw, dtype=np.uint64)
+    for j in range(32):  # base j of each word at bits 2j
+        words |= b[:, j].astype(np.uint64) << np.uint64(2 * j)
+    return words, off

@@ -1,0 +1,67 @@
+"""The GPU k-mer front end against the oracle, and sequences -> Jaccard end to end."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1911_04200_amd as jas  # noqa: E402
+from paper_1911_04200_amd import jas as cabi  # noqa: E402
+
+
+def gpu_kmers(samples, k, canonical):
+    seqs = [s for smp in samples for s in smp]
+    words, seq_off = synth.pack_2bit(seqs)
+    smp_off = np.zeros(len(samples) + 1, dtype=np.uint64)
+    np.cumsum([len(x) for x in samples], out=smp_off[1:])
+    ids_off = cabi.jas_kmer_offsets(seq_off, smp_off, k)
+    ids = torch.empty(max(1, int(ids_off[-1])), dtype=torch.int64, device="cuda")
+    cabi.jas_kmers(torch.from_numpy(words.view(np.int64)).cuda(), seq_off, k,
+                   cabi.JAS_CANONICAL if canonical else 0, None, ids)
+    torch.cuda.synchronize()
+    return ids, ids_off
+
+
+@pytest.mark.parametrize("k", [1, 3, 19, 31])
+@pytest.mark.parametrize("canonical", [False, True])
+def test_kmers_match_the_oracle(k, canonical):
+    rng = np.random.default_rng(k)
+    lens = [0, 1, 5, 31, 32, 33, 63, 64, 65, 1000, 4097, 30]
+    samples = [[rng.integers(0, 4, size=L, dtype=np.uint8) for L in lens[i::3]] for i in range(3)]
+    samples.append([])  # a sample without sequences
+    ids, off = gpu_kmers(samples, k, canonical)
+    want, want_off = oracle.kmer_sets(samples, k, canonical)
+    assert np.array_equal(off, want_off)
+    assert np.array_equal(ids.cpu().numpy().view(np.uint64)[:want.size], want)
+
+
+def test_argument_checks():
+    with pytest.raises(cabi.JasError):
+        cabi.jas_kmer_offsets(np.array([0, 5], np.uint64), np.array([0, 1], np.uint64), 32)
+    with pytest.raises(cabi.JasError):
+        cabi.jas_kmer_offsets(np.array([0, 5], np.uint64), np.array([0, 2], np.uint64), 3)
+    with pytest.raises(cabi.JasError):
+        cabi.jas_kmers(None, np.array([0, 5], np.uint64), 3, 0x1, None, None)
+
+
+def test_sequences_to_jaccard_end_to_end():
+    # mutated copies of 4 reference genomes, 3 sequences each; k = 19 canonical
+    samples = synth.random_genomes(40, 20000, n_refs=4, mutation=0.01, seqs_per_sample=3, seed=5)
+    k = 19
+    ids, off = gpu_kmers(samples, k, True)
+    res_db, st = jas.encode(ids[:int(off[-1])], torch.from_numpy(off.view(np.int64)).cuda(), universe_bits=2 * k,
+                            batch_bits=30)
+    out = jas.gram(res_db, upper=False)
+    torch.cuda.synchronize()
+    want_ids, want_off = oracle.kmer_sets(samples, k, True)
+    ref = oracle.all_pairs(want_ids, want_off)
+    assert np.array_equal(out["card"].cpu().numpy(), ref["card"])
+    assert np.array_equal(out["B"].cpu().numpy().reshape(40, 40), ref["inter"])
+    J = out["J"].cpu().numpy().reshape(40, 40)
+    assert np.array_equal(J.view(np.uint64), ref["J"].view(np.uint64))
+    # copies of one reference are far more alike than copies of two
+    assert J.max(initial=0, where=~np.eye(40, dtype=bool)) > 0.5
+    res_db.close()
