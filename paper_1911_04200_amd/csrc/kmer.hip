@@ -7,9 +7,9 @@
 // k-mer and its reverse complement (the strand-independent form; odd k has
 // no k-mer equal to its own reverse complement, Sec. V-A2).
 //
-// One thread per output k-mer: the sequence holding it comes from a binary
-// search over the per-sequence k-mer starts, its bases from two 64-bit words
-// of the packed array.  Bases sit least significant first in the words (base b
+// One thread per output k-mer: the sequence holding it comes from a search
+// over the per-sequence k-mer starts, its bases from two 64-bit words of the
+// packed array.  Bases sit least significant first in the words (base b
 // at bits 2(b mod 32) of word b / 32), so a window read out of the words has
 // the first base in its low bits: the reverse complement is then the
 // complement of that window (3 - x per base is ~x on 2 bits), and the
@@ -25,32 +25,62 @@ __device__ __forceinline__ uint64_t reverse_pairs(uint64_t y) {
     return ((y >> 1) & 0x5555555555555555ull) | ((y & 0x5555555555555555ull) << 1);
 }
 
-__global__ void k_kmers(const uint64_t *__restrict__ seq, const uint64_t *__restrict__ seq_off,
-                        const uint64_t *__restrict__ kbase, uint64_t n_seq, uint64_t total, uint32_t k,
-                        int canonical, uint64_t *__restrict__ ids) {
+constexpr uint32_t kKmerNT = 256, kKmerPer = 8;  // a block's tile: kKmerNT * kKmerPer k-mers
+
+// A block per tile of consecutive k-mers: one binary search over the
+// per-sequence k-mer starts finds the sequence of the tile's first k-mer;
+// each thread walks forward from there (k-mers t, t + kKmerNT, ...; a tile
+// rarely crosses more than one sequence boundary).
+__global__ __launch_bounds__(kKmerNT) void k_kmers(const uint64_t *__restrict__ seq,
+                                                   const uint64_t *__restrict__ seq_off,
+                                                   const uint64_t *__restrict__ kbase, uint64_t n_seq,
+                                                   uint64_t total, uint32_t k, int canonical,
+                                                   uint64_t *__restrict__ ids) {
+    __shared__ uint64_t s0;
     const uint64_t mask = (k == 32) ? ~0ull : ((1ull << (2 * k)) - 1);
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        // sequence s: the largest with kbase[s] <= t (sequences without k-mers
-        // share their successor's start and are never the largest)
-        uint64_t lo = 0, hi = n_seq - 1;
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi + 1) >> 1;
-            if (kbase[mid] <= t) lo = mid;
-            else hi = mid - 1;
+    const uint64_t tile = (uint64_t)kKmerNT * kKmerPer;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < total; t0 += (uint64_t)gridDim.x * tile) {
+        if (threadIdx.x == 0) {
+            // the largest s with kbase[s] <= t0 (a sequence without k-mers
+            // shares its successor's start and is never the largest)
+            uint64_t lo = 0, hi = n_seq - 1;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi + 1) >> 1;
+                if (kbase[mid] <= t0) lo = mid;
+                else hi = mid - 1;
+            }
+            s0 = lo;
         }
-        const uint64_t b = seq_off[lo] + (t - kbase[lo]);  // first base of the k-mer
-        const uint64_t w = b >> 5, sh = 2 * (b & 31);
-        uint64_t win = seq[w] >> sh;
-        if (sh + 2 * k > 64) win |= seq[w + 1] << (64 - sh);  // only a word that holds bases of the k-mer
-        win &= mask;                                               // first base in the low bits
-        const uint64_t fwd = reverse_pairs(win) >> (64 - 2 * k);  // first base most significant
-        uint64_t id = fwd;
-        if (canonical) {
-            const uint64_t rc = ~win & mask;  // reverse complement, first base most significant
-            id = rc < fwd ? rc : fwd;
+        __syncthreads();
+        uint64_t s = s0;
+        __syncthreads();  // s0 is rewritten by the next tile
+        // this thread's sequence: its k-mers end before `next`, and k-mer t
+        // starts at base `shift + t`
+        uint64_t next = kbase[s + 1], shift = seq_off[s] - kbase[s];
+#pragma unroll
+        for (uint32_t u = 0; u < kKmerPer; ++u) {
+            const uint64_t t = t0 + (uint64_t)u * kKmerNT + threadIdx.x;
+            if (t >= total) break;
+            if (next <= t) {
+                do {
+                    ++s;
+                    next = kbase[s + 1];  // kbase[n_seq] = total > t ends the walk
+                } while (next <= t);
+                shift = seq_off[s] - kbase[s];
+            }
+            const uint64_t b = shift + t;  // first base of the k-mer
+            const uint64_t w = b >> 5, sh = 2 * (b & 31);
+            uint64_t win = seq[w] >> sh;
+            if (sh + 2 * k > 64) win |= seq[w + 1] << (64 - sh);  // only a word that holds bases of the k-mer
+            win &= mask;                                               // first base in the low bits
+            const uint64_t fwd = reverse_pairs(win) >> (64 - 2 * k);  // first base most significant
+            uint64_t id = fwd;
+            if (canonical) {
+                const uint64_t rc = ~win & mask;  // reverse complement, first base most significant
+                id = rc < fwd ? rc : fwd;
+            }
+            ids[t] = id;
         }
-        ids[t] = id;
     }
 }
 
@@ -75,10 +105,10 @@ void kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t
     doff.alloc((size_t)n_seq + 1, s, nullptr, true, "sequence offsets");
     JAS_HIP(hipMemcpyAsync(dkb.p, kb.data(), kb.size() * 8, hipMemcpyHostToDevice, s));
     JAS_HIP(hipMemcpyAsync(doff.p, seq_off, ((size_t)n_seq + 1) * 8, hipMemcpyHostToDevice, s));
-    const uint64_t blocks = std::min<uint64_t>(div_up(total, 256), 65536);
+    const uint64_t blocks = std::min<uint64_t>(div_up(total, (uint64_t)kKmerNT * kKmerPer), 65536);
     {
         JAS_TIMED("kmers", s);
-        k_kmers<<<(uint32_t)blocks, 256, 0, s>>>(seq, doff.p, dkb.p, (uint64_t)n_seq, total, k, canonical ? 1 : 0,
+        k_kmers<<<(uint32_t)blocks, kKmerNT, 0, s>>>(seq, doff.p, dkb.p, (uint64_t)n_seq, total, k, canonical ? 1 : 0,
                                                   ids);
     }
     check_launch("k-mers");
