@@ -25,7 +25,7 @@ __device__ __forceinline__ uint64_t reverse_pairs(uint64_t y) {
     return ((y >> 1) & 0x5555555555555555ull) | ((y & 0x5555555555555555ull) << 1);
 }
 
-constexpr uint32_t kKmerNT = 256, kKmerPer = 8;  // a block's tile: kKmerNT * kKmerPer k-mers
+constexpr uint32_t kKmerNT = 256, kKmerPer = 16;  // a block's tile: kKmerNT * kKmerPer k-mers
 constexpr uint32_t kKmerStage = 512;              // packed words a tile stages in LDS, at most
 
 // Largest s with kbase[s] <= t (a sequence without k-mers shares its
