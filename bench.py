@@ -320,7 +320,6 @@ def main():
     import torch
 
     import synth
-    import paper_1911_04200_amd as jas
     from paper_1911_04200_amd import jas as cabi
 
     if args.stream_part_bits > 0:
