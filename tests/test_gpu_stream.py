@@ -81,3 +81,12 @@ def test_accumulate_flag_rules():
     assert np.array_equal(card.cpu().numpy(), 2 * ref["card"])
     assert np.array_equal(B.cpu().numpy().reshape(20, 20), 2 * ref["inter"])
     db.close()
+
+
+def test_streamed_graph_neighbourhoods():
+    # skewed rows (hubs next to isolated vertices) split over 4 ID ranges
+    ids, off = synth.rmat_graph(10, 16, seed=4)
+    ref = oracle.all_pairs(ids, off)
+    res = stream.all_pairs_streamed(ids, off, 10, 2, batch_bits=8, upper=True)
+    torch.cuda.synchronize()
+    check(host(res), ref, True)
