@@ -246,8 +246,9 @@ def run_streamed(args):
     torch.cuda.set_device(0)
 
     def step():
+        gf = cabi.JAS_GRAM_VARIANT(args.gram_variant) if args.gram_variant >= 0 else 0
         res = stream.all_pairs_streamed(ids, off, U, K, batch_bits=synth.BATCH_BITS[args.workload],
-                                        dense_min_degree=args.dmin, upper=args.upper, bounds=bounds)
+                                        dense_min_degree=args.dmin, upper=args.upper, bounds=bounds, gram_flags=gf)
         torch.cuda.synchronize()
         return res
 
@@ -272,7 +273,8 @@ def run_streamed(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "u64 keys / i32 counts / f64 J", "data": "synthetic (seeded counter-based generator, synth/)",
            "config": {"workload": f"{args.workload}_n{n}_u{U}_streamed", "n": n, "universe_bits": U, "ids": int(ids.size),
-                      "parts": 1 << K, "inputs": "host memory; gather into page-locked staging and host-to-device "
+                      "parts": 1 << K, "gram_variant": args.gram_variant,
+                      "inputs": "host memory; gather into page-locked staging and host-to-device "
                       "copies inside the timed region", "layout": "upper" if args.upper else "full"},
            "roofline": None, "cpu_baseline": None,
            "detail": {"host_gather_s_per_step": res["host_gather_s"], "max_part_ids": res["max_part_ids"],
@@ -303,6 +305,8 @@ def main():
     ap.add_argument("--stream-part-bits", type=int, default=0,
                     help="K > 0: keep the sets in host memory and stream them in 2^K ID-range parts "
                          "(Bernoulli workloads, whose sets are ascending); host-to-device copies are timed")
+    ap.add_argument("--gram-variant", type=int, default=-1,
+                    help="with --stream-part-bits: run MFMA tile variant V for every part (default: the library's)")
     ap.add_argument("--kmer-front-end", action="store_true",
                     help="time the GPU k-mer front end instead (128 genomes of 4 Mbases, k = 31, canonical): "
                          "bases/s, inputs resident in HBM")
