@@ -6,7 +6,9 @@ batches' Gram products.  Here the sets stay in host memory and are cut into
 parts, each an ID range of 2^(U - part_bits) rows (one or more batches).  A
 producer thread gathers part p + 1 into page-locked memory and copies it to
 the GPU on its own stream while the caller's thread encodes part p and adds
-its counts into the resident B (jas_gram with JAS_ACCUMULATE); jas_finalize
+its counts into the resident B (jas_gram with JAS_ACCUMULATE; the part's IDs
+relabelled to offsets in its range, so it is encoded over 2^(U - part_bits)
+rows); jas_finalize
 then writes the diagonal, the unions and J.  Two staging slots in host and
 device memory alternate, so the device holds two parts' IDs, one part's
 encoding and B at any time.
@@ -50,16 +52,17 @@ def plan_parts(ids: np.ndarray, offsets: np.ndarray, universe_bits: int, part_bi
     return bounds
 
 
-def _gather(ids, lo, hi, dst, pool, chunks):
-    """dst[k] <- concatenation of ids[lo[i]:hi[i]] over i; returns the CSR offsets."""
+def _gather(ids, lo, hi, dst, pool, chunks, base: int = 0):
+    """dst <- concatenation of ids[lo[i]:hi[i]] - base over i; returns the CSR offsets."""
     sizes = (hi - lo).astype(np.int64)
     off = np.zeros(sizes.size + 1, dtype=np.int64)
     np.cumsum(sizes, out=off[1:])
+    b = np.uint64(base)
 
     def work(r):
         for i in range(r[0], r[1]):
             if sizes[i]:
-                dst[off[i]:off[i + 1]] = ids[int(lo[i]):int(hi[i])]
+                np.subtract(ids[int(lo[i]):int(hi[i])], b, out=dst[off[i]:off[i + 1]])
 
     n = sizes.size
     step = max(1, -(-n // chunks))
@@ -84,6 +87,12 @@ def all_pairs_streamed(ids: np.ndarray, offsets: np.ndarray, universe_bits: int,
     if bounds is None:
         bounds = plan_parts(ids, offsets, universe_bits, part_bits, check_sorted)
     nparts = bounds.shape[0] - 1
+    # a part's IDs are relabelled to their offset in the part's range, so each
+    # part is encoded over its own 2^(U - part_bits) rows: the sort's top-bit
+    # buckets then split the part's IDs, not the whole universe's
+    part_bits = (nparts - 1).bit_length()
+    part_shift = universe_bits - part_bits
+    part_U = max(1, part_shift)
     part_len = (bounds[1:] - bounds[:-1]).sum(axis=1).astype(np.int64)
     cap = max(1, int(part_len.max(initial=0)))
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -120,7 +129,8 @@ def all_pairs_streamed(ids: np.ndarray, offsets: np.ndarray, universe_bits: int,
                             copied[k].synchronize()   # the host slot's last copy has landed
                             copy.wait_event(used[k])  # the device slot is no longer read
                         t0 = time.perf_counter()
-                        o = _gather(ids, bounds[p], bounds[p + 1], host[k].numpy().view(np.uint64), pool, workers)
+                        o = _gather(ids, bounds[p], bounds[p + 1], host[k].numpy().view(np.uint64), pool, workers,
+                                    base=p << part_shift)
                         host_off[k].numpy()[:] = o
                         t_gather[0] += time.perf_counter() - t0
                         L = int(o[-1])
@@ -146,7 +156,7 @@ def all_pairs_streamed(ids: np.ndarray, offsets: np.ndarray, universe_bits: int,
                 raise errors[0]
             p, k, L = item
             compute.wait_event(copied[k])
-            opts = cabi.jas_encode_opts(universe_bits, batch_bits, dense_min_degree, 0, 0)
+            opts = cabi.jas_encode_opts(part_U, min(batch_bits, part_U) if batch_bits else 0, dense_min_degree, 0, 0)
             db, st = cabi.jas_encode(dids[k], doff[k], n, opts, compute)
             cabi.jas_gram(db, flags, compute, B, card)
             ev = torch.cuda.Event()

@@ -36,6 +36,14 @@ def test_gather_packs_one_part_as_csr():
         x = dst[o[i]:o[i + 1]]
         assert np.array_equal(x, ids[int(bounds[1, i]):int(bounds[2, i])])
         assert np.all((x >> np.uint64(10)) == 1)
+    # relabelled to offsets in the part's ID range [1 << 10, 2 << 10)
+    with ThreadPoolExecutor(4) as pool:
+        o2 = stream._gather(ids, bounds[1], bounds[2], dst, pool, 4, base=1 << 10)
+    assert np.array_equal(o2, o)
+    for i in range(20):
+        x = dst[o[i]:o[i + 1]]
+        assert np.array_equal(x + np.uint64(1 << 10), ids[int(bounds[1, i]):int(bounds[2, i])])
+        assert np.all(x < (1 << 10))
 
 
 def test_unsorted_or_out_of_range_sets_are_refused():
