@@ -2,7 +2,7 @@
 
 A plain C implementation (``oracle.c``) of the definitions in Sec. II-A of the
 paper: sets are normalised (sorted, repeats dropped), intersections and unions
-are counted by walking two sorted lists, and J = |X cap Y| / |X cup Y| in
+are counted in one walk over two sorted lists, and J = |X cap Y| / |X cup Y| in
 binary64 with J(empty, empty) = 1.  ``kmers`` writes out the k-mer
 definition of Sec. II-B in numpy (base-4 digits, reverse complement).  It
 shares no code with the GPU library and is loaded only by the tests, the smoke
@@ -36,10 +36,8 @@ def _bind(lib):
     P = ctypes.POINTER
     u64p, i64p, i32p, dp = P(ctypes.c_uint64), P(ctypes.c_int64), P(ctypes.c_int32), P(ctypes.c_double)
     lib.oracle_normalize.argtypes = [u64p, u64p, ctypes.c_int32, u64p, u64p]
-    lib.oracle_intersection.argtypes = [u64p, ctypes.c_uint64, u64p, ctypes.c_uint64]
-    lib.oracle_intersection.restype = ctypes.c_uint64
-    lib.oracle_union.argtypes = [u64p, ctypes.c_uint64, u64p, ctypes.c_uint64]
-    lib.oracle_union.restype = ctypes.c_uint64
+    lib.oracle_counts.argtypes = [u64p, ctypes.c_uint64, u64p, ctypes.c_uint64, u64p, u64p]
+    lib.oracle_counts.restype = None
     lib.oracle_jaccard.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.oracle_jaccard.restype = ctypes.c_double
     lib.oracle_pairs.argtypes = [u64p, u64p, ctypes.c_int32, u64p, u64p, ctypes.c_int32, ctypes.c_int64,

@@ -67,29 +67,23 @@ int oracle_normalize(const uint64_t *ids, const uint64_t *offsets, int32_t n, ui
     return 0;
 }
 
-/* |X cap Y| of two sorted, repeat-free lists. */
-uint64_t oracle_intersection(const uint64_t *x, uint64_t nx, const uint64_t *y, uint64_t ny)
+/* |X cap Y| and |X cup Y| of two sorted, repeat-free lists, counted in one
+ * walk over both: each step takes the smaller of the two heads (both heads
+ * when they are equal, which is then an element of the intersection), so
+ * every step takes exactly one element of the union; whatever remains of
+ * either list after the other is exhausted belongs to the union only. */
+void oracle_counts(const uint64_t *x, uint64_t nx, const uint64_t *y, uint64_t ny, uint64_t *inter, uint64_t *uni)
 {
-    uint64_t a = 0, b = 0, c = 0;
+    uint64_t a = 0, b = 0, c = 0, u = 0;
     while (a < nx && b < ny) {
-        if (x[a] < y[b]) ++a;
-        else if (y[b] < x[a]) ++b;
-        else { ++c; ++a; ++b; }
+        const uint64_t p = x[a], q = y[b];
+        c += p == q;
+        a += p <= q;
+        b += q <= p;
+        ++u;
     }
-    return c;
-}
-
-/* |X cup Y| of two sorted, repeat-free lists. */
-uint64_t oracle_union(const uint64_t *x, uint64_t nx, const uint64_t *y, uint64_t ny)
-{
-    uint64_t a = 0, b = 0, c = 0;
-    while (a < nx && b < ny) {
-        if (x[a] < y[b]) ++a;
-        else if (y[b] < x[a]) ++b;
-        else { ++a; ++b; }
-        ++c;
-    }
-    return c + (nx - a) + (ny - b);
+    *inter = c;
+    *uni = u + (nx - a) + (ny - b);
 }
 
 /* J from the two counts (Sec. II-A, including J(empty, empty) = 1). */
@@ -112,8 +106,8 @@ int oracle_pairs(const uint64_t *q, const uint64_t *qoff, int32_t nq, const uint
     for (int64_t k = 0; k < npairs; ++k) {
         const uint64_t *a = q + qoff[qi[k]], *b = x + xoff[xi[k]];
         const uint64_t na = qoff[qi[k] + 1] - qoff[qi[k]], nb = xoff[xi[k] + 1] - xoff[xi[k]];
-        const uint64_t c = oracle_intersection(a, na, b, nb);
-        const uint64_t u = oracle_union(a, na, b, nb);
+        uint64_t c, u;
+        oracle_counts(a, na, b, nb, &c, &u);
         if (inter) inter[k] = (int64_t)c;
         if (uni) uni[k] = (int64_t)u;
         if (jac) jac[k] = oracle_jaccard(c, u);
@@ -132,8 +126,8 @@ int oracle_cross(const uint64_t *q, const uint64_t *qoff, int32_t nq, const uint
         const int32_t i = (int32_t)(k / nx), j = (int32_t)(k % nx);
         const uint64_t *a = q + qoff[i], *b = x + xoff[j];
         const uint64_t na = qoff[i + 1] - qoff[i], nb = xoff[j + 1] - xoff[j];
-        const uint64_t c = oracle_intersection(a, na, b, nb);
-        const uint64_t u = oracle_union(a, na, b, nb);
+        uint64_t c, u;
+        oracle_counts(a, na, b, nb, &c, &u);
         if (inter) inter[k] = (int64_t)c;
         if (uni) uni[k] = (int64_t)u;
         if (jac) jac[k] = oracle_jaccard(c, u);

@@ -16,6 +16,10 @@ same checks serve the oracle tests and the planted-mistake test.
                   set of row degrees, with degrees from numpy's unique counts.
   triangle      - d_J = 1 - J is a metric (Sec. II-A): triangle inequality in
                   exact rational arithmetic.
+  two_collections - query sets against a different collection (Q != X, of
+                  other sizes and offsets), every pair and selected pairs,
+                  against Python's set type: catches the two collections'
+                  offsets or sizes mixed up, which Q = X cannot show.
 """
 from __future__ import annotations
 
@@ -232,7 +236,43 @@ def triangle(lib=None, trials=400):
     return fails
 
 
-ALL = [brute_force, python_sets, closed_forms, golden_hand, invariants, triangle]
+def two_collections(lib=None, seeds=range(3)):
+    fails = []
+    for seed in seeds:
+        rng = np.random.default_rng(4000 + seed)
+        m = int(2 ** rng.integers(4, 10))
+        # different counts and sizes on the two sides, so that no offset of
+        # one collection is also a valid offset of the other by chance
+        if seed % 2 == 1:  # fewer query sets than database sets
+            qsets = _random_tiny(rng, int(rng.integers(2, 7)), m, empty_p=0.15)
+            xsets = [s + [int(v) for v in rng.integers(0, m, 3)] for s in _random_tiny(rng, int(rng.integers(7, 13)), m)]
+        else:  # more, smaller query sets: a mixed-up offset stays inside the other collection
+            qsets = [[int(v) for v in rng.integers(0, m, int(rng.integers(0, 4)))] for _ in range(int(rng.integers(9, 14)))]
+            xsets = [[int(v) for v in rng.integers(0, m, m // 2)] for _ in range(int(rng.integers(3, 7)))]
+        qn, qo = oracle.normalize(*_collection(qsets), lib=lib)
+        xn, xo = oracle.normalize(*_collection(xsets), lib=lib)
+        Q, X = [set(s) for s in qsets], [set(s) for s in xsets]
+        nq, nx = len(Q), len(X)
+        want_i = np.array([[len(Q[a] & X[b]) for b in range(nx)] for a in range(nq)], dtype=np.int64)
+        want_u = np.array([[len(Q[a] | X[b]) for b in range(nx)] for a in range(nq)], dtype=np.int64)
+        want_j = np.array([[1.0 if want_u[a, b] == 0 else float(Fraction(int(want_i[a, b]), int(want_u[a, b])))
+                            for b in range(nx)] for a in range(nq)], dtype=np.float64)
+        ci, cu, cj = oracle.cross_normalized(qn, qo, xn, xo, lib=lib)
+        _check_equal(f"two seed {seed} cross inter", ci, want_i, fails)
+        _check_equal(f"two seed {seed} cross union", cu, want_u, fails)
+        _check_equal(f"two seed {seed} cross J", cj.view(np.uint64), want_j.view(np.uint64), fails)
+        qi = rng.integers(0, nq, 50)
+        xi = rng.integers(0, nx, 50)
+        pi, pu, pj = oracle.pairs_normalized(qn, qo, xn, xo, qi, xi, lib=lib)
+        _check_equal(f"two seed {seed} pairs inter", pi, want_i[qi, xi], fails)
+        _check_equal(f"two seed {seed} pairs union", pu, want_u[qi, xi], fails)
+        _check_equal(f"two seed {seed} pairs J", pj.view(np.uint64), want_j[qi, xi].view(np.uint64), fails)
+        if fails:
+            break  # one failing case is enough (a later one may read out of bounds)
+    return fails
+
+
+ALL = [brute_force, python_sets, closed_forms, golden_hand, invariants, triangle, two_collections]
 
 
 def run_all(lib=None):

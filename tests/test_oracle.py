@@ -53,26 +53,51 @@ def test_rejects_bad_offsets():
 # dropped term, a wrong branch or operand, a wrong convention).  Built from a
 # copy of oracle.c, every mutant must fail at least one pin.
 MUTANTS = {
-    "count_on_wrong_branch": ("if (x[a] < y[b]) ++a;\n        else if (y[b] < x[a]) ++b;\n        else { ++c; ++a; ++b; }",
-                              "if (x[a] < y[b]) { ++a; ++c; }\n        else if (y[b] < x[a]) ++b;\n        else { ++c; ++a; ++b; }"),
-    "union_drops_tails": ("return c + (nx - a) + (ny - b);", "return c + (nx - a);"),
+    "count_on_wrong_branch": ("c += p == q;", "c += p <= q;"),
+    "union_drops_tails": ("*uni = u + (nx - a) + (ny - b);", "*uni = u + (nx - a);"),
+    "union_counts_match_twice": ("++u;\n    }", "u += 1 + (p == q);\n    }"),
     "empty_pair_is_zero": ("if (uni == 0) return 1.0;", "if (uni == 0) return 0.0;"),
     "keeps_repeats": ("if (dst[t] != dst[k - 1]) dst[k++] = dst[t];", "dst[k++] = dst[t];"),
     "transposed_ratio": ("return (double)inter / (double)uni;", "return (double)uni / (double)(inter ? inter : 1);"),
     "float_quotient": ("return (double)inter / (double)uni;", "return (double)((float)inter / (float)uni);"),
-    "off_by_one_start": ("uint64_t a = 0, b = 0, c = 0;\n    while (a < nx && b < ny) {\n        if (x[a] < y[b]) ++a;\n        else if (y[b] < x[a]) ++b;\n        else { ++c; ++a; ++b; }",
-                         "uint64_t a = 1, b = 0, c = 0;\n    while (a < nx && b < ny) {\n        if (x[a] < y[b]) ++a;\n        else if (y[b] < x[a]) ++b;\n        else { ++c; ++a; ++b; }"),
+    "off_by_one_start": ("uint64_t a = 0, b = 0, c = 0, u = 0;", "uint64_t a = 1, b = 0, c = 0, u = 0;"),
     "signed_compare": ("return (x > y) - (x < y);", "return ((int64_t)x > (int64_t)y) - ((int64_t)x < (int64_t)y);"),
+    # the two collections' offsets confused: invisible while Q = X
+    "pairs_mix_offsets": ("*b = x + xoff[xi[k]];", "*b = x + qoff[xi[k]];"),
+    "pairs_mix_sizes": ("nb = xoff[xi[k] + 1] - xoff[xi[k]];", "nb = qoff[xi[k] + 1] - qoff[xi[k]];"),
+    "cross_mix_offsets": ("*b = x + xoff[j];", "*b = x + qoff[j];"),
 }
+
+
+_CHILD = """
+import sys
+sys.path[:0] = [{root!r}, {tests!r}]
+import oracle, pins
+lib = oracle.load({lib!r})
+failed = 0
+for check in pins.ALL:
+    if check(lib=lib):
+        failed += 1
+        print("PINS_FAILED", check.__name__, flush=True)
+print("PINS_PASSED" if not failed else "DONE", flush=True)
+"""
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_is_caught(name, tmp_path):
+    """The mutant's pins run in a child process: a mistake that makes the
+    oracle read out of bounds may crash it, and a crash is a detection too."""
+    import subprocess
+    import sys
     src = open(oracle._SRC).read()
     old, new = MUTANTS[name]
     assert src.count(old) == 1, f"mutation site for {name} not unique"
     msrc = tmp_path / "oracle_mut.c"
     msrc.write_text(src.replace(old, new))
-    lib = oracle.load(oracle.build(force=True, src=str(msrc), out=str(tmp_path / "liboracle_mut.so")))
-    fails = pins.run_all(lib=lib)
-    assert fails, f"planted mistake {name} passed every pin"
+    lib = oracle.build(force=True, src=str(msrc), out=str(tmp_path / "liboracle_mut.so"))
+    tests = os.path.dirname(os.path.abspath(__file__))
+    code = _CHILD.format(root=os.path.dirname(tests), tests=tests, lib=lib)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    if "PINS_FAILED" in r.stdout:
+        return  # a pin failed (a later one may have crashed on the mutant's reads)
+    assert r.returncode < 0, f"planted mistake {name} passed every pin:\n{r.stdout}\n{r.stderr[-2000:]}"
