@@ -140,7 +140,9 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
  * captured) and calls jas_finalize after the last one; until then the
  * diagonal and, in the full layout, the lower triangle of B are undefined.
  * The db of each batch must hold the same n samples; a row (ID) may appear in
- * only one of them.
+ * only one of them.  The sums are int32: they are exact while every summed
+ * |X_i| stays below 2^31 (B_ij <= min(|X_i|, |X_j|), so no sum of B can then
+ * overflow); jas_finalize checks that bound.
  */
 jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t *B, int64_t *card, int64_t *den,
                     double *J);
@@ -157,10 +159,20 @@ jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t 
  *  B       int32, device, n*n or n(n+1)/2 entries: read and completed.
  *  card    int64[n], device: |X_i| summed over the batches.
  *  den, J  as in jas_gram; may be NULL.
- * Asynchronous on hip_stream.  EINVAL for n < 0, NULL B or card, other flags.
+ * Before writing anything, checks on the device that every summed |X_i| is
+ * below jas_card_limit() and reads that one flag back (synchronises
+ * hip_stream): EOVERFLOW otherwise, because an int32 sum of B may then have
+ * overflowed.  EINVAL for n < 0, NULL B or card, other flags.
  */
 jas_status jas_finalize(int32_t n, uint32_t flags, void *hip_stream, int32_t *B, const int64_t *card, int64_t *den,
                         double *J);
+
+/* The bound on set sizes the int32 intersections allow: jas_encode and
+ * jas_finalize return EOVERFLOW for a set of jas_card_limit() or more distinct
+ * IDs.  2^31, unless the environment variable JAS_TEST_CARD_LIMIT holds a
+ * positive integer below 2^31 (a test hook, read at every check, so tests can
+ * reach the error with small inputs).  Host only. */
+uint64_t jas_card_limit(void);
 
 /*
  * jas_kmer_offsets / jas_kmers -- the k-mer sets of n samples from their

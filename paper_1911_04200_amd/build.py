@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "libjas.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["scan.hip", "radix.hip", "encode.hip", "gram.hip", "query.hip", "api.hip", "timing.hip", "memory.hip", "tune.hip", "kmer.hip"]
-HEADERS = ["jas_internal.hpp", "device_util.hpp"]
+HEADERS = ["jas_internal.hpp", "device_util.hpp", "onesweep_index.hpp"]
 
 # gfx950 only; packed FP32 instructions disabled; no fast math.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

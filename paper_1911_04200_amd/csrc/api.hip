@@ -1,6 +1,7 @@
 // The C entry points of libjas (include/jas.h): argument checks on the host,
 // error capture, host staging for JAS_HOST_PTRS, and the call sequence of
 // each operation.  No exception crosses the ABI.
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -66,6 +67,15 @@ void check_hip(hipError_t e, const char *what) {
     }
 }
 
+uint64_t card_limit() {
+    constexpr uint64_t kLimit = uint64_t(1) << 31;
+    const char *e = std::getenv("JAS_TEST_CARD_LIMIT");
+    if (!e || !*e) return kLimit;
+    char *end = nullptr;
+    const unsigned long long v = std::strtoull(e, &end, 10);
+    return (end && *end == 0 && v > 0 && v < kLimit) ? (uint64_t)v : kLimit;
+}
+
 void check_launch(const char *what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) fail(JAS_EDEVICE, std::string("launch of ") + what + ": " + hipGetErrorString(e));
@@ -93,6 +103,8 @@ const char *jas_version(void) { return "jas 0.1 (gfx950)"; }
 int32_t jas_db_size(const jas_db *db) { return db ? db->n : -1; }
 
 int32_t jas_gram_variants(void) { return jas::gram_variants(); }
+
+uint64_t jas_card_limit(void) { return jas::card_limit(); }
 
 jas_status jas_db_stats(const jas_db *db, jas_encode_stats *stats) {
     return guard([&] {
@@ -272,6 +284,9 @@ jas_status jas_finalize(int32_t n, uint32_t flags, void *hip_stream, int32_t *B,
         if (flags & ~(uint32_t)JAS_UPPER) fail(JAS_EINVAL, "jas_finalize: only JAS_UPPER is accepted");
         if (n > 0 && (!B || !card)) fail(JAS_EINVAL, "jas_finalize: B or card is NULL");
         JAS_HOST_TIMED("jas_finalize");
+        // int32 sums over batches are exact while every summed |X_i| is below
+        // the limit (B_ij <= min(|X_i|, |X_j|)); checked before anything is written
+        check_card_limit(card, (uint32_t)n, (hipStream_t)hip_stream);
         finalize((uint32_t)n, flags & JAS_UPPER, (hipStream_t)hip_stream, B, card, den, J);
     });
 }

@@ -1325,10 +1325,11 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         std::vector<uint64_t> hc(n);
         JAS_HIP(hipMemcpyAsync(hc.data(), cardc.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
         JAS_HIP(hipStreamSynchronize(s));
+        const uint64_t lim = card_limit();
         for (int32_t i = 0; i < n; ++i)
-            if (hc[i] >= (uint64_t(1) << 31))
+            if (hc[i] >= lim)
                 fail(JAS_EOVERFLOW, "sample " + std::to_string(i) + " has " + std::to_string(hc[i]) +
-                                        " distinct IDs (limit 2^31 - 1)");
+                                        " distinct IDs (limit " + std::to_string(lim - 1) + ")");
         JAS_HIP(hipMemcpyAsync(db->card.p, cardc.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
     }
     cardc.release();

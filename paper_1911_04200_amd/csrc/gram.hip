@@ -709,6 +709,16 @@ __global__ void k_add_i64(int64_t *__restrict__ dst, const int64_t *__restrict__
     if (i < n) dst[i] += src[i];
 }
 
+// flag[0] = 1 when some card[i] >= limit.
+__global__ void k_card_check(const int64_t *__restrict__ card, uint32_t n, int64_t limit, uint32_t *flag) {
+    bool over = false;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        over |= card[i] >= limit;
+    if (__ballot(over) && lane_id() == 0) atomicOr(flag, 1u);
+}
+
+__global__ void k_zero_flag(uint32_t *flag) { *flag = 0; }
+
 __global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ card, uint32_t n, int upper,
                            uint32_t jblocks, int64_t *__restrict__ den, double *__restrict__ J) {
     const uint32_t i = blockIdx.x / jblocks;
@@ -846,6 +856,25 @@ void finalize(uint32_t n, bool upper, hipStream_t s, int32_t *B, const int64_t *
         k_finalize<<<(uint32_t)fb, 256, 0, s>>>(B, card, n, upper, jb, den, J);
     }
     check_launch("finalize");
+}
+
+void check_card_limit(const int64_t *card, uint32_t n, hipStream_t s) {
+    if (n == 0) return;
+    DevBuf<uint32_t> flag;
+    flag.alloc(1, s, nullptr, true, "overflow flag");
+    {
+        JAS_TIMED("card_check", s);
+        k_zero_flag<<<1, 1, 0, s>>>(flag.p);
+        k_card_check<<<(uint32_t)std::min<uint64_t>(div_up(n, 256), 1024), 256, 0, s>>>(card, n,
+                                                                                        (int64_t)card_limit(), flag.p);
+    }
+    check_launch("card check");
+    uint32_t h = 0;
+    JAS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    JAS_HIP(hipStreamSynchronize(s));
+    if (h)
+        fail(JAS_EOVERFLOW, "a summed |X_i| reaches " + std::to_string(card_limit()) +
+                                " distinct IDs: int32 intersections would overflow");
 }
 
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J) {

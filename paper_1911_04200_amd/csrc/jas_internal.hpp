@@ -221,6 +221,9 @@ uint32_t choose_dense_min_degree(const std::vector<uint64_t> &deg_hist, uint32_t
 // Gram and finalize (see gram.hip).
 void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *card, int64_t *den, double *J);
 void finalize(uint32_t n, bool upper, hipStream_t s, int32_t *B, const int64_t *card, int64_t *den, double *J);
+// Fails with JAS_EOVERFLOW when some card[i] >= card_limit() (one device
+// flag, read back: synchronises s).
+void check_card_limit(const int64_t *card, uint32_t n, hipStream_t s);
 uint64_t kmer_starts(const uint64_t *seq_off, int64_t n_seq, uint32_t k, std::vector<uint64_t> &kbase);
 void kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t k, bool canonical, hipStream_t s,
            uint64_t *ids);
@@ -230,6 +233,12 @@ int32_t gram_variants();
 void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint64_t NQ,
            hipStream_t s, int32_t *B, int64_t *q_card, int64_t *den, double *J);
 uint64_t query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids);
+
+// Largest |X_i| (distinct IDs of one set) the int32 intersections allow:
+// 2^31 - 1.  The environment variable JAS_TEST_CARD_LIMIT (a positive
+// integer below 2^31, read on the host at every check) lowers the bound so
+// tests can reach the overflow error with small inputs.
+uint64_t card_limit();
 
 inline uint32_t ceil_log2_u64(uint64_t v) {
     uint32_t b = 0;

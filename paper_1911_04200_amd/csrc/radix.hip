@@ -14,6 +14,7 @@
 
 #include "device_util.hpp"
 #include "jas_internal.hpp"
+#include "onesweep_index.hpp"
 
 namespace jas {
 namespace {
@@ -152,11 +153,11 @@ __global__ __launch_bounds__(kNT) void k_radix_scatter(const uint64_t *__restric
 // a 30-bit count; the caller guarantees every digit total is < 2^30.  The
 // same kernel sorts 64-bit keys (the encoder and the query path) and 32-bit
 // row-list pair words.
-constexpr uint32_t kFlagA = 1u << 30;  // the tile's own count is available
-constexpr uint32_t kFlagP = 2u << 30;  // the inclusive prefix over tiles 0..t is available
-constexpr uint32_t kValMask = (1u << 30) - 1u;
+using onesweep::kFlagA;
+using onesweep::kFlagP;
+using onesweep::kValMask;
+using onesweep::kLookWindow;  // 4 measured best of 4, 8, 16
 constexpr uint32_t kMaxSpin = 1u << 20;  // bounded wait (~0.1 s of polls), then give up and flag
-constexpr int kLookWindow = 4;           // predecessor tiles read per look-back step (4 measured best of 4, 8, 16)
 
 __device__ __forceinline__ void status_store(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -200,8 +201,8 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
         __syncthreads();
         const uint32_t tile = tile_sh;
         if (tile >= ntiles) break;  // uniform: every thread read the same ticket
-        const uint64_t t0 = (uint64_t)tile * (kOsNT * R);
-        const uint64_t c1 = min(N, t0 + (kOsNT * R));
+        const uint64_t t0 = onesweep::tile_first(tile, kOsNT * R);
+        const uint64_t c1 = onesweep::tile_end(tile, kOsNT * R, N);
         const uint64_t wb = t0 + (uint64_t)w * ((kOsNT * R) / kOsWaves);
         K key[R];
         uint32_t rank[R];
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
 #pragma unroll
             for (int k = 0; k < kOsWaves; ++k) tc += wcnt[k][tid];
             // publish the tile's count of digit tid at once
-            status_store(status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagP : kFlagA) | tc);
+            status_store(status + onesweep::status_index(tile, tid), (tile == 0 ? kFlagP : kFlagA) | tc);
         }
         // reorder the tile in LDS by digit (local offsets only)
         uint64_t tot;
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
                     uint32_t v[kLookWindow];
 #pragma unroll
                     for (int k = 0; k < kLookWindow; ++k)
-                        v[k] = j0 - k >= 0 ? status_load(status + (uint64_t)(j0 - k) * kRadix + tid) : kFlagP;
+                        v[k] = j0 - k >= 0 ? status_load(status + onesweep::status_index(j0 - k, tid)) : kFlagP;
 #pragma unroll
                     for (int k = 0; k < kLookWindow; ++k) {
                         if (found) break;
@@ -320,13 +321,13 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
                                 break;
                             }
                             __builtin_amdgcn_s_sleep(1);
-                            v[k] = status_load(status + (uint64_t)(j0 - k) * kRadix + tid);
+                            v[k] = status_load(status + onesweep::status_index(j0 - k, tid));
                         }
                         excl += v[k] & kValMask;
                         found = (v[k] & ~kValMask) == kFlagP;
                     }
                 }
-                status_store(status + (uint64_t)tile * kRadix + tid, kFlagP | ((excl + tc) & kValMask));
+                status_store(status + onesweep::status_index(tile, tid), kFlagP | ((excl + tc) & kValMask));
             }
             base[tid] = gs + excl;
         }
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
         for (uint32_t i = tid; i < cnt_tile; i += kOsNT) {
             const K k = stage[i];
             const uint32_t d = (uint32_t)(k >> shift) & mask;
-            out[base[d] + (i - tdp[d])] = k;
+            out[onesweep::out_index(base[d], i, tdp[d])] = k;
         }
         __syncthreads();  // stage, tdp, base and tile_sh are reused by the next tile
     }
@@ -446,13 +447,24 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
     JAS_HIP(hipStreamSynchronize(s));
     for (uint32_t q = 0; q < npass; ++q)
         if (hm[q] >= (uint64_t)kValMask) return false;
-    const uint64_t ntiles = div_up(N, (uint64_t)kOsNT * Rounds);
+    const uint64_t ntiles = onesweep::num_tiles(N, (uint32_t)kOsNT * Rounds);
     if (ntiles > 0xFFFFFFFFull) return false;
     // persistent blocks: two per CU (256 CUs) fit, never more than there are tiles
     const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 2);
     DevBuf<uint32_t> status, ticket;
-    status.alloc(ntiles * kRadix + 1, s, b, true, "look-back status");
+    status.alloc(onesweep::status_words(ntiles), s, b, true, "look-back status");
     ticket.alloc(1, s, b, true, "tile ticket");
+    // What the kernel's indexing relies on (see onesweep_index.hpp): the key
+    // buffers hold N keys, the tiles cover exactly [0, N), the status array
+    // has a word for every (tile, digit), every pass has a row of digit
+    // starts, and no 30-bit status count can wrap.
+    if (keys.n < N || alt.n < N || ntiles * (uint64_t)kOsNT * Rounds < N ||
+        onesweep::tile_first(ntiles - 1, kOsNT * Rounds) >= N ||
+        status.n < onesweep::status_words(ntiles) || gstart.n < (uint64_t)npass * kRadix || grid > ntiles ||
+        N > 0xFFFFFFFFull * (uint64_t)kOsNT * Rounds)
+        fail(JAS_EDEVICE, "single-pass scatter: buffer sizes do not cover its indexing");
+    for (uint32_t q = 0; q < npass; ++q)
+        if (hm[q] > kValMask) fail(JAS_EDEVICE, "single-pass scatter: a digit total exceeds the status count");
     for (uint32_t q = 0; q < npass; ++q) {
         const uint32_t bit = lo_bit + width * q;
         const uint32_t nbits = min(width, hi_bit - bit);

@@ -35,7 +35,7 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
                 -6: "JAS_EUNSUPPORTED"}
 
 # Every symbol include/jas.h declares.
-EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_gram_variants", "jas_query", "jas_query_workspace_bytes",
+EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_workspace_bytes",
                   "jas_db_size", "jas_db_stats", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
                   "jas_timing_report", "jas_trim"])
 
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.jas_query_workspace_bytes.restype = u64
     lib.jas_db_size.argtypes = [vp]
     lib.jas_db_size.restype = i32
+    lib.jas_card_limit.argtypes = []
+    lib.jas_card_limit.restype = u64
     lib.jas_gram_variants.argtypes = []
     lib.jas_gram_variants.restype = i32
     lib.jas_db_stats.argtypes = [vp, ctypes.POINTER(jas_encode_stats)]
@@ -218,6 +220,10 @@ def jas_query_workspace_bytes(db, nq: int, n_q_ids: int) -> int:
 
 def jas_db_size(db) -> int:
     return int(load().jas_db_size(_h(db)))
+
+
+def jas_card_limit() -> int:
+    return int(load().jas_card_limit())
 
 
 def jas_gram_variants() -> int:

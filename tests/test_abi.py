@@ -111,3 +111,14 @@ def test_finalize_argument_checks():
     assert "JAS_UPPER" in jas.jas_last_error()
     assert lib.jas_finalize(4, 0, None, None, None, None, None) == jas.JAS_EINVAL
     assert lib.jas_finalize(0, 0, None, None, None, None, None) == jas.JAS_OK
+
+
+def test_card_limit_and_its_test_hook(monkeypatch):
+    """2^31 by default; JAS_TEST_CARD_LIMIT lowers it, and values that are not
+    a positive integer below 2^31 are ignored."""
+    monkeypatch.delenv("JAS_TEST_CARD_LIMIT", raising=False)
+    assert jas.jas_card_limit() == 1 << 31
+    for value, want in [("100", 100), ("1", 1), (str((1 << 31) - 1), (1 << 31) - 1), (str(1 << 31), 1 << 31),
+                        ("0", 1 << 31), ("-5", 1 << 31), ("12x", 1 << 31), ("", 1 << 31)]:
+        monkeypatch.setenv("JAS_TEST_CARD_LIMIT", value)
+        assert jas.jas_card_limit() == want, value

@@ -90,3 +90,43 @@ def test_streamed_graph_neighbourhoods():
     res = stream.all_pairs_streamed(ids, off, 10, 2, batch_bits=8, upper=True)
     torch.cuda.synchronize()
     check(host(res), ref, True)
+
+
+def test_overflow_is_reported_by_encode_and_by_finalize(monkeypatch):
+    """With the set-size bound lowered to 100 (test hook): a set of 150
+    distinct IDs is refused by jas_encode, and the same set cut into two ID
+    ranges of 75 each encodes part by part but is refused by jas_finalize,
+    whose summed |X_i| reaches the bound."""
+    monkeypatch.setenv("JAS_TEST_CARD_LIMIT", "100")
+    assert cabi.jas_card_limit() == 100
+    big = np.arange(0, 300, 2, dtype=np.uint64)  # 150 distinct IDs
+    sets = [big, np.arange(0, 40, dtype=np.uint64), np.array([1, 2, 3, 299], dtype=np.uint64)]
+    off = np.zeros(4, np.uint64)
+    off[1:] = np.cumsum([x.size for x in sets])
+    ids = np.concatenate(sets)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
+    with pytest.raises(cabi.JasError) as e:
+        cabi.jas_encode(d(ids), d(off), 3, cabi.jas_encode_opts(9, 0, 0, 0, 0), None)
+    assert e.value.status == cabi.JAS_EOVERFLOW
+    B = torch.zeros(9, dtype=torch.int32, device="cuda")
+    card = torch.zeros(3, dtype=torch.int64, device="cuda")
+    for lo, hi in [(0, 150), (150, 300)]:  # two ID ranges: 75 IDs of the big set in each
+        part = [x[(x >= lo) & (x < hi)] for x in sets]
+        po = np.zeros(4, np.uint64)
+        po[1:] = np.cumsum([x.size for x in part])
+        db, st = cabi.jas_encode(d(np.concatenate(part)), d(po), 3, cabi.jas_encode_opts(9, 0, 0, 0, 0), None)
+        cabi.jas_gram(db, cabi.JAS_ACCUMULATE, None, B, card)
+        db.close()
+    torch.cuda.synchronize()
+    assert card.cpu().tolist() == [150, 40, 4]
+    with pytest.raises(cabi.JasError) as e:
+        cabi.jas_finalize(3, 0, None, B, card)
+    assert e.value.status == cabi.JAS_EOVERFLOW
+    # below the bound the same sums finalize
+    monkeypatch.setenv("JAS_TEST_CARD_LIMIT", "151")
+    den = torch.empty(9, dtype=torch.int64, device="cuda")
+    cabi.jas_finalize(3, 0, None, B, card, den)
+    torch.cuda.synchronize()
+    ref = oracle.all_pairs(ids, off)
+    assert np.array_equal(B.cpu().numpy().reshape(3, 3), ref["inter"])
+    assert np.array_equal(den.cpu().numpy().reshape(3, 3), ref["union"])
