@@ -228,6 +228,24 @@ int32_t jas_gram_variants(void);
 jas_status jas_query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq,
                      uint32_t flags, void *hip_stream, int32_t *B, int64_t *q_card, int64_t *den, double *J);
 
+/*
+ * jas_query_noalloc -- jas_query for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as jas_query, with
+ * device pointers only (flags must be 0), but every temporary comes from a
+ * fixed workspace of 136 MiB that the library holds on each device it runs
+ * on until the process ends: no device memory is allocated or freed.  It
+ * takes at most 65,536 query sets and 2^23 query IDs (entries, repeats
+ * included) per call; larger requests fail with JAS_ENOMEM before any work
+ * is enqueued.  Calls share the workspace, so the library serialises them
+ * (a lock per process) and each returns only after its work on hip_stream
+ * has finished (synchronises hip_stream); the workspace keeps the last
+ * call's contents, and everything that must start at zero is cleared by the
+ * call itself.
+ */
+jas_status jas_query_noalloc(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq,
+                             uint32_t flags, void *hip_stream, int32_t *B, int64_t *q_card, int64_t *den, double *J);
+
 /* Device bytes jas_query allocates for nq queries with n_q_ids entries in total
  * (for admission control by an HBM budget). */
 uint64_t jas_query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids);

@@ -374,6 +374,41 @@ jas_status jas_query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_
     });
 }
 
+jas_status jas_query_noalloc(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq,
+                             uint32_t flags, void *hip_stream, int32_t *B, int64_t *q_card, int64_t *den,
+                             double *J) {
+    return guard([&] {
+        if (!db) fail(JAS_EINVAL, "jas_query_noalloc: db is NULL");
+        if (!(db->flags & JAS_KEEP_IDS)) fail(JAS_EINVAL, "jas_query_noalloc: db was encoded without JAS_KEEP_IDS");
+        if (flags != 0) fail(JAS_EINVAL, "jas_query_noalloc: takes no flags (device pointers only)");
+        if (nq < 0) fail(JAS_EINVAL, "jas_query_noalloc: nq < 0");
+        if (nq > 0 && !q_offsets) fail(JAS_EINVAL, "jas_query_noalloc: q_offsets is NULL");
+        if (nq > 0 && db->n > 0 && !B) fail(JAS_EINVAL, "jas_query_noalloc: B is NULL");
+        const uint32_t qbits = ceil_log2_u64((uint64_t)std::max<int32_t>(nq, 1));
+        if (db->U + qbits > 64) fail(JAS_EINVAL, "jas_query_noalloc: universe_bits + ceil(log2 nq) exceeds 64");
+        if (nq > noalloc_max_queries())
+            fail(JAS_ENOMEM, "jas_query_noalloc: " + std::to_string(nq) + " query sets exceed the fixed workspace (at most " +
+                                 std::to_string(noalloc_max_queries()) + ")");
+        if (nq == 0) return;
+        hipStream_t s = (hipStream_t)hip_stream;
+        const std::vector<uint64_t> hoff = host_offsets(q_offsets, nq, false, s, "jas_query_noalloc");
+        const uint64_t NQ = hoff[nq];
+        if (NQ > noalloc_max_ids())
+            fail(JAS_ENOMEM, "jas_query_noalloc: " + std::to_string(NQ) + " query IDs exceed the fixed workspace (at most " +
+                                 std::to_string(noalloc_max_ids()) + ")");
+        if (NQ > 0 && !q_ids) fail(JAS_EINVAL, "jas_query_noalloc: q_ids is NULL");
+        std::unique_lock<std::mutex> lk;
+        Arena ar = noalloc_arena(lk);
+        try {
+            query(db, q_ids, q_offsets, nq, NQ, s, B, q_card, den, J, &ar);
+        } catch (...) {
+            (void)hipStreamSynchronize(s);  // the workspace is free again only when its kernels are done
+            throw;
+        }
+        JAS_HIP(hipStreamSynchronize(s));
+    });
+}
+
 uint64_t jas_query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids) {
     if (!db || nq < 0) return 0;
     return query_workspace_bytes(db, nq, n_q_ids);

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "jas.h"
@@ -79,6 +81,7 @@ struct DevBuf {
     size_t n = 0;
     Budget *budget = nullptr;
     bool owned_by_db = false;  // freed by jas_db_free after a device synchronisation
+    bool external = false;     // memory owned elsewhere (an Arena): never freed here
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -86,10 +89,15 @@ struct DevBuf {
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; n = o.n; budget = o.budget; owned_by_db = o.owned_by_db;
-            o.p = nullptr; o.n = 0;
+            p = o.p; n = o.n; budget = o.budget; owned_by_db = o.owned_by_db; external = o.external;
+            o.p = nullptr; o.n = 0; o.external = false;
         }
         return *this;
+    }
+    // view of count elements at ptr (not owned)
+    void wrap(T *ptr, size_t count) {
+        release();
+        p = ptr; n = count; budget = nullptr; owned_by_db = false; external = true;
     }
     ~DevBuf() { release(); }
     // db_owned = false: a temporary of the call (stream-ordered reuse);
@@ -109,14 +117,45 @@ struct DevBuf {
         owned_by_db = !temporary;
     }
     void release() {
-        if (p) {
+        if (p && !external) {
             cache_free(p, owned_by_db);
             if (budget) budget->give((n ? n : 1) * sizeof(T));
         }
-        p = nullptr; n = 0;
+        p = nullptr; n = 0; external = false;
     }
     size_t bytes() const { return n * sizeof(T); }
 };
+
+// Exchange two buffers of one kind (the two halves of a ping-pong sort).
+template <class T>
+void swap_bufs(DevBuf<T> &a, DevBuf<T> &b) {
+    std::swap(a.p, b.p);
+    std::swap(a.n, b.n);
+    std::swap(a.external, b.external);
+}
+
+// A fixed region of device memory handed out front to back (256-byte
+// aligned pieces); used instead of the cache by calls that must not
+// allocate.  Exceeding it fails with JAS_ENOMEM before the piece is used.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    template <class T>
+    void take(DevBuf<T> &b, size_t count, const char *what) {
+        const size_t bytes = (((count ? count : 1) * sizeof(T)) + 255) & ~size_t(255);
+        if (used + bytes > cap)
+            fail(JAS_ENOMEM, std::string("fixed workspace of ") + std::to_string(cap) + " bytes too small for " + what);
+        b.wrap(reinterpret_cast<T *>(base + used), count);
+        used += bytes;
+    }
+};
+
+// A temporary of a call: from the arena when one is given, else from the cache.
+template <class T>
+void temp_buf(DevBuf<T> &b, size_t count, hipStream_t s, Budget *budget, Arena *ar, const char *what) {
+    if (ar) ar->take(b, count, what);
+    else b.alloc(count, s, budget, true, what);
+}
 
 
 
@@ -169,7 +208,7 @@ struct RadixWork {
     DevBuf<uint64_t> offs, tmp;
 };
 void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
-                    RadixWork &w, hipStream_t s, Budget *b);
+                    RadixWork &w, hipStream_t s, Budget *b, Arena *ar = nullptr);
 
 // Single-pass-per-digit sort (decoupled look-back) of keys whose digit totals
 // are known: ghist = kGhistReplicas copies of [kMaxPasses][256] totals; pass q
@@ -181,12 +220,12 @@ constexpr uint32_t kMaxPasses = 8;
 constexpr uint32_t kGhistReplicas = 32;
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
                          uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
-                         hipStream_t s, Budget *b);
+                         hipStream_t s, Budget *b, Arena *ar = nullptr);
 bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,
                              uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
-                             hipStream_t s, Budget *b);
+                             hipStream_t s, Budget *b, Arena *ar = nullptr);
 // Allocates w for N keys; returns the number of chunks (counts is [256][chunks]).
-uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b);
+uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b, Arena *ar = nullptr);
 uint64_t radix_work_bytes(uint64_t N);
 
 // How the ID bits are sorted.  Only the top `top_bits` of the U ID bits are
@@ -230,9 +269,17 @@ void kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t
 int32_t gram_variants();
 
 // Query (see query.hip).
+// ar: take every temporary from this region instead of the cache (nothing is allocated).
 void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint64_t NQ,
-           hipStream_t s, int32_t *B, int64_t *q_card, int64_t *den, double *J);
+           hipStream_t s, int32_t *B, int64_t *q_card, int64_t *den, double *J, Arena *ar = nullptr);
 uint64_t query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids);
+
+// The fixed workspace of jas_query_noalloc (noalloc.hip): the largest query
+// it takes, and an arena over the current device's copy, returned with the
+// lock that serialises its users held in lk.
+uint64_t noalloc_max_ids();
+int32_t noalloc_max_queries();
+Arena noalloc_arena(std::unique_lock<std::mutex> &lk);
 
 // Largest |X_i| (distinct IDs of one set) the int32 intersections allow:
 // 2^31 - 1.  The environment variable JAS_TEST_CARD_LIMIT (a positive

@@ -155,7 +155,7 @@ uint64_t query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids) {
 }
 
 void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint64_t NQ,
-           hipStream_t s, int32_t *B, int64_t *q_card, int64_t *den, double *J) {
+           hipStream_t s, int32_t *B, int64_t *q_card, int64_t *den, double *J, Arena *ar) {
     const uint32_t n = (uint32_t)db->n;
     const uint32_t U = db->U;
     const uint32_t qbits = ceil_log2_u64((uint64_t)std::max<int32_t>(nq, 1));
@@ -170,7 +170,7 @@ void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, i
         check_launch("zero B");
     }
     DevBuf<unsigned long long> qc;
-    qc.alloc(nq, s, nullptr, true, "query card");
+    temp_buf(qc, nq, s, nullptr, ar, "query card");
     {
         JAS_TIMED("fill_u64", s);
         k_fill_u64<<<(uint32_t)div_up(nq, 256), 256, 0, s>>>(qc.p, nq);
@@ -179,9 +179,9 @@ void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, i
     if (NQ > 0) {
         DevBuf<uint64_t> keys, alt;
         DevBuf<uint32_t> err;
-        keys.alloc(NQ, s, nullptr, true, "query keys");
-        alt.alloc(NQ, s, nullptr, true, "query keys");
-        err.alloc(1, s, nullptr, true, "query error flag");
+        temp_buf(keys, NQ, s, nullptr, ar, "query keys");
+        temp_buf(alt, NQ, s, nullptr, ar, "query keys");
+        temp_buf(err, 1, s, nullptr, ar, "query error flag");
         {
             JAS_TIMED("fill_u32", s);
             k_fill_u32<<<1, 64, 0, s>>>(err.p, 1);
@@ -189,7 +189,7 @@ void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, i
         const uint64_t kb = div_up(NQ, 4096);
         const uint32_t kbits = U + qbits, npass = (kbits + 7) / 8;
         DevBuf<unsigned long long> ghist;
-        ghist.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, nullptr, true, "query digit totals");
+        temp_buf(ghist, (uint64_t)kGhistReplicas * kMaxPasses * 256, s, nullptr, ar, "query digit totals");
         {
             JAS_TIMED("fill_u64", s);
             k_fill_u64<<<64, 256, 0, s>>>(ghist.p, (uint64_t)kGhistReplicas * kMaxPasses * 256);
@@ -205,7 +205,7 @@ void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, i
         if (herr) fail(JAS_EINVAL, "a query ID is >= 2^universe_bits");
         // single-pass scatters; if one cannot run (or its look-back gave up),
         // the keys are rebuilt and sorted with per-pass histograms instead
-        bool sorted = radix_sort_onesweep(keys, alt, NQ, 0, kbits, 8, ghist.p, err.p, s, nullptr);
+        bool sorted = radix_sort_onesweep(keys, alt, NQ, 0, kbits, 8, ghist.p, err.p, s, nullptr, ar);
         if (sorted) {
             JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
@@ -219,13 +219,13 @@ void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, i
             k_qkeys<<<(uint32_t)kb, kNT, 0, s>>>(q_ids, q_offsets, nq, NQ, U, keys.p, err.p, 0, nullptr);
             check_launch("query keys");
             RadixWork rw;
-            radix_sort_u64(keys, alt, NQ, 0, kbits, rw, s, nullptr);
+            radix_sort_u64(keys, alt, NQ, 0, kbits, rw, s, nullptr, ar);
         }
         alt.release();
         DevBuf<uint64_t> nb, bo, tmp;
-        nb.alloc(nq, s, nullptr, true, "query blocks");
-        bo.alloc(nq + 1, s, nullptr, true, "query blocks");
-        tmp.alloc(scan_tmp_elems(nq), s, nullptr, true, "scan scratch");
+        temp_buf(nb, nq, s, nullptr, ar, "query blocks");
+        temp_buf(bo, nq + 1, s, nullptr, ar, "query blocks");
+        temp_buf(tmp, scan_tmp_elems(nq), s, nullptr, ar, "scan scratch");
         {
             JAS_TIMED("qblocks", s);
             k_qblocks<<<(uint32_t)div_up(nq, 256), 256, 0, s>>>(q_offsets, nq, nb.p);

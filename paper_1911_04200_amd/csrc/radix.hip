@@ -386,21 +386,21 @@ uint64_t radix_work_bytes(uint64_t N) {
     return len * 4 + (len + 1) * 8 + scan_tmp_elems(len) * 8;
 }
 
-uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b) {
+uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b, Arena *ar) {
     const uint64_t nchunks = div_up(std::max<uint64_t>(N, 1), kChunk);
     if (nchunks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "radix sort: too many keys");
     const uint64_t len = (uint64_t)kRadix * nchunks;
-    if (w.counts.n < len) w.counts.alloc(len, s, b, true, "radix counts");
-    if (w.offs.n < len + 1) w.offs.alloc(len + 1, s, b, true, "radix offsets");
+    if (w.counts.n < len) temp_buf(w.counts, len, s, b, ar, "radix counts");
+    if (w.offs.n < len + 1) temp_buf(w.offs, len + 1, s, b, ar, "radix offsets");
     const size_t tl = scan_tmp_elems(len);
-    if (w.tmp.n < tl) w.tmp.alloc(tl, s, b, true, "radix scan scratch");
+    if (w.tmp.n < tl) temp_buf(w.tmp, tl, s, b, ar, "radix scan scratch");
     return nchunks;
 }
 
 void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit,
-                    RadixWork &w, hipStream_t s, Budget *b) {
+                    RadixWork &w, hipStream_t s, Budget *b, Arena *ar) {
     if (N <= 1 || hi_bit <= lo_bit) return;
-    const uint64_t nchunks = radix_prepare(w, N, s, b);
+    const uint64_t nchunks = radix_prepare(w, N, s, b, ar);
     const uint64_t len = (uint64_t)kRadix * nchunks;
     for (uint32_t bit = lo_bit; bit < hi_bit; bit += 8) {
         const uint32_t nbits = min(8u, hi_bit - bit);
@@ -417,8 +417,7 @@ void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, u
                                                              (uint32_t)nchunks);
         }
         check_launch("radix scatter");
-        std::swap(keys.p, alt.p);
-        std::swap(keys.n, alt.n);
+        swap_bufs(keys, alt);
     }
 }
 
@@ -429,14 +428,15 @@ namespace jas {
 namespace {
 template <class K, int Rounds, bool Table>
 bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit, uint32_t width,
-                   const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b, const char *name) {
+                   const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b, Arena *ar,
+                   const char *name) {
     if (N <= 1 || hi_bit <= lo_bit) return true;
     if (width < 1 || width > 8) return false;
     const uint32_t npass = (hi_bit - lo_bit + width - 1) / width;
     if (npass > kMaxPasses) return false;
     DevBuf<uint64_t> gstart, maxima;
-    gstart.alloc((uint64_t)kMaxPasses * kRadix, s, b, true, "digit starts");
-    maxima.alloc(kMaxPasses, s, b, true, "digit maxima");
+    temp_buf(gstart, (uint64_t)kMaxPasses * kRadix, s, b, ar, "digit starts");
+    temp_buf(maxima, kMaxPasses, s, b, ar, "digit maxima");
     {
         JAS_TIMED("digit_starts", s);
         k_digit_starts<<<1, kNT, 0, s>>>(ghist, npass, gstart.p, maxima.p);
@@ -452,8 +452,8 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
     // persistent blocks: two per CU (256 CUs) fit, never more than there are tiles
     const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 2);
     DevBuf<uint32_t> status, ticket;
-    status.alloc(onesweep::status_words(ntiles), s, b, true, "look-back status");
-    ticket.alloc(1, s, b, true, "tile ticket");
+    temp_buf(status, onesweep::status_words(ntiles), s, b, ar, "look-back status");
+    temp_buf(ticket, 1, s, b, ar, "tile ticket");
     // What the kernel's indexing relies on (see onesweep_index.hpp): the key
     // buffers hold N keys, the tiles cover exactly [0, N), the status array
     // has a word for every (tile, digit), every pass has a row of digit
@@ -481,8 +481,7 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
                                                   ticket.p, (uint32_t)ntiles, err);
         }
         check_launch("radix scatter (look-back)");
-        std::swap(keys.p, alt.p);
-        std::swap(keys.n, alt.n);
+        swap_bufs(keys, alt);
     }
     return true;
 }
@@ -495,15 +494,15 @@ constexpr bool kU64Table = false;
 
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
                          uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
-                         hipStream_t s, Budget *b) {
-    return onesweep_sort<uint64_t, kU64Rounds, kU64Table>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b,
+                         hipStream_t s, Budget *b, Arena *ar) {
+    return onesweep_sort<uint64_t, kU64Rounds, kU64Table>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, ar,
                                                           "radix_onesweep");
 }
 
 bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,
                              uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
-                             hipStream_t s, Budget *b) {
-    return onesweep_sort<uint32_t, 16, true>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, "pair_sort");
+                             hipStream_t s, Budget *b, Arena *ar) {
+    return onesweep_sort<uint32_t, 16, true>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, ar, "pair_sort");
 }
 
 }  // namespace jas

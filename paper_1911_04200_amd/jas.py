@@ -35,7 +35,7 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
                 -6: "JAS_EUNSUPPORTED"}
 
 # Every symbol include/jas.h declares.
-EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_workspace_bytes",
+EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_noalloc", "jas_query_workspace_bytes",
                   "jas_db_size", "jas_db_stats", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
                   "jas_timing_report", "jas_trim"])
 
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.jas_gram.restype = ctypes.c_int
     lib.jas_query.argtypes = [vp, vp, vp, i32, u32, vp, vp, vp, vp, vp]
     lib.jas_query.restype = ctypes.c_int
+    lib.jas_query_noalloc.argtypes = [vp, vp, vp, i32, u32, vp, vp, vp, vp, vp]
+    lib.jas_query_noalloc.restype = ctypes.c_int
     lib.jas_query_workspace_bytes.argtypes = [vp, i32, u64]
     lib.jas_query_workspace_bytes.restype = u64
     lib.jas_db_size.argtypes = [vp]
@@ -212,6 +214,11 @@ def jas_query(db, q_ids, q_offsets, nq: int, flags: int, stream, B, q_card=None,
     s = None if (flags & JAS_HOST_PTRS and stream is None) else _stream(stream)
     _check(lib.jas_query(_h(db), _ptr(q_ids), _ptr(q_offsets), nq, flags, s, _ptr(B), _ptr(q_card), _ptr(den),
                          _ptr(J)))
+
+
+def jas_query_noalloc(db, q_ids, q_offsets, nq: int, flags: int, stream, B, q_card=None, den=None, J=None):
+    _check(load().jas_query_noalloc(_h(db), _ptr(q_ids), _ptr(q_offsets), nq, flags, _stream(stream), _ptr(B),
+                                    _ptr(q_card), _ptr(den), _ptr(J)))
 
 
 def jas_query_workspace_bytes(db, nq: int, n_q_ids: int) -> int:
