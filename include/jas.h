@@ -70,6 +70,9 @@ typedef struct {
                                   (cost model of the two Gram paths); 2 = pack every shared row */
     uint32_t flags;            /* JAS_HOST_PTRS, JAS_KEEP_IDS */
     uint64_t hbm_budget_bytes; /* cap on device memory this call may hold at once; 0 = none */
+    uint32_t word_bits;        /* b, rows per bitmask word (Sec. III-B): 32 or 64; 0 = 64.  B does
+                                  not depend on it (every word's popcount sums its rows) */
+    uint32_t reserved;         /* 0 */
 } jas_encode_opts;
 
 typedef struct {
@@ -80,12 +83,16 @@ typedef struct {
     uint64_t n_packed_rows; /* rows bit-packed (degree >= dense_min_degree) */
     uint64_t n_list_rows;   /* rows kept as row lists (2 <= degree < dense_min_degree) */
     uint64_t n_batches;     /* row batches holding at least one packed row */
-    uint64_t n_word_rows;   /* H: 64-row word rows of the packed matrix */
+    uint64_t n_word_rows;   /* h: word rows of b rows each (b = word_bits) over all batches */
     uint64_t nnz_words;     /* nonzero packed words */
     uint64_t word_pairs_F;  /* sum over word rows of z(z+1)/2, z = nonzero words in the row */
     uint64_t list_pairs;    /* sum over list rows of d(d-1)/2 (pair increments of the list path) */
     uint64_t device_bytes;  /* device memory the db holds */
     uint64_t dense_min_degree; /* the threshold used (chosen by the library when opts asked for 0) */
+    uint64_t word_bits;     /* b used (32 or 64) */
+    uint64_t w_rows;        /* rows of the stored word array (JAS_DB_WORDS): h for b = 64, ceil(h/2) for 32 */
+    uint64_t w_stride;      /* 64-bit elements per stored row (n rounded up to a multiple of 128) */
+    uint64_t n_list_pairs;  /* entries of JAS_DB_LIST_PAIRS */
 } jas_encode_stats;
 
 /*
@@ -255,6 +262,38 @@ int32_t jas_db_size(const jas_db *db);
 
 /* Statistics recorded by jas_encode.  Returns EINVAL for NULL arguments. */
 jas_status jas_db_stats(const jas_db *db, jas_encode_stats *stats);
+
+/*
+ * jas_db_part_size / jas_db_read -- the db's arrays, read back to the host
+ * (for checking or keeping an encoding; the layout is that of this build).
+ *  JAS_DB_CARD          int64[n]: |X_i| (the column sums of Eq. (4)).
+ *  JAS_DB_WORDS         uint64[w_rows * w_stride]: the bitmask words (Sec. III-B) of
+ *                       the rows shared by >= dense_min_degree sets, batch by batch
+ *                       (Eq. (3)) and in ID order inside a batch; packed row p of a
+ *                       batch is bit p mod b of word row floor(p / b) of that batch,
+ *                       and word row r of all batches is element row r (b = 64) or the
+ *                       low (r even) / high (r odd) half of element row r/2 (b = 32);
+ *                       element (row, i) is at row * w_stride + i; columns >= n are 0.
+ *  JAS_DB_LIST_PAIRS    uint32: for every row shared by 2..dense_min_degree-1 sets
+ *                       (the row lists) and every pair a < b of its sets, the word
+ *                       (a << 16) | b, ordered by a (kept when n <= 10240).
+ *  JAS_DB_LIST_PTR, JAS_DB_LIST_SAMPLES  uint64 / uint32: the same rows as a CSR of
+ *                       their sets, ascending (kept instead of the pairs when n > 10240).
+ *  JAS_DB_KEYS          uint64: with JAS_KEEP_IDS, every distinct (ID, sample) as
+ *                       (ID << ceil(log2 n)) | sample, ascending.
+ * jas_db_part_size returns the part's element count (0 for an unknown part or a
+ * NULL db).  jas_db_read copies count elements from element `first` into
+ * host_out (synchronous, on the db's device); EINVAL for a range outside the
+ * part.  Rows with a single set are not stored: they add only to |X_i|.
+ */
+#define JAS_DB_CARD 0
+#define JAS_DB_WORDS 1
+#define JAS_DB_LIST_PAIRS 2
+#define JAS_DB_LIST_PTR 3
+#define JAS_DB_LIST_SAMPLES 4
+#define JAS_DB_KEYS 5
+uint64_t jas_db_part_size(const jas_db *db, int32_t part);
+jas_status jas_db_read(const jas_db *db, int32_t part, uint64_t first, uint64_t count, void *host_out);
 
 /* Frees the db and its device memory (synchronises the device first). NULL is a no-op. */
 void jas_db_free(jas_db *db);

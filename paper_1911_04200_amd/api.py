@@ -14,13 +14,13 @@ def _dev_u64(x, device):
 
 
 def encode(ids, offsets, universe_bits: int, batch_bits: int = 0, dense_min_degree: int = 0, keep_ids: bool = False,
-           hbm_budget_bytes: int = 0, device="cuda", stream=None):
+           hbm_budget_bytes: int = 0, word_bits: int = 64, device="cuda", stream=None):
     """Encode n CSR sets (device tensors, or anything torch.as_tensor accepts)."""
     ids_t = _dev_u64(ids, device)
     off_t = _dev_u64(offsets, device)
     n = off_t.numel() - 1
     opts = jas_encode_opts(universe_bits, batch_bits, dense_min_degree, JAS_KEEP_IDS if keep_ids else 0,
-                           hbm_budget_bytes)
+                           hbm_budget_bytes, word_bits)
     return jas_encode(ids_t, off_t, n, opts, stream)
 
 

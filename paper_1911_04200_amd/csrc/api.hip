@@ -113,6 +113,47 @@ jas_status jas_db_stats(const jas_db *db, jas_encode_stats *stats) {
     });
 }
 
+uint64_t jas_db_part_size(const jas_db *db, int32_t part) {
+    if (!db) return 0;
+    switch (part) {
+        case JAS_DB_CARD: return (uint64_t)db->n;
+        case JAS_DB_WORDS: return db->H * db->stats.w_stride;
+        case JAS_DB_LIST_PAIRS: return db->n_lpairs;
+        case JAS_DB_LIST_PTR: return db->n_lpairs || db->n_list == 0 ? 0 : db->n_list + 1;
+        case JAS_DB_LIST_SAMPLES: return db->n_lpairs ? 0 : db->list_nnz;
+        case JAS_DB_KEYS: return (db->flags & JAS_KEEP_IDS) ? db->n_keys : 0;
+        default: return 0;
+    }
+}
+
+jas_status jas_db_read(const jas_db *db, int32_t part, uint64_t first, uint64_t count, void *host_out) {
+    return guard([&] {
+        if (!db) fail(JAS_EINVAL, "jas_db_read: db is NULL");
+        if (part < JAS_DB_CARD || part > JAS_DB_KEYS) fail(JAS_EINVAL, "jas_db_read: unknown part");
+        const uint64_t size = jas_db_part_size(db, part);
+        if (first > size || count > size - first) fail(JAS_EINVAL, "jas_db_read: range outside the part");
+        if (count == 0) return;
+        if (!host_out) fail(JAS_EINVAL, "jas_db_read: host_out is NULL");
+        const void *src = nullptr;
+        size_t elem = 8;
+        switch (part) {
+            case JAS_DB_CARD: src = db->card.p; break;
+            case JAS_DB_WORDS: src = db->W.p; break;
+            case JAS_DB_LIST_PAIRS: src = db->pairs.p; elem = 4; break;
+            case JAS_DB_LIST_PTR: src = db->list_ptr.p; break;
+            case JAS_DB_LIST_SAMPLES: src = db->list_smp.p; elem = 4; break;
+            default: src = db->keys.p; break;
+        }
+        int cur = 0;
+        JAS_HIP(hipGetDevice(&cur));
+        if (cur != db->device) JAS_HIP(hipSetDevice(db->device));
+        const hipError_t e = hipMemcpy(host_out, static_cast<const char *>(src) + first * elem, count * elem,
+                                       hipMemcpyDeviceToHost);
+        if (cur != db->device) (void)hipSetDevice(cur);
+        check_hip(e, "jas_db_read: hipMemcpy");
+    });
+}
+
 void jas_db_free(jas_db *db) {
     if (!db) return;
     int cur = 0;
@@ -141,6 +182,8 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
         if (n > 0 && !offsets) fail(JAS_EINVAL, "jas_encode: offsets is NULL");
         const uint32_t U = opts->universe_bits;
         if (U < 1 || U > 63) fail(JAS_EINVAL, "jas_encode: universe_bits must be in 1..63");
+        if (opts->word_bits != 0 && opts->word_bits != 32 && opts->word_bits != 64)
+            fail(JAS_EINVAL, "jas_encode: word_bits must be 32, 64 or 0 (= 64)");
         const uint32_t sbits = ceil_log2_u64((uint64_t)std::max<int32_t>(n, 1));
         if (U + sbits > 64) fail(JAS_EINVAL, "jas_encode: universe_bits + ceil(log2 n) exceeds 64");
         const bool host = opts->flags & JAS_HOST_PTRS;
@@ -163,6 +206,7 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
         db->batch_bits = (opts->batch_bits == 0 || opts->batch_bits >= U) ? U : opts->batch_bits;
         db->dmin = opts->dense_min_degree == 0 ? 0u : std::max<uint32_t>(2u, opts->dense_min_degree);
         db->flags = opts->flags;
+        db->word_bits = opts->word_bits == 32 ? 32 : 64;
         // one budget for the call: temporaries (tb) and the db's own buffers
         Budget tb;
         tb.limit = opts->hbm_budget_bytes;

@@ -743,30 +743,39 @@ __global__ void k_batch_start(const uint32_t *bs, const uint64_t *bpos, uint64_t
         if (bs[q]) bq[bpos[q]] = q;
 }
 
-__global__ void k_batch_words(const uint64_t *bq, uint64_t nb, uint64_t *nw) {
+// Word rows of b = wb bits (32 or 64) per batch: ceil(rows / b).
+__global__ void k_batch_words(const uint64_t *bq, uint64_t nb, uint32_t wb, uint64_t *nw) {
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x)
-        nw[b] = (bq[b + 1] - bq[b] + 63) / 64;
+        nw[b] = (bq[b + 1] - bq[b] + wb - 1) / wb;
 }
 
-__global__ void k_word_rows(uint64_t QD, const uint64_t *bpos, const uint64_t *bq, const uint64_t *wbase,
+// Word row w (of wb bits) holds packed rows [wq0[w], wq1[w]): bit p % wb of
+// row p / wb of its batch.
+__global__ void k_word_rows(uint64_t QD, const uint64_t *bpos, const uint64_t *bq, const uint64_t *wbase, uint32_t wb,
                             uint64_t *wq0, uint64_t *wq1) {
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t b = bpos[q + 1] - 1;  // batch of packed row q
         const uint64_t p = q - bq[b];        // position inside the batch
-        if ((p & 63) == 0) {
-            const uint64_t w = wbase[b] + p / 64;
+        if (p % wb == 0) {
+            const uint64_t w = wbase[b] + p / wb;
             wq0[w] = q;
-            wq1[w] = min(q + 64, bq[b + 1]);
+            wq1[w] = min(q + wb, bq[b + 1]);
         }
     }
 }
 
-// One block per word row: OR the bits of its <= 64 rows into an LDS row of
-// words and write it out.  Wave 0 loads the rows' list starts and degrees and
-// scans them, then all threads walk the word row's (row, sample) pairs in
-// parallel (consecutive threads read consecutive samples of a row).
-__global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t ldw, uint64_t H,
-                                               const uint64_t *__restrict__ wq0, const uint64_t *__restrict__ wq1,
+// One block per 64-bit row of W: OR the bits of its <= 64 rows into an LDS
+// row of words and write it out.  With b = 64 a row of W is one word row;
+// with b = 32 it holds word rows 2w (bits 0..31) and 2w + 1 (bits 32..63),
+// each a 32-bit word per column, so the Gram kernels read both as one 64-bit
+// step (the AND + popcount, or the dot product, of a 64-bit element is the
+// sum over its two halves).  Wave 0 loads the rows' list starts and degrees
+// (lane t: the row of bit t) and scans them, then all threads walk the rows'
+// (row, sample) pairs in parallel (consecutive threads read consecutive
+// samples of a row).  Hw = word rows of b bits.
+__global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t Hw,
+                                               uint32_t wb, const uint64_t *__restrict__ wq0,
+                                               const uint64_t *__restrict__ wq1,
                                                const uint64_t *__restrict__ Drow,
                                                const uint64_t *__restrict__ row_ptr,
                                                const uint32_t *__restrict__ row_deg,
@@ -775,15 +784,27 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
     extern __shared__ unsigned long long lw[];
     __shared__ uint64_t rstart[kWave + 1];  // exclusive prefix of the rows' degrees
     __shared__ uint64_t rbase[kWave];       // first pair of each row in S
-    __shared__ uint32_t zsh;
+    __shared__ uint32_t zsh[2];  // nonzero words of the row (b = 32: of each half)
     const uint32_t tid = threadIdx.x, lane = lane_id();
     unsigned long long nnz_acc = 0, f_acc = 0;  // this block's totals (thread 0)
     for (uint64_t w = blockIdx.x; w < H; w += gridDim.x) {
         if (tid < kWave) {
-            const uint64_t q0 = wq0[w], q1 = wq1[w];
+            uint64_t q0 = 0, q1 = 0, qi = 0;  // this lane's row: qi, if below q1
+            if (wb == 64) {
+                q0 = wq0[w];
+                q1 = wq1[w];
+                qi = q0 + lane;
+            } else {
+                const uint64_t ww = 2 * w + (lane >> 5);
+                if (ww < Hw) {
+                    q0 = wq0[ww];
+                    q1 = wq1[ww];
+                }
+                qi = q0 + (lane & 31);
+            }
             uint64_t base = 0, deg = 0;
-            if (q0 + lane < q1) {
-                const uint64_t r = Drow[q0 + lane];
+            if (qi < q1) {
+                const uint64_t r = Drow[qi];
                 base = row_ptr[r];
                 deg = row_deg[r];
             }
@@ -792,7 +813,7 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
             if (lane == 0) rstart[0] = 0;
             rbase[lane] = base;
         }
-        if (tid == 0) zsh = 0;
+        if (tid < 2) zsh[tid] = 0;
         for (uint64_t c0 = 0; c0 < ldw; c0 += cols) {
             const uint32_t cn = (uint32_t)min((uint64_t)cols, ldw - c0);
             for (uint32_t i = tid; i < cn; i += kNT) lw[i] = 0;
@@ -842,19 +863,25 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
                 }
             }
             __syncthreads();
-            uint32_t z = 0;
+            uint32_t zl = 0, zh = 0;
             for (uint32_t i = tid; i < cn; i += kNT) {
                 const unsigned long long v = lw[i];
                 W[w * ldw + c0 + i] = v;
-                z += v != 0;
+                if (wb == 64) {
+                    zl += v != 0;
+                } else {
+                    zl += (uint32_t)v != 0;
+                    zh += (v >> 32) != 0;
+                }
             }
-            if (z) atomicAdd(&zsh, z);
+            if (zl) atomicAdd(&zsh[0], zl);
+            if (zh) atomicAdd(&zsh[1], zh);
             __syncthreads();
         }
         if (tid == 0) {
-            const unsigned long long z = zsh;
-            nnz_acc += z;
-            f_acc += z * (z + 1) / 2;
+            const unsigned long long z0 = zsh[0], z1 = zsh[1];
+            nnz_acc += z0 + z1;
+            f_acc += z0 * (z0 + 1) / 2 + z1 * (z1 + 1) / 2;
         }
         __syncthreads();
     }
@@ -1401,7 +1428,8 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
 
     // --- packed rows: batches, word rows, pack -------------------------------
     const uint64_t ldw = div_up((uint64_t)std::max<int32_t>(n, 1), 128) * 128;
-    uint64_t nb = 0, H = 0;
+    const uint32_t wb = db->word_bits;
+    uint64_t nb = 0, H = 0, Hw = 0;  // rows of W (64-bit), word rows of wb bits
     if (QD > 0) {
         DevBuf<uint32_t> bs;
         DevBuf<uint64_t> bpos, bq, nw, wbase, tmp, wq0, wq1;
@@ -1426,19 +1454,20 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         }
         check_launch("batch starts");
         nw.alloc(nb, s, tb, true, "batch words");
-        launch_1d(nb, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_words", st_); k_batch_words<<<b, 256, 0, st_>>>(bq.p, nb, nw.p); } });
+        launch_1d(nb, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_words", st_); k_batch_words<<<b, 256, 0, st_>>>(bq.p, nb, wb, nw.p); } });
         check_launch("batch words");
         wbase.alloc(nb + 1, s, tb, true, "word bases");
         tmp.release();
         tmp.alloc(scan_tmp_elems(nb), s, tb, true, "scan scratch");
         scan_excl_u64(nw.p, wbase.p, nb, tmp.p, s);
-        H = to_host_u64(wbase.p + nb, s);
-        wq0.alloc(H, s, tb, true, "word rows");
-        wq1.alloc(H, s, tb, true, "word rows");
+        Hw = to_host_u64(wbase.p + nb, s);
+        H = wb == 64 ? Hw : div_up(Hw, 2);
+        wq0.alloc(Hw, s, tb, true, "word rows");
+        wq1.alloc(Hw, s, tb, true, "word rows");
         launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("word_rows", st_);
-                k_word_rows<<<b, 256, 0, st_>>>(QD, bpos.p, bq.p, wbase.p, wq0.p, wq1.p);
+                k_word_rows<<<b, 256, 0, st_>>>(QD, bpos.p, bq.p, wbase.p, wb, wq0.p, wq1.p);
             }
         });
         check_launch("word rows");
@@ -1450,8 +1479,8 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         const uint32_t grid = (uint32_t)std::min<uint64_t>(H, 4096);
         {
             JAS_TIMED("pack", s);
-            k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, wq0.p, wq1.p, Drow.p, rptrp,
-                                                                        rdegp, Sp, cols, st.p);
+            k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, Hw, wb, wq0.p, wq1.p,
+                                                                        Drow.p, rptrp, rdegp, Sp, cols, st.p);
         }
         check_launch("pack");
     }
@@ -1576,7 +1605,11 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     o.n_packed_rows = QD;
     o.n_list_rows = QL;
     o.n_batches = nb;
-    o.n_word_rows = H;
+    o.n_word_rows = Hw;
+    o.word_bits = wb;
+    o.w_rows = H;
+    o.w_stride = ldw;
+    o.n_list_pairs = db->n_lpairs;
     o.nnz_words = hst[ST_NNZW];
     o.word_pairs_F = hst[ST_F];
     o.list_pairs = hst[ST_LISTPAIRS];

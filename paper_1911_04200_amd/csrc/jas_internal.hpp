@@ -167,11 +167,14 @@ struct jas_db {
     int device = 0;
     int32_t n = 0;
     uint32_t U = 0, sbits = 0, batch_bits = 0, dmin = 0, flags = 0;
+    uint32_t word_bits = 64;  // b: rows per bitmask word (32 or 64)
     jas_encode_stats stats{};
     jas::Budget budget;  // db-owned memory
     // |X_i|
     jas::DevBuf<int64_t> card;
-    // packed part: W[H][n] 64-bit words, word row w holds bits of up to 64 rows
+    // packed part: W[H][ldw] 64-bit elements; with b = 64 element row w is
+    // word row w (up to 64 rows), with b = 32 it holds word rows 2w and 2w + 1
+    // in its low and high halves
     uint64_t H = 0;
     jas::DevBuf<uint64_t> W;
     // row-list part: rows of degree 2..dmin-1, CSR over samples (ascending)

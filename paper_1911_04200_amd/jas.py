@@ -25,6 +25,7 @@ JAS_FORCE_MFMA = 0x40
 JAS_TUNE = 0x80
 JAS_ACCUMULATE = 0x100
 JAS_CANONICAL = 0x200
+JAS_DB_CARD, JAS_DB_WORDS, JAS_DB_LIST_PAIRS, JAS_DB_LIST_PTR, JAS_DB_LIST_SAMPLES, JAS_DB_KEYS = range(6)
 
 
 def JAS_GRAM_VARIANT(v: int) -> int:
@@ -36,7 +37,7 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
 
 # Every symbol include/jas.h declares.
 EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_noalloc", "jas_query_workspace_bytes",
-                  "jas_db_size", "jas_db_stats", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
+                  "jas_db_size", "jas_db_stats", "jas_db_part_size", "jas_db_read", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
                   "jas_timing_report", "jas_trim"])
 
 
@@ -50,13 +51,15 @@ class JasError(RuntimeError):
 class jas_encode_opts(ctypes.Structure):
     _fields_ = [("universe_bits", ctypes.c_uint32), ("batch_bits", ctypes.c_uint32),
                 ("dense_min_degree", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("hbm_budget_bytes", ctypes.c_uint64), ("word_bits", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class jas_encode_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in
                 ["n_ids", "n_pairs", "n_rows", "n_shared_rows", "n_packed_rows", "n_list_rows", "n_batches",
-                 "n_word_rows", "nnz_words", "word_pairs_F", "list_pairs", "device_bytes", "dense_min_degree"]]
+                 "n_word_rows", "nnz_words", "word_pairs_F", "list_pairs", "device_bytes", "dense_min_degree",
+                 "word_bits", "w_rows", "w_stride", "n_list_pairs"]]
 
     def to_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -106,6 +109,10 @@ def load(path: str = LIB_PATH):
     lib.jas_gram_variants.restype = i32
     lib.jas_db_stats.argtypes = [vp, ctypes.POINTER(jas_encode_stats)]
     lib.jas_db_stats.restype = ctypes.c_int
+    lib.jas_db_part_size.argtypes = [vp, i32]
+    lib.jas_db_part_size.restype = u64
+    lib.jas_db_read.argtypes = [vp, i32, u64, u64, vp]
+    lib.jas_db_read.restype = ctypes.c_int
     lib.jas_db_free.argtypes = [vp]
     lib.jas_db_free.restype = None
     lib.jas_last_error.restype = ctypes.c_char_p
@@ -241,6 +248,23 @@ def jas_db_stats(db) -> dict:
     st = jas_encode_stats()
     _check(load().jas_db_stats(_h(db), ctypes.byref(st)))
     return st.to_dict()
+
+
+_PART_DTYPE = {JAS_DB_CARD: np.int64, JAS_DB_WORDS: np.uint64, JAS_DB_LIST_PAIRS: np.uint32,
+               JAS_DB_LIST_PTR: np.uint64, JAS_DB_LIST_SAMPLES: np.uint32, JAS_DB_KEYS: np.uint64}
+
+
+def jas_db_part_size(db, part: int) -> int:
+    return int(load().jas_db_part_size(_h(db), part))
+
+
+def jas_db_read(db, part: int, first: int = 0, count: int | None = None) -> np.ndarray:
+    """Elements [first, first + count) of a db part (all of it by default), as a host array."""
+    size = jas_db_part_size(db, part)
+    count = size - first if count is None else count
+    out = np.empty(max(count, 0), dtype=_PART_DTYPE.get(part, np.uint64))
+    _check(load().jas_db_read(_h(db), part, first, count, out.ctypes.data if out.size else None))
+    return out
 
 
 def jas_db_free(db):

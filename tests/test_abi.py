@@ -122,3 +122,23 @@ def test_card_limit_and_its_test_hook(monkeypatch):
                         ("0", 1 << 31), ("-5", 1 << 31), ("12x", 1 << 31), ("", 1 << 31)]:
         monkeypatch.setenv("JAS_TEST_CARD_LIMIT", value)
         assert jas.jas_card_limit() == want, value
+
+
+def test_db_part_constants_and_null_db():
+    text = open(os.path.join(ROOT, "include", "jas.h")).read()
+    parts = dict(re.findall(r"#define (JAS_DB_\w+) (\d+)\n", text))
+    assert len(parts) == 6
+    for name, value in parts.items():
+        assert getattr(jas, name) == int(value), name
+    lib = jas.load()
+    assert lib.jas_db_part_size(None, jas.JAS_DB_WORDS) == 0
+    assert lib.jas_db_read(None, jas.JAS_DB_WORDS, 0, 0, None) == jas.JAS_EINVAL
+
+
+def test_encode_rejects_a_bad_word_width():
+    ids = np.arange(3, dtype=np.uint64)
+    for wb in (16, 48, 128):
+        opts = jas.jas_encode_opts(24, 0, 0, jas.JAS_HOST_PTRS, 0, wb)
+        with pytest.raises(jas.JasError) as e:
+            jas.jas_encode(ids, np.array([0, 3], dtype=np.uint64), 1, opts)
+        assert e.value.status == jas.JAS_EINVAL and "word_bits" in e.value.message
