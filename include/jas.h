@@ -187,7 +187,8 @@ uint64_t jas_card_limit(void);
  * a sequence (Sec. II-B); sample i's set is the k-mers of its sequences.
  * The ID of a k-mer is its bases read as a base-4 number, first base most
  * significant (A = 0, C = 1, G = 2, T = 3), so IDs are below 2^(2k) and
- * jas_encode takes universe_bits = 2k.  JAS_CANONICAL replaces each by the
+ * jas_encode takes universe_bits = 2k (when 2k + ceil(log2 n) exceeds 64, as for k = 31 and n > 4, the
+ * IDs go through jas_relabel first).  JAS_CANONICAL replaces each by the
  * smaller of it and its reverse complement (strand-independent k-mers; an
  * odd k has no palindromes, Sec. V-A2).  Repeated k-mers are left in; the
  * encoding removes them.
@@ -212,6 +213,25 @@ jas_status jas_kmer_offsets(const uint64_t *seq_off, int64_t n_seq, const uint64
                             uint64_t *ids_off);
 jas_status jas_kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t k, uint32_t flags,
                      void *hip_stream, uint64_t *ids);
+
+/*
+ * jas_relabel -- an exact relabelling of IDs: every ID becomes its rank among
+ * the distinct IDs of the array (0 .. D-1).  Equal IDs stay equal and distinct
+ * ones stay distinct, so every intersection and union of sets built from
+ * these IDs is unchanged (B, C and J are the same), while the IDs then fit
+ * ceil(log2 D) bits.  For k-mers of k > 32 - ceil(log2 n) / 2 (k = 31: IDs
+ * below 2^62, Sec. II-B), whose IDs and sample numbers do not fit one 64-bit
+ * key of jas_encode together.  Relabel everything that is compared in one
+ * call (a database and the queries that will be run against it together).
+ *  ids     uint64[n_ids], device, each < 2^universe_bits (else EINVAL).
+ *  out     uint64[n_ids], device; may be ids itself.
+ *  n_distinct, new_universe_bits  host outputs (may be NULL): D, and
+ *          max(1, ceil(log2 D)), the universe_bits to encode the result with.
+ * Sorts a copy of the IDs on hip_stream (2 x 8 bytes per ID of temporaries)
+ * and synchronises it.
+ */
+jas_status jas_relabel(const uint64_t *ids, uint64_t n_ids, uint32_t universe_bits, void *hip_stream, uint64_t *out,
+                       uint64_t *n_distinct, uint32_t *new_universe_bits);
 
 /* Number of MFMA tile variants jas_gram can run (tile shape, word rows per
  * step, K split); variant indices are stable within one build of the library. */

@@ -335,6 +335,18 @@ jas_status jas_finalize(int32_t n, uint32_t flags, void *hip_stream, int32_t *B,
     });
 }
 
+jas_status jas_relabel(const uint64_t *ids, uint64_t n_ids, uint32_t universe_bits, void *hip_stream, uint64_t *out,
+                       uint64_t *n_distinct, uint32_t *new_universe_bits) {
+    return guard([&] {
+        if (universe_bits < 1 || universe_bits > 64) fail(JAS_EINVAL, "jas_relabel: universe_bits must be in 1..64");
+        if (n_ids > 0 && (!ids || !out)) fail(JAS_EINVAL, "jas_relabel: ids or out is NULL");
+        JAS_HOST_TIMED("jas_relabel");
+        const uint64_t D = relabel(ids, n_ids, universe_bits, (hipStream_t)hip_stream, out);
+        if (n_distinct) *n_distinct = D;
+        if (new_universe_bits) *new_universe_bits = std::max<uint32_t>(1, ceil_log2_u64(D));
+    });
+}
+
 namespace {
 void check_seq_off(const uint64_t *seq_off, int64_t n_seq, uint32_t k, const char *what) {
     if (n_seq < 0) fail(JAS_EINVAL, std::string(what) + ": n_seq < 0");

@@ -271,6 +271,10 @@ void kmers(const uint64_t *seq, const uint64_t *seq_off, int64_t n_seq, uint32_t
            uint64_t *ids);
 int32_t gram_variants();
 
+// Exact relabelling (see relabel.hip): out[i] = rank of ids[i] among the
+// distinct IDs (each < 2^U); returns their number D.  Synchronises s.
+uint64_t relabel(const uint64_t *ids, uint64_t N, uint32_t U, hipStream_t s, uint64_t *out);
+
 // Query (see query.hip).
 // ar: take every temporary from this region instead of the cache (nothing is allocated).
 void query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq, uint64_t NQ,

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
                 -6: "JAS_EUNSUPPORTED"}
 
 # Every symbol include/jas.h declares.
-EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_noalloc", "jas_query_workspace_bytes",
+EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_relabel", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_noalloc", "jas_query_workspace_bytes",
                   "jas_db_size", "jas_db_stats", "jas_db_part_size", "jas_db_read", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
                   "jas_timing_report", "jas_trim"])
 
@@ -92,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.jas_kmer_offsets.argtypes = [vp, ctypes.c_int64, vp, i32, u32, vp]
     lib.jas_kmers.restype = i32
     lib.jas_kmers.argtypes = [vp, vp, ctypes.c_int64, u32, u32, vp, vp]
+    lib.jas_relabel.restype = i32
+    lib.jas_relabel.argtypes = [vp, u64, u32, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(u32)]
     lib.jas_finalize.restype = i32
     lib.jas_finalize.argtypes = [i32, u32, vp, vp, vp, vp, vp]
     lib.jas_gram.restype = ctypes.c_int
@@ -214,6 +216,14 @@ def jas_kmers(seq, seq_off: np.ndarray, k: int, flags: int, stream, ids):
     """Device: the k-mer IDs of every sequence into ids (seq_off on the host)."""
     seq_off = np.ascontiguousarray(seq_off, dtype=np.uint64)
     _check(load().jas_kmers(_ptr(seq), seq_off.ctypes.data, seq_off.size - 1, k, flags, _stream(stream), _ptr(ids)))
+
+
+def jas_relabel(ids, n_ids: int, universe_bits: int, stream, out):
+    """Device IDs -> their ranks among the distinct IDs; returns (D, new universe_bits)."""
+    d, u = ctypes.c_uint64(), ctypes.c_uint32()
+    _check(load().jas_relabel(_ptr(ids), n_ids, universe_bits, _stream(stream), _ptr(out), ctypes.byref(d),
+                              ctypes.byref(u)))
+    return int(d.value), int(u.value)
 
 
 def jas_query(db, q_ids, q_offsets, nq: int, flags: int, stream, B, q_card=None, den=None, J=None):
