@@ -124,10 +124,11 @@ def cpu_baseline(spec, k: int, seed: int = 5):
                        f"n(n+1)/2 / (n * per-set + n(n+1)/2 * per-pair time) for the full n={n}")}
 
 
-def run_serving(n_requests: int, n_saturation: int, seed: int = 1):
+def run_serving(n_requests: int, n_saturation: int, n_warmup: int = 200, pool: int = 200, seed: int = 1):
     """Resident serving database (n=8192, U=36, 3.2e9 IDs); Poisson request stream at
     0.7 x the saturation rate measured by a closed pre-run; continuous batching over 4 slots
-    within an 8 GiB HBM budget."""
+    within an 8 GiB HBM budget.  The requests cycle through `pool` seeded payloads (1-64
+    query sets of 1e4-1e6 IDs each), so a long stream needs no more host memory than that."""
     import numpy as np
     import torch
 
@@ -152,11 +153,24 @@ def run_serving(n_requests: int, n_saturation: int, seed: int = 1):
     del ids_d
     torch.cuda.synchronize()
     log(f"[serving] encoded in {enc_s:.2f} s; generating requests")
-    warm = serve.make_requests(spec, 8, seed=seed * 1000 + 1, first_id=100000, pinned=True)
-    sat = serve.make_requests(spec, n_saturation, seed=seed * 1000 + 2, first_id=200000, pinned=True)
-    reqs = serve.make_requests(spec, n_requests, seed=seed * 1000 + 3, first_id=300000, pinned=True)
-    server = serve.Server(db, slots=4, budget_bytes=8 << 30, max_batch_sets=64)
-    server.run(warm)
+    payload = serve.make_requests(spec, pool, seed=seed * 1000 + 3, first_id=300000, pinned=True)
+
+    def stream_of(count, first):
+        out = []
+        for k in range(count):
+            src = payload[(first + k) % pool]
+            r = serve.Request(first + k, src.ids, src.offsets)
+            r._payload = src
+            out.append(r)
+        return out
+
+    warm = stream_of(n_warmup, 0)
+    sat = stream_of(n_saturation, n_warmup)
+    reqs = stream_of(n_requests, n_warmup + n_saturation)
+    server = serve.Server(db, slots=4, budget_bytes=8 << 30, max_batch_sets=64, keep_results=False)
+    arr_w = serve.poisson_arrivals(len(warm), 200.0, seed + 7)
+    server.run(warm, arr_w)
+    log(f"[serving] {len(warm)} warm-up requests done")
     t = time.perf_counter()
     server.run(sat)
     sat_rate = len(sat) / (time.perf_counter() - t)
@@ -170,6 +184,7 @@ def run_serving(n_requests: int, n_saturation: int, seed: int = 1):
     out.update({"workload": f"serving_n{spec.n}_u{spec.universe_bits}", "db_ids": N,
                 "db_encode_s": enc_s, "db_device_bytes": st["device_bytes"], "saturation_requests_per_s": sat_rate,
                 "offered_requests_per_s": rate, "slots": 4, "hbm_budget_bytes": 8 << 30, "max_batch_sets": 64,
+                "warmup_requests": len(warm), "saturation_requests": len(sat), "distinct_payloads": pool,
                 "latency": "completion - Poisson arrival (host arrays in and out, queueing included)"})
     db.close()
     cabi.jas_trim()
@@ -284,60 +299,21 @@ def run_streamed(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="paperlike",
-                    choices=["tiny", "paperlike", "precision", "batching", "bernoulli_p1e-4", "bernoulli_p1e-3",
-                             "bernoulli_p1e-2", "bernoulli_p1e-1", "graph_s13_ef64"],
-                    help="bernoulli_p*: the paper's synthetic matrices (each entry 1 with probability p); "
-                         "graph_*: neighbourhoods of an R-MAT graph (vertex similarity)")
-    ap.add_argument("--dmin", type=int, default=0, help="dense_min_degree (0: library default)")
-    ap.add_argument("--upper", action="store_true", help="packed upper-triangle outputs")
-    ap.add_argument("--path", default="auto", choices=["auto", "popcount", "mfma"], help="Gram path for packed tiles")
-    ap.add_argument("--cpu-sample", type=int, default=64, help="sets in the oracle's timed sample (0: skip)")
-    ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing in the timed region")
-    ap.add_argument("--serving-requests", type=int, default=160,
-                    help="requests in the timed Poisson serving run (0: no serving run)")
-    ap.add_argument("--serving-saturation", type=int, default=48, help="requests in the closed saturation run")
-    ap.add_argument("--stream-part-bits", type=int, default=0,
-                    help="K > 0: keep the sets in host memory and stream them in 2^K ID-range parts "
-                         "(Bernoulli workloads, whose sets are ascending); host-to-device copies are timed")
-    ap.add_argument("--gram-variant", type=int, default=-1,
-                    help="with --stream-part-bits: run MFMA tile variant V for every part (default: the library's)")
-    ap.add_argument("--kmer-front-end", action="store_true",
-                    help="time the GPU k-mer front end instead (128 genomes of 4 Mbases, k = 31, canonical): "
-                         "bases/s, inputs resident in HBM")
-    ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="MiB copied device-to-device before the steps: a plain copy of known size that scales "
-                         "the HBM byte counters of a profiler run")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def run_all_pairs(args, workload: str, upper: bool):
+    """Time the all-pairs step (encode + Gram, inputs resident in HBM) on one
+    full-size workload: (summary dict, encode stats, spec, N)."""
     import numpy as np
     import torch
 
     import synth
     from paper_1911_04200_amd import jas as cabi
 
-    if args.stream_part_bits > 0:
-        run_streamed(args)
-        return
-    if args.kmer_front_end:
-        run_kmers(args)
-        return
-    spec = synth.workload(args.workload)
-    bb = synth.BATCH_BITS[args.workload]
+    spec = synth.workload(workload)
+    bb = synth.BATCH_BITS[workload]
     n = spec.n
     off = synth.offsets(spec)
     N = int(off[-1])
-    log(f"[bench] workload {args.workload}: n={n} U={spec.universe_bits} N={N} ids, batch 2^{bb}")
+    log(f"[bench] workload {workload}: n={n} U={spec.universe_bits} N={N} ids, batch 2^{bb}")
     t = time.perf_counter()
     host = torch.empty(N, dtype=torch.int64, pin_memory=True)
     ids_np = host.numpy().view(np.uint64)
@@ -360,15 +336,13 @@ def main():
         del src, dst
 
     stream = torch.cuda.current_stream()
-    if args.workload == "batching":
-        args.upper = True  # the batching form returns the upper triangle only
-    length = n * (n + 1) // 2 if args.upper else n * n
+    length = n * (n + 1) // 2 if upper else n * n
     B = torch.empty(length, dtype=torch.int32, device=dev)
     card = torch.empty(n, dtype=torch.int64, device=dev)
     den = torch.empty(length, dtype=torch.int64, device=dev)
     J = torch.empty(length, dtype=torch.float64, device=dev)
     opts = cabi.jas_encode_opts(spec.universe_bits, bb, args.dmin, 0, 0)
-    flags = cabi.JAS_UPPER if args.upper else 0
+    flags = cabi.JAS_UPPER if upper else 0
     flags |= {"auto": 0, "popcount": cabi.JAS_FORCE_POPCOUNT, "mfma": cabi.JAS_FORCE_MFMA}[args.path]
 
     def step(extra_flags=0):
@@ -430,7 +404,7 @@ def main():
             traffic = None
             tf = os.path.join(ROOT, "profiles", "traffic.json")
             if os.path.exists(tf):
-                rec = json.load(open(tf)).get(f"{dom}:{args.workload}")
+                rec = json.load(open(tf)).get(f"{dom}:{workload}")
                 if rec and rec.get("source_hash") == kernel_source_hash(dom):
                     traffic = rec.get("bytes_per_launch")
             roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
@@ -449,6 +423,78 @@ def main():
 
     del ids_d, B, den, J
     cabi.jas_trim()
+    summary = {"value": value, "unit": "pairs/s", "ms_per_step": sec * 1e3, "steps": args.steps,
+               "config": {"workload": f"{workload}_n{n}_u{spec.universe_bits}", "n": n,
+                          "universe_bits": spec.universe_bits, "batch_rows": f"2^{bb}", "ids": N,
+                          "pairs_per_step": pairs, "layout": "upper" if upper else "full",
+                          "dense_min_degree": args.dmin},
+               "roofline": roof, "detail": extra}
+    return summary, st, spec, N
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="paperlike",
+                    choices=["tiny", "paperlike", "precision", "batching", "bernoulli_p1e-4", "bernoulli_p1e-3",
+                             "bernoulli_p1e-2", "bernoulli_p1e-1", "graph_s13_ef64"],
+                    help="bernoulli_p*: the paper's synthetic matrices (each entry 1 with probability p); "
+                         "graph_*: neighbourhoods of an R-MAT graph (vertex similarity)")
+    ap.add_argument("--dmin", type=int, default=0, help="dense_min_degree (0: library default)")
+    ap.add_argument("--upper", action="store_true", help="packed upper-triangle outputs")
+    ap.add_argument("--path", default="auto", choices=["auto", "popcount", "mfma"], help="Gram path for packed tiles")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="sets in the oracle's timed sample (0: skip)")
+    ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing in the timed region")
+    ap.add_argument("--extra-configs", type=int, default=1,
+                    help="with the paperlike workload: also time the precision and batching forms (0: skip)")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests in the timed Poisson serving run (0: no serving run)")
+    ap.add_argument("--serving-saturation", type=int, default=200, help="requests in the closed saturation run")
+    ap.add_argument("--stream-part-bits", type=int, default=0,
+                    help="K > 0: keep the sets in host memory and stream them in 2^K ID-range parts "
+                         "(Bernoulli workloads, whose sets are ascending); host-to-device copies are timed")
+    ap.add_argument("--gram-variant", type=int, default=-1,
+                    help="with --stream-part-bits: run MFMA tile variant V for every part (default: the library's)")
+    ap.add_argument("--kmer-front-end", action="store_true",
+                    help="time the GPU k-mer front end instead (128 genomes of 4 Mbases, k = 31, canonical): "
+                         "bases/s, inputs resident in HBM")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied device-to-device before the steps: a plain copy of known size that scales "
+                         "the HBM byte counters of a profiler run")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1911_04200_amd import jas as cabi
+
+    if args.stream_part_bits > 0:
+        run_streamed(args)
+        return
+    if args.kmer_front_end:
+        run_kmers(args)
+        return
+    upper = args.upper or args.workload == "batching"  # the batching form returns the upper triangle only
+    main_res, st, spec, N = run_all_pairs(args, args.workload, upper)
+    others = {}
+    if args.workload == "paperlike" and args.extra_configs:
+        # the precision and batching forms, timed the same way (their own dominant kernels)
+        for name in ("precision", "batching"):
+            try:
+                r, _, _, _ = run_all_pairs(args, name, name == "batching")
+                r["detail"] = {k: r["detail"][k] for k in ("gram_ms", "gram_autotune_ms", "encode_stats")} | {
+                    "kernels": {k: v for k, v in r["detail"]["kernels"].items() if v["ms_per_step"] >= 0.5}}
+                others[name] = r
+            except Exception as e:  # reported, not fatal to the main line
+                others[name] = {"error": repr(e)}
     serving = None
     if args.serving_requests > 0:
         try:
@@ -462,14 +508,14 @@ def main():
         cpu = cpu_baseline(spec, args.cpu_sample)
 
     out = {"metric": "sample-pair intersections/s (exact B, C, J of all pairs i <= j)",
-           "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "u64 keys / i32 counts / f64 J", "data": "synthetic (seeded counter-based generator, synth/)",
-           "config": {"workload": f"{args.workload}_n{n}_u{spec.universe_bits}", "n": n,
-                      "universe_bits": spec.universe_bits, "batch_rows": f"2^{bb}", "ids": N,
-                      "pairs_per_step": pairs, "layout": "upper" if args.upper else "full",
-                      "dense_min_degree": args.dmin},
-           "roofline": roof, "cpu_baseline": cpu, "serving": serving, "detail": extra}
+           "value": main_res["value"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": main_res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": ("exact integers: u64 keys, i32 B, i64 C; packed Gram on fp4 (e2m1 0/1) MFMA operands with "
+                     "f32 sums kept below 2^24 (exact); f64 J"),
+           "data": "synthetic (seeded counter-based generator, synth/)",
+           "config": main_res["config"], "roofline": main_res["roofline"], "cpu_baseline": cpu,
+           "precision": others.get("precision"), "batching": others.get("batching"), "serving": serving,
+           "detail": main_res["detail"]}
     print(json.dumps(out), flush=True)
 
 

@@ -49,15 +49,20 @@ class Request:
 
 
 class Server:
+    """keep_results: hand every request its rows of B, |Q|, C and J (copied out
+    of the slot's output buffers); False keeps only the timings (long runs)."""
+
     def __init__(self, db, slots: int = 4, budget_bytes: int = 8 << 30, max_batch_sets: int = 64,
-                 device: int = 0):
+                 device: int = 0, keep_results: bool = True):
         self.db = db
         self.n = db.n
         self.slots = slots
         self.budget = budget_bytes
         self.max_batch_sets = max_batch_sets
         self.device = device
+        self.keep_results = keep_results
         self.streams = None  # created on the first run (one default-priority stream per slot)
+        self.outbufs = None  # per slot: page-locked B, |Q|, C, J for max_batch_sets query rows
         self.queue: collections.deque = collections.deque()
         self.cv = threading.Condition()
         self.in_use = 0
@@ -103,7 +108,22 @@ class Server:
             self.cv.notify_all()
 
     # -- one call ---------------------------------------------------------------
-    def _run_batch(self, batch, stream, t0):
+    def _outputs(self, slot, nq):
+        """The slot's page-locked output buffers (allocated once, at the largest
+        call size), viewed at nq rows; a larger call gets buffers of its own."""
+        import torch
+        cap = self.max_batch_sets
+        if nq > cap:
+            return (np.empty((nq, self.n), np.int32), np.empty(nq, np.int64), np.empty((nq, self.n), np.int64),
+                    np.empty((nq, self.n), np.float64))
+        if self.outbufs[slot] is None:
+            self.outbufs[slot] = tuple(torch.empty(shape, dtype=dt, pin_memory=True).numpy() for shape, dt in
+                                       [((cap, self.n), torch.int32), ((cap,), torch.int64),
+                                        ((cap, self.n), torch.int64), ((cap, self.n), torch.float64)])
+        B, qc, den, J = self.outbufs[slot]
+        return B[:nq], qc[:nq], den[:nq], J[:nq]
+
+    def _run_batch(self, batch, stream, t0, slot=0):
         import torch
         sizes = [r.nq for r in batch]
         nq = sum(sizes)
@@ -115,17 +135,16 @@ class Server:
             off[k + 1:k + 1 + r.nq] = r.offsets[1:] + np.uint64(base)
             base += int(r.offsets[-1])
             k += r.nq
-        B = np.empty((nq, self.n), dtype=np.int32)
-        qc = np.empty(nq, dtype=np.int64)
-        den = np.empty((nq, self.n), dtype=np.int64)
-        J = np.empty((nq, self.n), dtype=np.float64)
+        B, qc, den, J = self._outputs(slot, nq)
         start = time.perf_counter() - t0
         with torch.cuda.device(self.device):
             cabi.jas_query(self.db, ids, off, nq, cabi.JAS_HOST_PTRS, stream, B, qc, den, J)
         done = time.perf_counter() - t0
         k = 0
         for r in batch:
-            r.B, r.q_card, r.den, r.J = B[k:k + r.nq], qc[k:k + r.nq], den[k:k + r.nq], J[k:k + r.nq]
+            if self.keep_results:
+                r.B, r.q_card = B[k:k + r.nq].copy(), qc[k:k + r.nq].copy()
+                r.den, r.J = den[k:k + r.nq].copy(), J[k:k + r.nq].copy()
             r.start, r.done, r.batch_size = start, done, len(batch)
             k += r.nq
 
@@ -142,7 +161,7 @@ class Server:
                         self.cv.wait(0.05)
                 batch, c = got
             try:
-                self._run_batch(batch, stream, t0)
+                self._run_batch(batch, stream, t0, slot)
             except BaseException as e:  # noqa: BLE001 - surfaced by run()
                 self.errors.append(e)
             finally:
@@ -158,6 +177,7 @@ class Server:
         if self.streams is None:
             import torch
             self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.slots)]
+            self.outbufs = [None] * self.slots
         self.closed = False
         self.errors = []
         finished: List[Request] = []
@@ -196,16 +216,31 @@ def summarize(reqs: List[Request], n: int, wall: float) -> dict:
             "requests_per_s": len(reqs) / wall, "query_sets_per_s": sets / wall,
             "pair_intersections_per_s": sets * n / wall,
             "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
-            "mean_batch_requests": float(np.mean([r.batch_size for r in reqs])) if reqs else None}
+            "mean_batch_requests": float(np.mean([r.batch_size for r in reqs])) if reqs else None,
+            "p999_ms": 1e3 * percentile(lat, 99.9),
+            "requests_by_call_size": {int(k): int(v) for k, v in
+                                      zip(*np.unique([r.batch_size for r in reqs], return_counts=True))}
+            if reqs else {}}
 
 
 def make_requests(db_spec, count: int, seed: int, max_sets: int = 64, size_scale: float = 1.0,
-                  first_id: int = 0, pinned: bool = False) -> List[Request]:
+                  first_id: int = 0, pinned: bool = False, pool: int = 0) -> List[Request]:
     """Seeded synthetic requests: 1..max_sets query sets each (sizes and sharing as synth.query_spec).
 
     pinned: the IDs are received into page-locked host memory (as a server's
-    receive buffers would be), so their copy to the device is a plain DMA."""
+    receive buffers would be), so their copy to the device is a plain DMA.
+    pool > 0: only `pool` distinct payloads are drawn and request k carries
+    payload k % pool (a long stream without holding every payload in memory)."""
     import synth
+    if pool and pool < count:
+        base = make_requests(db_spec, pool, seed, max_sets, size_scale, first_id, pinned)
+        out = []
+        for k in range(count):
+            src = base[k % pool]
+            req = Request(first_id + k, src.ids, src.offsets)
+            req._payload = src  # keeps a page-locked payload alive
+            out.append(req)
+        return out
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
