@@ -238,6 +238,54 @@ jas_status jas_relabel(const uint64_t *ids, uint64_t n_ids, uint32_t universe_bi
 int32_t jas_gram_variants(void);
 
 /*
+ * Encode plans -- the batching form as one capturable launch sequence: the
+ * encode of Sec. III-B (Eqs. (3)-(6)) for collections of one shape, with no
+ * host synchronisation and no allocation, so that jas_plan_encode, jas_gram
+ * and jas_finalize's work can be captured in one HIP graph and replayed for
+ * every new collection.
+ *
+ * jas_plan_create encodes (ids, offsets, n) once as jas_encode does and keeps
+ * what that encode decided (the sort's bits, the range stride, the key width
+ * in LDS, the row degree threshold) together with buffers for every
+ * intermediate array at this collection's sizes times (1 + headroom), plus a
+ * floor of 64 rows (1024 list pairs) for each form of row the threshold admits,
+ * also where this collection has none (packed and list rows are each capped
+ * at the shared-row capacity).  opts as
+ * in jas_encode, device pointers only, no JAS_KEEP_IDS, 1 <= n <= 10240;
+ * with dense_min_degree = 0 and JAS_TUNE in opts->flags the threshold is
+ * chosen by timing encode + Gram on the device for candidate thresholds (the
+ * cost model's choice t, t/2, 2t, 2 and n+1; jas_plan_tuning lists them).
+ * Synchronises hip_stream.  headroom in [0, 4].
+ *
+ * jas_plan_encode encodes another collection of the same n into the plan's db
+ * (jas_plan_db; owned by the plan, never passed to jas_db_free): everything
+ * is enqueued on hip_stream, every size is computed and read on the device.
+ * Capturable.  The plan's db is then valid for jas_gram once the stream has
+ * run; calls on one plan must not overlap.
+ *
+ * jas_plan_check (after the stream has run; synchronises it) returns what the
+ * last jas_plan_encode found: OK; ENOMEM when a size exceeded its capacity
+ * (plan again with more headroom); EUNSUPPORTED when the collection needed
+ * what the plan did not prepare (wider LDS keys, a shorter range stride, the
+ * per-pass sort); EINVAL for an ID >= 2^U; EOVERFLOW for a set of
+ * jas_card_limit() or more IDs; EDEVICE when the sort's look-back gave up.
+ * Unless OK, the db's contents are unspecified.  stats (may be NULL) gets the
+ * encode's statistics.
+ */
+typedef struct jas_plan jas_plan;
+jas_status jas_plan_create(const uint64_t *ids, const uint64_t *offsets, int32_t n, const jas_encode_opts *opts,
+                           double headroom, void *hip_stream, jas_plan **plan_out);
+jas_status jas_plan_encode(jas_plan *plan, const uint64_t *ids, const uint64_t *offsets, void *hip_stream);
+jas_status jas_plan_check(jas_plan *plan, void *hip_stream, jas_encode_stats *stats);
+const jas_db *jas_plan_db(const jas_plan *plan);
+/* The plan's row degree threshold (0 for NULL). */
+uint32_t jas_plan_threshold(const jas_plan *plan);
+/* Up to cap (threshold, encode + Gram ms) pairs of the timing that chose it; returns how many there are. */
+int32_t jas_plan_tuning(const jas_plan *plan, uint32_t *thresholds, double *ms, int32_t cap);
+/* Frees the plan and its device memory (synchronises the device first).  NULL is a no-op. */
+void jas_plan_free(jas_plan *plan);
+
+/*
  * jas_query -- similarity of nq query sets against every encoded sample:
  * Eq. (1) with i ranging over the queries and j over the database.
  *

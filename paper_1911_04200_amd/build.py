@@ -13,7 +13,7 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libjas.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["scan.hip", "radix.hip", "encode.hip", "gram.hip", "query.hip", "api.hip", "timing.hip", "memory.hip", "tune.hip", "kmer.hip", "noalloc.hip", "relabel.hip"]
+SOURCES = ["scan.hip", "radix.hip", "encode.hip", "gram.hip", "query.hip", "api.hip", "timing.hip", "memory.hip", "tune.hip", "kmer.hip", "noalloc.hip", "relabel.hip", "plan.hip"]
 HEADERS = ["jas_internal.hpp", "device_util.hpp", "onesweep_index.hpp"]
 
 # gfx950 only; packed FP32 instructions disabled; no fast math.

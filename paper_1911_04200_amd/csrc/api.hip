@@ -60,6 +60,8 @@ std::vector<uint64_t> host_offsets(const uint64_t *offsets, int32_t n, bool host
 
 void fail(jas_status st, const std::string &msg) { throw Error{st, msg}; }
 
+void set_last_error(const std::string &msg) { g_err = msg; }
+
 void check_hip(hipError_t e, const char *what) {
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -255,7 +257,9 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
             ids_d.release();
             JAS_HOST_TIMED("sort_enqueue");
             const uint32_t lo = sbits + U - plan.top_bits, hi = sbits + U;
-            if (plan.top_bits > 0 && !radix_sort_onesweep(keys, alt, N, lo, hi, plan.width, ghist.p, err.p, s, &tb)) {
+            db->trace.onesweep = plan.top_bits == 0 ||
+                                 radix_sort_onesweep(keys, alt, N, lo, hi, plan.width, ghist.p, err.p, s, &tb);
+            if (!db->trace.onesweep) {
                 RadixWork rw;
                 radix_sort_u64(keys, alt, N, lo, hi, rw, s, &tb);
             }

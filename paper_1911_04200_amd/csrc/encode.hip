@@ -43,10 +43,14 @@ constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass, at most
 constexpr uint32_t kPackLoads = 8;         // sample loads in flight per lane in k_pack
 
 enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
+static_assert(ST_N == ST_N_ && ST_ROWS == ST_ROWS_ && ST_NNZW == ST_NNZW_ && ST_F == ST_F_ &&
+                  ST_LISTPAIRS == ST_LISTPAIRS_,
+              "encode counters");
 // Counters that many blocks add to are spread over kStatReplicas slots (one
 // counter would serialise an atomic from every block) and summed into st by
 // k_sum_replicas.
 constexpr uint32_t kStatReplicas = 64;
+static_assert(kStatReplicas == kStatReplicasPub, "counter replicas");
 
 // ---------------------------------------------------------------------------
 // Keys of one chunk (kChunk entries) per block, and the totals of every digit
@@ -57,11 +61,15 @@ __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__
                                                      const uint64_t *__restrict__ off, int32_t n, uint64_t N,
                                                      uint32_t sbits, uint64_t hi_mask, uint64_t *__restrict__ keys,
                                                      uint32_t *err, uint32_t npass, uint32_t idlo, uint32_t width,
-                                                     unsigned long long *__restrict__ ghist) {
+                                                     unsigned long long *__restrict__ ghist,
+                                                     const uint64_t *__restrict__ dsz) {
     __shared__ int32_t s_lo, s_hi;
     __shared__ uint32_t gh[kMaxPasses][256];
     const uint32_t tid = threadIdx.x;
+    if (plan_aborted(dsz)) return;
+    if (dsz) N = dsz[PZ_N];
     const uint64_t b0 = (uint64_t)blockIdx.x * kChunk;
+    if (b0 >= N) return;  // a planned launch covers the largest N
     const uint64_t b1 = min(N, b0 + kChunk);
     const uint32_t dmask = (1u << width) - 1u;
 #pragma unroll
@@ -309,6 +317,7 @@ constexpr uint32_t kLRounds = (kLocalCapKeys + kLNT - 1) / kLNT;  // keys per th
 constexpr uint64_t kLStrides[] = {4096, 3072, 2048};
 
 __device__ __forceinline__ uint64_t bucket_of(uint64_t key, uint32_t bsh) { return bsh >= 64 ? 0 : key >> bsh; }
+__device__ __forceinline__ uint64_t div_up_dev(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 __device__ __forceinline__ uint32_t dev_ceil_log2(uint64_t v) { return v <= 1 ? 0u : 64u - (uint32_t)__clzll(v - 1); }
 
 // rs[c] = first bucket edge at or after c*stride, c in [0, nlc]; positions
@@ -316,7 +325,12 @@ __device__ __forceinline__ uint32_t dev_ceil_log2(uint64_t v) { return v <= 1 ? 
 // kLocalCapKeys keys away is not looked for: rs[c] = ~0 and err |= 8.
 __global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict__ K, uint64_t N, uint32_t bsh,
                                                        uint64_t stride, uint64_t nlc, uint64_t *__restrict__ rs,
-                                                       uint32_t *err) {
+                                                       uint32_t *err, const uint64_t *__restrict__ dsz) {
+    if (plan_aborted(dsz)) return;
+    if (dsz) {
+        N = dsz[PZ_N];
+        nlc = div_up_dev(N, stride);
+    }
     const uint64_t c = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint32_t lane = lane_id();
     if (c > nlc) return;  // whole waves
@@ -350,7 +364,10 @@ __global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict
 // The flags of a thread's ranges are gathered first and set with one atomic
 // per wave (every range may set bit 16).
 __global__ void k_range_check(const uint64_t *__restrict__ K, const uint64_t *rs, uint64_t nlc, uint32_t bsh,
-                              uint32_t lowbits, uint32_t sbits, uint32_t *err) {
+                              uint32_t lowbits, uint32_t sbits, uint32_t *err, const uint64_t *__restrict__ dsz,
+                              uint64_t stride) {
+    if (plan_aborted(dsz)) return;
+    if (dsz) nlc = div_up_dev(dsz[PZ_N], stride);
     uint32_t f = 0;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nlc; c += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t a = rs[c], b = rs[c + 1];
@@ -373,7 +390,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
     uint64_t *__restrict__ K, uint32_t sbits, uint64_t smask, uint32_t bsh, uint32_t lowbits,
     const uint64_t *__restrict__ rs, uint32_t nlc, uint32_t *__restrict__ cnt, int keep, uint32_t *__restrict__ Sg,
     uint64_t *__restrict__ rid_g, uint64_t *__restrict__ rptr_g, unsigned long long *__restrict__ dupc,
-    unsigned long long *__restrict__ rows_rep) {
+    unsigned long long *__restrict__ rows_rep, const uint64_t *__restrict__ dsz, uint64_t stride, uint32_t *err) {
     __shared__ KT A[kLocalCapKeys];
     __shared__ uint32_t wcnt[kLWaves][256];
     __shared__ uint64_t T[kLWaves][256];  // per wave: lanes of the current round with digit d
@@ -383,6 +400,23 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint64_t lt = lanemask_lt();
     const uint32_t c = blockIdx.x;
+    if (plan_aborted(dsz)) return;
+    if (dsz) {
+        // a planned launch covers the most ranges; the others count nothing,
+        // and a range the planned stride cannot hold is flagged and skipped
+        const bool beyond = c >= div_up_dev(dsz[PZ_N], stride);
+        const bool bad = !beyond && (rs[c] == ~0ull || rs[c + 1] == ~0ull || rs[c + 1] < rs[c] ||
+                                     rs[c + 1] - rs[c] > kLocalCapKeys);
+        if (beyond || bad) {
+            if (tid == 0) {
+                cnt[c] = 0;
+                cnt[nlc + c] = 0;
+                cnt[2 * (uint64_t)nlc + c] = 0;
+                if (bad) atomicOr(err, 8u);
+            }
+            return;
+        }
+    }
     for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&T[0][0])[i] = 0;
     const uint64_t s0 = rs[c], s1 = rs[c + 1];
     const uint32_t L = (uint32_t)(s1 - s0);  // <= kLocalCapKeys (k_range_check)
@@ -587,7 +621,10 @@ __global__ __launch_bounds__(256) void k_local_move(const uint64_t *__restrict__
                                                      const uint64_t *__restrict__ rid_g,
                                                      const uint64_t *__restrict__ rptr_g, uint64_t *__restrict__ Dk,
                                                      uint64_t *__restrict__ row_id, uint64_t *__restrict__ row_ptr,
-                                                     uint32_t *__restrict__ row_deg) {
+                                                     uint32_t *__restrict__ row_deg, const uint64_t *__restrict__ dsz,
+                                                     uint64_t stride) {
+    if (plan_aborted(dsz)) return;
+    if (dsz) nlc = div_up_dev(dsz[PZ_N], stride);
     for (uint64_t c = blockIdx.x; c < nlc; c += gridDim.x) {
         const uint64_t s0 = rs[c], r0 = s0 / 2;
         const uint64_t d0 = oD[c], nd = oD[c + 1] - d0;
@@ -644,6 +681,7 @@ __global__ __launch_bounds__(kNT) void k_deg_hist(const uint32_t *row_deg, uint6
 // before it.
 constexpr uint32_t kSplitPer = 8;
 constexpr uint64_t kSplitTile = (uint64_t)kNT * kSplitPer;
+static_assert(kSplitTile == kSplitTilePub, "row split tile");
 
 // The 8 degrees of rows [r0, r0 + 8) (two 16-byte loads when all exist; r0 is a
 // multiple of 8, so they are aligned); rows past R read as degree 0.
@@ -661,8 +699,11 @@ __device__ __forceinline__ void load_degrees(const uint32_t *__restrict__ row_de
 }
 
 __global__ __launch_bounds__(kNT) void k_row_count(const uint32_t *__restrict__ row_deg, uint64_t R, uint32_t dmin,
-                                                    uint32_t *__restrict__ tcnt, unsigned long long *lp_rep) {
+                                                    uint32_t *__restrict__ tcnt, unsigned long long *lp_rep,
+                                                    const uint64_t *__restrict__ dsz) {
     __shared__ uint64_t sh[kWaves], sh2[kWaves];
+    if (plan_aborted(dsz)) return;
+    if (dsz) R = dsz[PZ_R];  // tiles past R count nothing
     const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
     uint64_t nd = 0, lp = 0;
     uint32_t dg[kSplitPer];
@@ -704,8 +745,10 @@ __global__ void k_sum_replicas(const unsigned long long *rep, uint32_t nrep, uns
 
 __global__ __launch_bounds__(kNT) void k_row_split(const uint32_t *__restrict__ row_deg, uint64_t R, uint32_t dmin,
                                                     const uint64_t *__restrict__ toff, uint64_t *__restrict__ Drow,
-                                                    uint64_t *__restrict__ Lrow) {
+                                                    uint64_t *__restrict__ Lrow, const uint64_t *__restrict__ dsz) {
     __shared__ uint64_t sh[kWaves];
+    if (plan_aborted(dsz)) return;
+    if (dsz) R = dsz[PZ_R];
     const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
     uint32_t flags = 0, nd = 0;
     uint32_t dg[kSplitPer];
@@ -730,29 +773,45 @@ __global__ __launch_bounds__(kNT) void k_row_split(const uint32_t *__restrict__ 
 }
 
 // Batches of packed rows.
+// (planned: flags for q < QD, zeros up to the capacity QDcap = the host QD)
 __global__ void k_batch_flag(const uint64_t *Drow, const uint64_t *row_id, uint64_t QD, uint32_t bbits,
-                             uint32_t *bs) {
+                             uint32_t *bs, const uint64_t *__restrict__ dsz) {
+    if (plan_aborted(dsz)) return;
+    const uint64_t qd = dsz ? dsz[PZ_QD] : QD;
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x) {
+        if (q >= qd) {
+            bs[q] = 0;
+            continue;
+        }
         const uint64_t b = row_id[Drow[q]] >> bbits;
         bs[q] = (q == 0) || b != (row_id[Drow[q - 1]] >> bbits);
     }
 }
 
-__global__ void k_batch_start(const uint32_t *bs, const uint64_t *bpos, uint64_t QD, uint64_t *bq) {
+__global__ void k_batch_start(const uint32_t *bs, const uint64_t *bpos, uint64_t QD, uint64_t *bq,
+                              const uint64_t *__restrict__ dsz) {
+    if (plan_aborted(dsz)) return;
+    if (dsz) QD = dsz[PZ_QD];
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x)
         if (bs[q]) bq[bpos[q]] = q;
 }
 
 // Word rows of b = wb bits (32 or 64) per batch: ceil(rows / b).
-__global__ void k_batch_words(const uint64_t *bq, uint64_t nb, uint32_t wb, uint64_t *nw) {
+// (planned: nb batches, zeros up to the capacity nbcap = the host nb)
+__global__ void k_batch_words(const uint64_t *bq, uint64_t nb, uint32_t wb, uint64_t *nw,
+                              const uint64_t *__restrict__ dsz) {
+    if (plan_aborted(dsz)) return;
+    const uint64_t nbv = dsz ? dsz[PZ_NB] : nb;
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x)
-        nw[b] = (bq[b + 1] - bq[b] + wb - 1) / wb;
+        nw[b] = b < nbv ? (bq[b + 1] - bq[b] + wb - 1) / wb : 0;
 }
 
 // Word row w (of wb bits) holds packed rows [wq0[w], wq1[w]): bit p % wb of
 // row p / wb of its batch.
 __global__ void k_word_rows(uint64_t QD, const uint64_t *bpos, const uint64_t *bq, const uint64_t *wbase, uint32_t wb,
-                            uint64_t *wq0, uint64_t *wq1) {
+                            uint64_t *wq0, uint64_t *wq1, const uint64_t *__restrict__ dsz) {
+    if (plan_aborted(dsz)) return;
+    if (dsz) QD = dsz[PZ_QD];
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t b = bpos[q + 1] - 1;  // batch of packed row q
         const uint64_t p = q - bq[b];        // position inside the batch
@@ -780,14 +839,23 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
                                                const uint64_t *__restrict__ row_ptr,
                                                const uint32_t *__restrict__ row_deg,
                                                const uint32_t *__restrict__ S, uint32_t cols,
-                                               unsigned long long *st) {
+                                               unsigned long long *st, const uint64_t *__restrict__ dsz) {
     extern __shared__ unsigned long long lw[];
     __shared__ uint64_t rstart[kWave + 1];  // exclusive prefix of the rows' degrees
     __shared__ uint64_t rbase[kWave];       // first pair of each row in S
     __shared__ uint32_t zsh[2];  // nonzero words of the row (b = 32: of each half)
     const uint32_t tid = threadIdx.x, lane = lane_id();
+    if (plan_aborted(dsz)) return;
+    // planned: H is the capacity; rows from the actual count on are written as
+    // zeros (they add nothing to the Gram product)
+    const uint64_t Hv = dsz ? dsz[PZ_H] : H;
+    if (dsz) Hw = dsz[PZ_HW];
     unsigned long long nnz_acc = 0, f_acc = 0;  // this block's totals (thread 0)
     for (uint64_t w = blockIdx.x; w < H; w += gridDim.x) {
+        if (w >= Hv) {
+            for (uint64_t i = tid; i < ldw; i += kNT) W[w * ldw + i] = 0;
+            continue;
+        }
         if (tid < kWave) {
             uint64_t q0 = 0, q1 = 0, qi = 0;  // this lane's row: qi, if below q1
             if (wb == 64) {
@@ -914,8 +982,12 @@ __global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, con
 // pairs as one contiguous run (the row-by-row form of B = A^T A over the row
 // lists).  wnp[g] = pairs of list rows [64g, 64g + 64): one wave per group,
 // which is also one wave's share of the emission below.
-__global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint32_t *row_deg, uint64_t QL, uint64_t *wnp) {
+__global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint32_t *row_deg, uint64_t QL, uint64_t *wnp,
+                                  const uint64_t *__restrict__ dsz) {
+    if (plan_aborted(dsz)) return;
+    // planned: QL is the capacity; groups past the actual rows count nothing
     const uint64_t nw = (QL + kWave - 1) / kWave;
+    if (dsz) QL = dsz[PZ_QL];
     const uint32_t lane = lane_id();
     for (uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g < nw;
          g += ((uint64_t)gridDim.x * blockDim.x) / kWave) {
@@ -1018,8 +1090,11 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
                                                     const uint32_t *__restrict__ ls, uint64_t QL,
                                                     const uint64_t *__restrict__ wpo,
                                                     uint32_t *__restrict__ pairs, uint32_t npass, uint32_t width,
-                                                    unsigned long long *__restrict__ ghist) {
+                                                    unsigned long long *__restrict__ ghist,
+                                                    const uint64_t *__restrict__ dsz) {
     __shared__ uint32_t gh[kPairPasses][256];
+    if (plan_aborted(dsz)) return;
+    if (dsz) QL = dsz[PZ_QL];
     // per wave: the output stage, or (for waves whose pairs do not fit it)
     // the rows' first output words, degrees and first entries
     __shared__ uint64_t stgb[256 / kWave][kEmitStage / 2];
@@ -1121,6 +1196,95 @@ __global__ void k_bucket(const uint64_t *D, uint64_t ND, uint32_t sbits, uint32_
     }
 }
 
+// --- planned encode: sizes after each scan, checked against the capacities.
+// One thread each; a size above its capacity sets PZ_ABORT (every later
+// kernel of the encode then returns at once) and err bit 32.
+__global__ void k_plan_begin(const uint64_t *off, int32_t n, uint64_t Ncap, uint64_t *dsz, uint32_t *err) {
+    uint64_t N = n > 0 ? off[n] : 0;
+    for (int k = 0; k < PZ_COUNT; ++k) dsz[k] = 0;
+    err[0] = 0;
+    if (N > Ncap) {  // nothing is encoded (the sort sees no keys either)
+        dsz[PZ_ABORT] = 1;
+        dsz[PZ_OVER] = PZ_N + 1;
+        dsz[PZ_OVER_VALUE] = N;
+        err[0] = 32u;
+        N = 0;
+    }
+    dsz[PZ_N] = N;
+}
+
+__global__ void k_plan_rows(const uint64_t *offR, const uint64_t *offS, uint64_t nlc_cap, uint64_t Rcap,
+                            uint64_t *rptr, uint64_t *dsz, uint32_t *err) {
+    if (dsz[PZ_ABORT]) return;
+    const uint64_t R = offR[nlc_cap], NS = offS[nlc_cap];
+    if (R > Rcap) {
+        dsz[PZ_ABORT] = 1;
+        dsz[PZ_OVER] = PZ_R + 1;
+        dsz[PZ_OVER_VALUE] = R;
+        atomicOr(err, 32u);
+        return;
+    }
+    dsz[PZ_R] = R;
+    rptr[R] = NS;
+}
+
+__global__ void k_plan_split(const uint64_t *toff, uint64_t tile_cap, uint64_t QDcap, uint64_t QLcap, uint64_t *dsz,
+                             uint32_t *err) {
+    if (dsz[PZ_ABORT]) return;
+    const uint64_t QD = toff[tile_cap], QL = dsz[PZ_R] - QD;
+    if (QD > QDcap || QL > QLcap) {
+        dsz[PZ_ABORT] = 1;
+        dsz[PZ_OVER] = QD > QDcap ? PZ_QD + 1 : PZ_QL + 1;
+        dsz[PZ_OVER_VALUE] = QD > QDcap ? QD : QL;
+        atomicOr(err, 32u);
+        return;
+    }
+    dsz[PZ_QD] = QD;
+    dsz[PZ_QL] = QL;
+}
+
+__global__ void k_plan_batches(const uint64_t *bpos, uint64_t QDcap, uint64_t *bq, uint64_t *dsz) {
+    if (dsz[PZ_ABORT]) return;
+    const uint64_t nb = bpos[QDcap];  // the flags past QD are zero
+    dsz[PZ_NB] = nb;
+    bq[nb] = dsz[PZ_QD];
+}
+
+__global__ void k_plan_words(const uint64_t *wbase, uint64_t QDcap, uint32_t wb, uint64_t Hwcap, uint64_t Hcap,
+                             uint64_t *dsz, uint32_t *err) {
+    if (dsz[PZ_ABORT]) return;
+    const uint64_t Hw = wbase[QDcap], H = wb == 64 ? Hw : (Hw + 1) / 2;
+    if (Hw > Hwcap || H > Hcap) {
+        dsz[PZ_ABORT] = 1;
+        dsz[PZ_OVER] = PZ_HW + 1;
+        dsz[PZ_OVER_VALUE] = Hw;
+        atomicOr(err, 32u);
+        return;
+    }
+    dsz[PZ_HW] = Hw;
+    dsz[PZ_H] = H;
+}
+
+__global__ void k_plan_pairs(const uint64_t *npo, uint64_t gcap, uint64_t Pcap, uint64_t *dsz, uint32_t *err) {
+    if (dsz[PZ_ABORT]) return;
+    const uint64_t P = npo[gcap];
+    if (P > Pcap) {
+        dsz[PZ_ABORT] = 1;
+        dsz[PZ_OVER] = PZ_P + 1;
+        dsz[PZ_OVER_VALUE] = P;
+        atomicOr(err, 32u);
+        return;
+    }
+    dsz[PZ_P] = P;
+}
+
+// err bit 64: a set reaches the int32 bound (|X_i| >= limit)
+__global__ void k_plan_card(const int64_t *card, int32_t n, int64_t limit, uint32_t *err) {
+    bool over = false;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) over |= card[i] >= limit;
+    if (__ballot(over) && lane_id() == 0) atomicOr(err, 64u);
+}
+
 template <class F>
 void launch_1d(uint64_t work, hipStream_t s, F f) {
     const uint64_t blocks = std::min<uint64_t>(std::max<uint64_t>(div_up(work, 256), 1), 65536);
@@ -1146,7 +1310,7 @@ void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_
     {
         JAS_TIMED("build_keys", s);
         k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, keys, err, plan.npass,
-                                                      U - plan.top_bits, plan.width, ghist);
+                                                      U - plan.top_bits, plan.width, ghist, nullptr);
     }
     check_launch("build keys");
 }
@@ -1202,14 +1366,17 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             {
                 JAS_TIMED("range_starts", s);
                 k_range_starts<<<(uint32_t)div_up(nlc + 1, 256 / kWave), 256, 0, s>>>(keys.p, N, bsh, stride, nlc,
-                                                                                       rs.p, errL);
+                                                                                       rs.p, errL, nullptr);
                 k_range_check<<<(uint32_t)std::min<uint64_t>(div_up(nlc, 256), 4096), 256, 0, s>>>(
-                    keys.p, rs.p, nlc, bsh, lowbits, sbits, errL);
+                    keys.p, rs.p, nlc, bsh, lowbits, sbits, errL, nullptr, 0);
             }
             check_launch("range starts");
             JAS_HIP(hipMemcpyAsync(&herr, flags.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
-            if ((herr & 8u) == 0) break;
+            if ((herr & 8u) == 0) {
+                db->trace.stride = stride;
+                break;
+            }
         }
         if ((herr & 8u) == 0) {
             DevBuf<unsigned long long> dupc;
@@ -1234,11 +1401,13 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
                 if (herr & 16u)
                     k_local_cls<uint64_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
                                                                          (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
-                                                                         rid_g.p, rptr_g, dupc.p, rowsrep);
+                                                                         rid_g.p, rptr_g, dupc.p, rowsrep, nullptr, 0,
+                                                                         nullptr);
                 else
                     k_local_cls<uint32_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
                                                                          (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
-                                                                         rid_g.p, rptr_g, dupc.p, rowsrep);
+                                                                         rid_g.p, rptr_g, dupc.p, rowsrep, nullptr, 0,
+                                                                         nullptr);
                 k_sum_replicas<<<1, 64, 0, s>>>(rowsrep, kStatReplicas, st.p + ST_ROWS);
             }
             check_launch("local classify");
@@ -1257,6 +1426,9 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             NDk = t3[0];
             NS = t3[1];
             R = t3[2];
+            db->trace.local = true;
+            db->trace.wide = (herr & 16u) != 0;
+            db->trace.nlc = nlc;
             if (keep) Dk.alloc(NDk, s, &db->budget, false, "query index keys");
             rid_own.alloc(R, s, tb, true, "row ids");
             rptr_own.alloc(R + 1, s, tb, true, "row pointers");
@@ -1269,7 +1441,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
                 JAS_TIMED("local_move", s);
                 k_local_move<<<(uint32_t)std::min<uint64_t>(nlc, 65536), 256, 0, s>>>(
                     rs.p, nlc, offD.p, offS.p, offR.p, keys.p, rid_g.p, rptr_g, keep ? Dk.p : nullptr, ridp, rptrp,
-                    rdegp);
+                    rdegp, nullptr, 0);
             }
             check_launch("local move");
             {
@@ -1409,7 +1581,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         {
             JAS_TIMED("row_count", s);
             k_row_count<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, tcnt.p,
-                                                      reinterpret_cast<unsigned long long *>(lprep.p));
+                                                      reinterpret_cast<unsigned long long *>(lprep.p), nullptr);
             k_sum_replicas<<<1, 64, 0, s>>>(reinterpret_cast<const unsigned long long *>(lprep.p), kStatReplicas,
                                             st.p + ST_LISTPAIRS);
         }
@@ -1421,7 +1593,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         Lrow.alloc(QL, s, tb, true, "list rows");
         {
             JAS_TIMED("row_split", s);
-            k_row_split<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, toff.p, Drow.p, Lrow.p);
+            k_row_split<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, toff.p, Drow.p, Lrow.p, nullptr);
         }
         check_launch("row split");
     }
@@ -1438,7 +1610,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("batch_flag", st_);
-                k_batch_flag<<<b, 256, 0, st_>>>(Drow.p, ridp, QD, bbits, bs.p);
+                k_batch_flag<<<b, 256, 0, st_>>>(Drow.p, ridp, QD, bbits, bs.p, nullptr);
             }
         });
         check_launch("batch flags");
@@ -1447,14 +1619,14 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         scan_excl_u32(bs.p, bpos.p, QD, tmp.p, s);
         nb = to_host_u64(bpos.p + QD, s);
         bq.alloc(nb + 1, s, tb, true, "batch starts");
-        launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_start", st_); k_batch_start<<<b, 256, 0, st_>>>(bs.p, bpos.p, QD, bq.p); } });
+        launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_start", st_); k_batch_start<<<b, 256, 0, st_>>>(bs.p, bpos.p, QD, bq.p, nullptr); } });
         {
             JAS_TIMED("fill_u64", s);
             k_fill_u64<<<1, 1, 0, s>>>(bq.p + nb, 1, QD);
         }
         check_launch("batch starts");
         nw.alloc(nb, s, tb, true, "batch words");
-        launch_1d(nb, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_words", st_); k_batch_words<<<b, 256, 0, st_>>>(bq.p, nb, wb, nw.p); } });
+        launch_1d(nb, s, [&](uint32_t b, hipStream_t st_) { { JAS_TIMED("batch_words", st_); k_batch_words<<<b, 256, 0, st_>>>(bq.p, nb, wb, nw.p, nullptr); } });
         check_launch("batch words");
         wbase.alloc(nb + 1, s, tb, true, "word bases");
         tmp.release();
@@ -1467,7 +1639,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         launch_1d(QD, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("word_rows", st_);
-                k_word_rows<<<b, 256, 0, st_>>>(QD, bpos.p, bq.p, wbase.p, wb, wq0.p, wq1.p);
+                k_word_rows<<<b, 256, 0, st_>>>(QD, bpos.p, bq.p, wbase.p, wb, wq0.p, wq1.p, nullptr);
             }
         });
         check_launch("word rows");
@@ -1480,7 +1652,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         {
             JAS_TIMED("pack", s);
             k_pack<<<grid, kNT, cols * sizeof(unsigned long long), s>>>(db->W.p, ldw, H, Hw, wb, wq0.p, wq1.p,
-                                                                        Drow.p, rptrp, rdegp, Sp, cols, st.p);
+                                                                        Drow.p, rptrp, rdegp, Sp, cols, st.p, nullptr);
         }
         check_launch("pack");
     }
@@ -1500,7 +1672,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
             {
                 JAS_TIMED("list_npairs", st_);
-                k_list_wave_pairs<<<b, 256, 0, st_>>>(Lrow.p, rdegp, QL, np.p);
+                k_list_wave_pairs<<<b, 256, 0, st_>>>(Lrow.p, rdegp, QL, np.p, nullptr);
             }
         });
         check_launch("row pair counts");
@@ -1527,7 +1699,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         {
             JAS_TIMED("pair_emit", s);
             k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 8192), 256, 0, s>>>(
-                Lrow.p, rptrp, rdegp, Sp, QL, npo.p, pk.p, npass, width, gh.p);
+                Lrow.p, rptrp, rdegp, Sp, QL, npo.p, pk.p, npass, width, gh.p, nullptr);
         }
         check_launch("pair emit");
         const bool ok = radix_sort_onesweep_u32(pk, palt, P, 16, 16 + sb, width, gh.p, perr.p, s, tb);
@@ -1538,6 +1710,8 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             db->n_lpairs = P;
             db->pairs = std::move(pk);
             pairs_done = true;
+            db->trace.pairs = true;
+            db->trace.P = P;
         }
     }
     if (QL > 0 && !pairs_done) {
@@ -1598,6 +1772,15 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     JAS_HIP(hipMemcpyAsync(hst, st.p, sizeof(hst), hipMemcpyDeviceToHost, s));
     JAS_HIP(hipStreamSynchronize(s));
     jas_encode_stats &o = db->stats;
+    db->trace.N = N;
+    db->trace.ND = NDk;
+    db->trace.NS = NS;
+    db->trace.R = R;
+    db->trace.QD = QD;
+    db->trace.QL = QL;
+    db->trace.nb = nb;
+    db->trace.Hw = Hw;
+    db->trace.H = H;
     o.n_ids = N;
     o.n_pairs = NDk;
     o.n_rows = hst[ST_ROWS];
@@ -1614,6 +1797,189 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     o.word_pairs_F = hst[ST_F];
     o.list_pairs = hst[ST_LISTPAIRS];
     o.device_bytes = db->budget.held;
+}
+
+// The encode of a plan: the common path of jas_encode (single-pass scatters
+// on the top ID bits, ranges finished in LDS with the planned stride and key
+// width, the planned degree threshold, row lists as sorted pair words), every
+// size read from device memory and every buffer the plan's own.  Nothing is
+// read back and nothing allocated, so the whole sequence can be captured in a
+// HIP graph; what the eager path would have done differently (a fallback) or
+// a size above its capacity is flagged in p.err and reported afterwards.
+void encode_planned(PlanState &p, const uint64_t *ids, const uint64_t *offsets, hipStream_t s) {
+    const int32_t n = p.n;
+    const uint32_t sbits = p.sbits, U = p.U;
+    const uint64_t smask = sbits ? ((uint64_t(1) << sbits) - 1) : 0;
+    uint64_t *dsz = p.dsz.p;
+    uint32_t *err = p.err.p;
+    const uint64_t Ncap = p.Ncap;
+    auto fill = [&](void *ptr, uint64_t words) {
+        JAS_TIMED("fill_u64", s);
+        k_fill_u64<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(words, 256), 1024)), 256, 0, s>>>(
+            (uint64_t *)ptr, words, 0);
+    };
+    {
+        JAS_TIMED("plan_sizes", s);
+        k_plan_begin<<<1, 1, 0, s>>>(offsets, n, Ncap, dsz, err);
+    }
+    fill(p.ghist.p, (uint64_t)kGhistReplicas * kMaxPasses * 256);
+    fill(p.st.p, ST_N);
+    fill(p.dupc.p, (uint64_t)std::max<int32_t>(n, 1) + kStatReplicas);
+    fill(p.lprep.p, kStatReplicas);
+    check_launch("plan begin");
+    // keys and the global sort on the top ID bits
+    const uint64_t hi_mask = U >= 64 ? 0 : ~((uint64_t(1) << U) - 1);
+    {
+        JAS_TIMED("build_keys", s);
+        k_build_keys<<<(uint32_t)div_up(Ncap, kChunk), kNT, 0, s>>>(ids, offsets, n, Ncap, sbits, hi_mask, p.keys.p,
+                                                                     err, p.sort.npass, U - p.sort.top_bits,
+                                                                     p.sort.width, p.ghist.p, dsz);
+    }
+    check_launch("build keys (planned)");
+    uint64_t *K = p.keys.p, *F = p.alt.p;
+    if (p.sort.top_bits > 0) {
+        OnesweepBufs ob;
+        ob.gstart = p.os_gstart.p;
+        ob.maxima = p.os_maxima.p;
+        ob.status = p.os_status.p;
+        ob.ticket = p.os_ticket.p;
+        ob.status_words = p.os_status.n;
+        const uint32_t lo = sbits + U - p.sort.top_bits, hi = sbits + U;
+        radix_sort_onesweep_planned(K, F, dsz + PZ_N, Ncap, lo, hi, p.sort.width, p.ghist.p, err, ob, s);
+    }
+    // ranges of whole buckets, finished in LDS
+    const uint32_t lowbits = U - p.sort.top_bits;
+    const uint32_t bsh = sbits + lowbits;
+    const uint64_t nlc = p.nlc_cap;
+    {
+        JAS_TIMED("range_starts", s);
+        k_range_starts<<<(uint32_t)div_up(nlc + 1, 256 / kWave), 256, 0, s>>>(K, Ncap, bsh, p.stride, nlc, p.rs.p,
+                                                                               err, dsz);
+        k_range_check<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(nlc, 256), 4096)), 256, 0, s>>>(
+            K, p.rs.p, nlc, bsh, lowbits, sbits, err, dsz, p.stride);  // bit 16 matters only to narrow plans
+    }
+    check_launch("range starts (planned)");
+    const uint64_t ndup = (uint64_t)std::max<int32_t>(n, 1);
+    unsigned long long *rowsrep = p.dupc.p + ndup;
+    uint32_t *Sg = reinterpret_cast<uint32_t *>(F);
+    uint64_t *rptr_g = F + div_up(Ncap, 2);
+    {
+        JAS_TIMED(p.wide ? "local_cls_wide" : "local_cls", s);
+        if (p.wide)
+            k_local_cls<uint64_t><<<(uint32_t)nlc, kLNT, 0, s>>>(K, sbits, smask, bsh, lowbits, p.rs.p, (uint32_t)nlc,
+                                                                 p.cnt.p, 0, Sg, p.rid_g.p, rptr_g, p.dupc.p, rowsrep,
+                                                                 dsz, p.stride, err);
+        else
+            k_local_cls<uint32_t><<<(uint32_t)nlc, kLNT, 0, s>>>(K, sbits, smask, bsh, lowbits, p.rs.p, (uint32_t)nlc,
+                                                                 p.cnt.p, 0, Sg, p.rid_g.p, rptr_g, p.dupc.p, rowsrep,
+                                                                 dsz, p.stride, err);
+        k_sum_replicas<<<1, 64, 0, s>>>(rowsrep, kStatReplicas, p.st.p + ST_ROWS);
+    }
+    check_launch("local classify (planned)");
+    scan_excl_u32(p.cnt.p, p.offD.p, nlc, p.stmp.p, s);
+    scan_excl_u32(p.cnt.p + nlc, p.offS.p, nlc, p.stmp.p, s);
+    scan_excl_u32(p.cnt.p + 2 * nlc, p.offR.p, nlc, p.stmp.p, s);
+    {
+        JAS_TIMED("plan_sizes", s);
+        k_plan_rows<<<1, 1, 0, s>>>(p.offR.p, p.offS.p, nlc, p.Rcap, p.rptr.p, dsz, err);
+    }
+    {
+        JAS_TIMED("local_move", s);
+        k_local_move<<<(uint32_t)std::min<uint64_t>(nlc, 65536), 256, 0, s>>>(
+            p.rs.p, nlc, p.offD.p, p.offS.p, p.offR.p, K, p.rid_g.p, rptr_g, nullptr, p.rid.p, p.rptr.p, p.rdeg.p, dsz,
+            p.stride);
+    }
+    {
+        JAS_TIMED("card", s);
+        k_card_from_dups<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 1024)), 256, 0, s>>>(
+            offsets, p.dupc.p, n, reinterpret_cast<unsigned long long *>(p.card.p));
+        k_plan_card<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 1024)), 256, 0, s>>>(
+            p.card.p, n, (int64_t)card_limit(), err);
+    }
+    check_launch("local move (planned)");
+    // rows by degree
+    {
+        JAS_TIMED("row_count", s);
+        k_row_count<<<(uint32_t)p.tile_cap, kNT, 0, s>>>(p.rdeg.p, p.Rcap, p.dmin, p.tcnt.p, p.lprep.p, dsz);
+        k_sum_replicas<<<1, 64, 0, s>>>(p.lprep.p, kStatReplicas, p.st.p + ST_LISTPAIRS);
+    }
+    scan_excl_u32(p.tcnt.p, p.toff.p, p.tile_cap, p.stmp.p, s);
+    {
+        JAS_TIMED("plan_sizes", s);
+        k_plan_split<<<1, 1, 0, s>>>(p.toff.p, p.tile_cap, p.QDcap, p.QLcap, dsz, err);
+    }
+    {
+        JAS_TIMED("row_split", s);
+        k_row_split<<<(uint32_t)p.tile_cap, kNT, 0, s>>>(p.rdeg.p, p.Rcap, p.dmin, p.toff.p, p.Drow.p, p.Lrow.p, dsz);
+    }
+    check_launch("row split (planned)");
+    // packed rows
+    if (p.QDcap > 0) {
+        const uint64_t QDc = p.QDcap;
+        launch_1d(QDc, s, [&](uint32_t b, hipStream_t st_) {
+            JAS_TIMED("batch_flag", st_);
+            k_batch_flag<<<b, 256, 0, st_>>>(p.Drow.p, p.rid.p, QDc, p.batch_bits, p.bs.p, dsz);
+        });
+        scan_excl_u32(p.bs.p, p.bpos.p, QDc, p.stmp.p, s);
+        {
+            JAS_TIMED("plan_sizes", s);
+            k_plan_batches<<<1, 1, 0, s>>>(p.bpos.p, QDc, p.bq.p, dsz);
+        }
+        launch_1d(QDc, s, [&](uint32_t b, hipStream_t st_) {
+            JAS_TIMED("batch_start", st_);
+            k_batch_start<<<b, 256, 0, st_>>>(p.bs.p, p.bpos.p, QDc, p.bq.p, dsz);
+            k_batch_words<<<b, 256, 0, st_>>>(p.bq.p, QDc, p.word_bits, p.nw.p, dsz);
+        });
+        scan_excl_u64(p.nw.p, p.wbase.p, QDc, p.stmp.p, s);
+        {
+            JAS_TIMED("plan_sizes", s);
+            k_plan_words<<<1, 1, 0, s>>>(p.wbase.p, QDc, p.word_bits, p.Hwcap, p.Hcap, dsz, err);
+        }
+        launch_1d(QDc, s, [&](uint32_t b, hipStream_t st_) {
+            JAS_TIMED("word_rows", st_);
+            k_word_rows<<<b, 256, 0, st_>>>(QDc, p.bpos.p, p.bq.p, p.wbase.p, p.word_bits, p.wq0.p, p.wq1.p, dsz);
+        });
+        const uint64_t nchunk = div_up(p.ldw, (uint64_t)kPackCols);
+        const uint32_t cols = (uint32_t)(div_up(div_up(p.ldw, nchunk), 128) * 128);
+        {
+            JAS_TIMED("pack", s);
+            k_pack<<<(uint32_t)std::min<uint64_t>(p.Hcap, 4096), kNT, cols * sizeof(unsigned long long), s>>>(
+                p.W.p, p.ldw, p.Hcap, p.Hwcap, p.word_bits, p.wq0.p, p.wq1.p, p.Drow.p, p.rptr.p, p.rdeg.p,
+                reinterpret_cast<const uint32_t *>(F), cols, p.st.p, dsz);
+        }
+        check_launch("pack (planned)");
+    }
+    // row lists as pair words sorted by the smaller sample
+    if (p.QLcap > 0) {
+        const uint64_t QLc = p.QLcap;
+        launch_1d(QLc, s, [&](uint32_t b, hipStream_t st_) {
+            JAS_TIMED("list_npairs", st_);
+            k_list_wave_pairs<<<b, 256, 0, st_>>>(p.Lrow.p, p.rdeg.p, QLc, p.np.p, dsz);
+        });
+        scan_excl_u64(p.np.p, p.npo.p, p.gcap, p.stmp.p, s);
+        {
+            JAS_TIMED("plan_sizes", s);
+            k_plan_pairs<<<1, 1, 0, s>>>(p.npo.p, p.gcap, p.Pcap, dsz, err);
+        }
+        fill(p.gh.p, (uint64_t)kGhistReplicas * kMaxPasses * 256);
+        {
+            JAS_TIMED("pair_emit", s);
+            k_pair_emit<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(QLc, 256), 8192)), 256, 0, s>>>(
+                p.Lrow.p, p.rptr.p, p.rdeg.p, reinterpret_cast<const uint32_t *>(F), QLc, p.npo.p, p.pk.p,
+                p.pair_npass, p.pair_width, p.gh.p, dsz);
+        }
+        check_launch("pair emit (planned)");
+        OnesweepBufs ob;
+        ob.gstart = p.os2_gstart.p;
+        ob.maxima = p.os2_maxima.p;
+        ob.status = p.os2_status.p;
+        ob.ticket = p.os2_ticket.p;
+        ob.status_words = p.os2_status.n;
+        uint32_t *a = p.pk.p, *b = p.palt.p;
+        radix_sort_onesweep_u32_planned(a, b, dsz + PZ_P, p.Pcap, 16, 16 + p.pair_bits, p.pair_width, p.gh.p, err,
+                                        ob, s);
+        if (a != p.pairs_final) fail(JAS_EDEVICE, "planned pair sort ended in an unexpected buffer");
+    }
 }
 
 }  // namespace jas

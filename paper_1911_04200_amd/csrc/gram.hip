@@ -606,13 +606,16 @@ constexpr uint64_t kPairChunk = 16384;
 constexpr uint64_t kPairBlocks = 4096;
 
 __global__ __launch_bounds__(256) void k_pair_count(const uint32_t *__restrict__ pairs, uint64_t P, uint64_t chunk,
-                                                     uint32_t n, int32_t *__restrict__ B, int upper) {
+                                                     uint32_t n, int32_t *__restrict__ B, int upper,
+                                                     const uint64_t *__restrict__ dsz) {
     extern __shared__ uint32_t lds[];
     uint32_t *cnt = lds;                                         // n counters
     uint16_t *touched = reinterpret_cast<uint16_t *>(lds + n);  // n entries (n < 2^16)
     __shared__ uint32_t ntouched;
     __shared__ uint64_t seg_end;
+    if (dsz) P = min(P, dsz[PZ_P]);  // a plan's db: P is the capacity, the count is on the device
     const uint64_t lo = (uint64_t)blockIdx.x * chunk, hi = min(P, lo + chunk);
+    if (lo >= hi) return;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
     if (threadIdx.x == 0) ntouched = 0;
     __syncthreads();
@@ -949,7 +952,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         const size_t lds = (size_t)n * (sizeof(uint32_t) + sizeof(uint16_t));
         {
             JAS_TIMED("pair_count", s);
-            k_pair_count<<<(uint32_t)blocks, 256, lds, s>>>(db->pairs.p, db->n_lpairs, chunk, n, B, upper);
+            k_pair_count<<<(uint32_t)blocks, 256, lds, s>>>(db->pairs.p, db->n_lpairs, chunk, n, B, upper, db->dsz);
         }
         check_launch("row-list pairs");
     } else if (db->n_list > 0) {

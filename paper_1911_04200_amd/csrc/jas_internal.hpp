@@ -22,6 +22,29 @@ struct Error {
 };
 
 [[noreturn]] void fail(jas_status st, const std::string &msg);
+// The thread's last error message (jas_last_error).
+void set_last_error(const std::string &msg);
+// Runs f, turning any failure into a status and the thread's message.
+template <class F>
+jas_status guarded(F &&f) {
+    set_last_error("");
+    try {
+        f();
+        return JAS_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return JAS_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return JAS_EDEVICE;
+    } catch (...) {
+        set_last_error("unknown error");
+        return JAS_EDEVICE;
+    }
+}
 void check_hip(hipError_t e, const char *what);
 #define JAS_HIP(call) ::jas::check_hip((call), #call)
 
@@ -163,6 +186,20 @@ void temp_buf(DevBuf<T> &b, size_t count, hipStream_t s, Budget *budget, Arena *
 // The encoded database (jas_db).
 }  // namespace jas
 
+namespace jas {
+// What one eager encode decided and how large its intermediate arrays were:
+// a plan (plan.hip) repeats the same decisions with buffers of these sizes
+// plus headroom.
+struct EncodeTrace {
+    bool onesweep = false;    // the global sort ran as single-pass scatters
+    bool local = false;       // ranges finished in LDS (no global classification)
+    bool wide = false;        // 64-bit keys in LDS
+    bool pairs = false;       // row lists as sorted pair words
+    uint64_t stride = 0;      // range stride used
+    uint64_t N = 0, nlc = 0, ND = 0, NS = 0, R = 0, QD = 0, QL = 0, nb = 0, Hw = 0, H = 0, P = 0;
+};
+}  // namespace jas
+
 struct jas_db {
     int device = 0;
     int32_t n = 0;
@@ -191,6 +228,11 @@ struct jas_db {
     uint32_t ibits = 0;
     jas::DevBuf<uint64_t> keys;
     jas::DevBuf<uint64_t> bucket;     // (1 << ibits) + 1 entries
+    jas::EncodeTrace trace;
+    // a plan's db: device sizes (PlanSize) of its last encode; W has H rows of
+    // which the ones past the encoded count are zero, and the row-list pair
+    // count is dsz[PZ_P] (n_lpairs is the capacity).  Null for jas_encode's dbs.
+    const uint64_t *dsz = nullptr;
 };
 
 namespace jas {
@@ -227,6 +269,24 @@ bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t
 bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,
                              uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
                              hipStream_t s, Budget *b, Arena *ar = nullptr);
+// Buffers of a planned single-pass sort (see plan.hip): digit starts
+// [kMaxPasses][256], maxima [kMaxPasses], look-back status, ticket.
+struct OnesweepBufs {
+    uint64_t *gstart = nullptr, *maxima = nullptr;
+    uint32_t *status = nullptr, *ticket = nullptr;
+    uint64_t status_words = 0;
+};
+uint64_t onesweep_status_words(uint64_t N, bool u32);
+// Planned sorts: the key count is *dN (at most Ncap); keys/alt are swapped
+// as the passes go; no readback, no allocation.  err |= 4 when a digit total
+// is too large, err |= 2 when a look-back gave up.
+void radix_sort_onesweep_planned(uint64_t *&keys, uint64_t *&alt, const uint64_t *dN, uint64_t Ncap,
+                                 uint32_t lo_bit, uint32_t hi_bit, uint32_t width, const unsigned long long *ghist,
+                                 uint32_t *err, const OnesweepBufs &b, hipStream_t s);
+void radix_sort_onesweep_u32_planned(uint32_t *&keys, uint32_t *&alt, const uint64_t *dN, uint64_t Ncap,
+                                     uint32_t lo_bit, uint32_t hi_bit, uint32_t width,
+                                     const unsigned long long *ghist, uint32_t *err, const OnesweepBufs &b,
+                                     hipStream_t s);
 // Allocates w for N keys; returns the number of chunks (counts is [256][chunks]).
 uint64_t radix_prepare(RadixWork &w, uint64_t N, hipStream_t s, Budget *b, Arena *ar = nullptr);
 uint64_t radix_work_bytes(uint64_t N);
@@ -254,6 +314,35 @@ void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_
 // is used as scratch; offsets are the device CSR offsets.
 void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, const SortPlan &plan,
                    const uint64_t *offsets, hipStream_t s, Budget *tmpb);
+
+// A planned encode (plan.hip creates it, encode.hip runs it): the decisions
+// of one eager encode and buffers sized for them with headroom, so a like
+// collection encodes with no host synchronisation and no allocation.
+struct PlanState {
+    int32_t n = 0;
+    uint32_t U = 0, sbits = 0, batch_bits = 0, word_bits = 64, dmin = 2;
+    SortPlan sort;
+    uint64_t stride = 4096;
+    bool wide = false;
+    // capacities
+    uint64_t Ncap = 0, nlc_cap = 0, Rcap = 0, QDcap = 0, QLcap = 0, Hwcap = 0, Hcap = 0, Pcap = 0, tile_cap = 0,
+             gcap = 0, ldw = 0;
+    uint32_t pair_npass = 0, pair_width = 8, pair_bits = 0;
+    // device buffers (owned by the plan)
+    DevBuf<uint64_t> keys, alt, rs, offD, offS, offR, stmp, rid_g, rid, rptr, toff, Drow, Lrow, bpos, bq, nw, wbase,
+        wq0, wq1, npo, np, dsz;
+    DevBuf<uint32_t> err, cnt, rdeg, tcnt, bs, pk, palt;
+    DevBuf<unsigned long long> ghist, gh, dupc, lprep, st;
+    DevBuf<uint64_t> os_gstart, os_maxima, os2_gstart, os2_maxima;
+    DevBuf<uint32_t> os_status, os_ticket, os2_status, os2_ticket;
+    DevBuf<int64_t> card;
+    DevBuf<uint64_t> W;
+    uint32_t *pairs_final = nullptr;  // the buffer holding the sorted pair words after the pair sort
+};
+void encode_planned(PlanState &p, const uint64_t *ids, const uint64_t *offsets, hipStream_t s);
+enum { ST_PAIRS_ = 0, ST_ROWS_, ST_NNZW_, ST_F_, ST_LISTPAIRS_, ST_N_ };  // encode counters (encode.hip)
+constexpr uint32_t kStatReplicasPub = 64;
+constexpr uint64_t kSplitTilePub = 256 * 8;  // rows per row-split tile
 
 // Degree threshold: rows of degree >= the result are bit-packed, 2..result-1
 // kept as row lists; minimises the modelled Gram time (see tune.hip).
@@ -287,6 +376,13 @@ uint64_t query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids);
 uint64_t noalloc_max_ids();
 int32_t noalloc_max_queries();
 Arena noalloc_arena(std::unique_lock<std::mutex> &lk);
+
+// Sizes of a planned encode, in device memory (plan.hip): kernels read them
+// instead of host values, and every kernel returns at once when PZ_ABORT is
+// set (a size exceeded its buffer's capacity; nothing is written past a
+// buffer, the result is invalid and reported afterwards).
+enum PlanSize { PZ_N = 0, PZ_R, PZ_QD, PZ_QL, PZ_NB, PZ_HW, PZ_H, PZ_P, PZ_ABORT, PZ_OVER, PZ_OVER_VALUE, PZ_COUNT };
+__device__ __forceinline__ bool plan_aborted(const uint64_t *dsz) { return dsz && dsz[PZ_ABORT]; }
 
 // Largest |X_i| (distinct IDs of one set) the int32 intersections allow:
 // 2^31 - 1.  The environment variable JAS_TEST_CARD_LIMIT (a positive

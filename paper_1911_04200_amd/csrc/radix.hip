@@ -174,7 +174,7 @@ template <class K, int R, bool kTable>
 __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(
     const K *__restrict__ in, K *__restrict__ out, uint64_t N, uint32_t shift, uint32_t nbits,
     const uint64_t *__restrict__ gstart, uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
-    uint32_t ntiles, uint32_t *__restrict__ err) {
+    uint32_t ntiles, uint32_t *__restrict__ err, const uint64_t *__restrict__ dN) {
     __shared__ K stage[kOsNT * R];
     __shared__ uint32_t wcnt[kOsWaves][kRadix];
     __shared__ uint32_t tdp[kRadix];
@@ -182,6 +182,10 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
     __shared__ uint64_t sh[kOsWaves];
     __shared__ uint32_t tile_sh;
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    if (dN) {  // key count from device memory (planned encode): at most the buffers' N
+        N = min(N, *dN);
+        ntiles = (uint32_t)onesweep::num_tiles(N, kOsNT * R);
+    }
     const bool digit = tid < kRadix;  // this thread owns digit tid
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t lt = lanemask_lt();
@@ -344,7 +348,8 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
 
 // gstart[q][d] = exclusive scan over digits of the summed replicas; maxima[q] = largest digit total.
 __global__ __launch_bounds__(kNT) void k_digit_starts(const unsigned long long *__restrict__ ghist, uint32_t npass,
-                                                       uint64_t *__restrict__ gstart, uint64_t *__restrict__ maxima) {
+                                                       uint64_t *__restrict__ gstart, uint64_t *__restrict__ maxima,
+                                                       uint32_t *__restrict__ err) {
     __shared__ uint64_t sh[kWaves];
     __shared__ uint64_t tot_sh[kRadix];
     const uint32_t tid = threadIdx.x;
@@ -359,6 +364,7 @@ __global__ __launch_bounds__(kNT) void k_digit_starts(const unsigned long long *
             uint64_t m = 0;
             for (int d = 0; d < kRadix; ++d) m = m > tot_sh[d] ? m : tot_sh[d];
             maxima[q] = m;
+            if (err && m >= kValMask) atomicOr(err, 4u);  // planned sort: cannot run single-pass
         }
         __syncthreads();
     }
@@ -439,7 +445,7 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
     temp_buf(maxima, kMaxPasses, s, b, ar, "digit maxima");
     {
         JAS_TIMED("digit_starts", s);
-        k_digit_starts<<<1, kNT, 0, s>>>(ghist, npass, gstart.p, maxima.p);
+        k_digit_starts<<<1, kNT, 0, s>>>(ghist, npass, gstart.p, maxima.p, nullptr);
     }
     check_launch("digit starts");
     uint64_t hm[kMaxPasses];
@@ -478,14 +484,76 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
         {
             JAS_TIMED(name, s);
             k_radix_onesweep<K, Rounds, Table><<<grid, kOsNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
-                                                  ticket.p, (uint32_t)ntiles, err);
+                                                  ticket.p, (uint32_t)ntiles, err, nullptr);
         }
         check_launch("radix scatter (look-back)");
         swap_bufs(keys, alt);
     }
     return true;
 }
+// The same passes for a planned encode: the key count is read from *dN
+// (at most Ncap, the buffers' size) inside the kernels, every buffer is
+// given, nothing is read back and nothing allocated.  A digit total too large
+// for the 30-bit status counts sets bit 2 of err[0] (the result is then
+// invalid; the caller reports it after the stream completes).
+template <class K, int Rounds, bool Table>
+void onesweep_sort_planned(K *&keys, K *&alt, const uint64_t *dN, uint64_t Ncap, uint32_t lo_bit, uint32_t hi_bit,
+                           uint32_t width, const unsigned long long *ghist, uint32_t *err, const OnesweepBufs &b,
+                           hipStream_t s, const char *name) {
+    if (Ncap <= 1 || hi_bit <= lo_bit) return;
+    const uint32_t npass = (hi_bit - lo_bit + width - 1) / width;
+    if (npass > kMaxPasses || width < 1 || width > 8) fail(JAS_EUNSUPPORTED, "planned sort: bad digit plan");
+    const uint64_t ntiles = onesweep::num_tiles(Ncap, (uint32_t)kOsNT * Rounds);
+    if (b.status_words < onesweep::status_words(ntiles) || ntiles > 0xFFFFFFFFull)
+        fail(JAS_EDEVICE, "planned sort: status buffer too small");
+    {
+        JAS_TIMED("digit_starts", s);
+        k_digit_starts<<<1, kNT, 0, s>>>(ghist, npass, b.gstart, b.maxima, err);
+    }
+    check_launch("digit starts");
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 2);
+    for (uint32_t q = 0; q < npass; ++q) {
+        const uint32_t bit = lo_bit + width * q;
+        const uint32_t nbits = min(width, hi_bit - bit);
+        {
+            JAS_TIMED("fill_status", s);
+            k_fill32<<<(uint32_t)std::min<uint64_t>(div_up(onesweep::status_words(ntiles), 256), 65536), 256, 0, s>>>(
+                b.status, onesweep::status_words(ntiles));
+            k_fill32<<<1, 64, 0, s>>>(b.ticket, 1);
+        }
+        check_launch("look-back reset");
+        {
+            JAS_TIMED(name, s);
+            k_radix_onesweep<K, Rounds, Table><<<grid, kOsNT, 0, s>>>(keys, alt, Ncap, bit, nbits,
+                                                                       b.gstart + q * kRadix, b.status, b.ticket,
+                                                                       (uint32_t)ntiles, err, dN);
+        }
+        check_launch("radix scatter (planned)");
+        std::swap(keys, alt);
+    }
+}
+
 }  // namespace
+
+uint64_t onesweep_status_words(uint64_t N, bool u32) {
+    (void)u32;  // both key widths take 16 keys per lane
+    return onesweep::status_words(onesweep::num_tiles(N, (uint32_t)kOsNT * 16));
+}
+
+void radix_sort_onesweep_planned(uint64_t *&keys, uint64_t *&alt, const uint64_t *dN, uint64_t Ncap,
+                                 uint32_t lo_bit, uint32_t hi_bit, uint32_t width, const unsigned long long *ghist,
+                                 uint32_t *err, const OnesweepBufs &b, hipStream_t s) {
+    onesweep_sort_planned<uint64_t, 16, false>(keys, alt, dN, Ncap, lo_bit, hi_bit, width, ghist, err, b, s,
+                                               "radix_onesweep");
+}
+
+void radix_sort_onesweep_u32_planned(uint32_t *&keys, uint32_t *&alt, const uint64_t *dN, uint64_t Ncap,
+                                     uint32_t lo_bit, uint32_t hi_bit, uint32_t width,
+                                     const unsigned long long *ghist, uint32_t *err, const OnesweepBufs &b,
+                                     hipStream_t s) {
+    onesweep_sort_planned<uint32_t, 16, true>(keys, alt, dN, Ncap, lo_bit, hi_bit, width, ghist, err, b, s,
+                                              "pair_sort");
+}
 
 // 64-bit keys: 16 keys per lane, ballot ranking (the table form is no faster
 // for them and needs more registers); 32-bit pair words: table ranking.

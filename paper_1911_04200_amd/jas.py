@@ -37,7 +37,9 @@ STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERF
 
 # Every symbol include/jas.h declares.
 EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_relabel", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_noalloc", "jas_query_workspace_bytes",
-                  "jas_db_size", "jas_db_stats", "jas_db_part_size", "jas_db_read", "jas_db_free", "jas_last_error", "jas_version", "jas_timing_enable",
+                  "jas_db_size", "jas_db_stats", "jas_db_part_size", "jas_db_read", "jas_db_free",
+                  "jas_plan_create", "jas_plan_encode", "jas_plan_check", "jas_plan_db", "jas_plan_threshold",
+                  "jas_plan_tuning", "jas_plan_free", "jas_last_error", "jas_version", "jas_timing_enable",
                   "jas_timing_report", "jas_trim"])
 
 
@@ -115,6 +117,21 @@ def load(path: str = LIB_PATH):
     lib.jas_db_part_size.restype = u64
     lib.jas_db_read.argtypes = [vp, i32, u64, u64, vp]
     lib.jas_db_read.restype = ctypes.c_int
+    lib.jas_plan_create.argtypes = [vp, vp, i32, ctypes.POINTER(jas_encode_opts), ctypes.c_double, vp,
+                                    ctypes.POINTER(vp)]
+    lib.jas_plan_create.restype = ctypes.c_int
+    lib.jas_plan_encode.argtypes = [vp, vp, vp, vp]
+    lib.jas_plan_encode.restype = ctypes.c_int
+    lib.jas_plan_check.argtypes = [vp, vp, ctypes.POINTER(jas_encode_stats)]
+    lib.jas_plan_check.restype = ctypes.c_int
+    lib.jas_plan_db.argtypes = [vp]
+    lib.jas_plan_db.restype = vp
+    lib.jas_plan_threshold.argtypes = [vp]
+    lib.jas_plan_threshold.restype = u32
+    lib.jas_plan_tuning.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_double), i32]
+    lib.jas_plan_tuning.restype = i32
+    lib.jas_plan_free.argtypes = [vp]
+    lib.jas_plan_free.restype = None
     lib.jas_db_free.argtypes = [vp]
     lib.jas_db_free.restype = None
     lib.jas_last_error.restype = ctypes.c_char_p
@@ -257,6 +274,57 @@ def jas_gram_variants() -> int:
 def jas_db_stats(db) -> dict:
     st = jas_encode_stats()
     _check(load().jas_db_stats(_h(db), ctypes.byref(st)))
+    return st.to_dict()
+
+
+class Plan:
+    """Owns a jas_plan handle; .db is its (plan-owned) encoded database."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    @property
+    def db(self) -> int:
+        return int(load().jas_plan_db(self.handle))
+
+    @property
+    def threshold(self) -> int:
+        return int(load().jas_plan_threshold(self.handle))
+
+    def tuning(self) -> list:
+        lib = load()
+        k = lib.jas_plan_tuning(self.handle, None, None, 0)
+        t = (ctypes.c_uint32 * max(k, 1))()
+        ms = (ctypes.c_double * max(k, 1))()
+        lib.jas_plan_tuning(self.handle, t, ms, k)
+        return [(int(t[i]), float(ms[i])) for i in range(k)]
+
+    def close(self):
+        if self.handle:
+            load().jas_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def jas_plan_create(ids, offsets, n: int, opts: jas_encode_opts, headroom: float = 0.25, stream=None) -> Plan:
+    out = ctypes.c_void_p()
+    _check(load().jas_plan_create(_ptr(ids), _ptr(offsets), n, ctypes.byref(opts), float(headroom), _stream(stream),
+                                  ctypes.byref(out)))
+    return Plan(out.value)
+
+
+def jas_plan_encode(plan, ids, offsets, stream=None):
+    _check(load().jas_plan_encode(_h(plan), _ptr(ids), _ptr(offsets), _stream(stream)))
+
+
+def jas_plan_check(plan, stream=None) -> dict:
+    st = jas_encode_stats()
+    _check(load().jas_plan_check(_h(plan), _stream(stream), ctypes.byref(st)))
     return st.to_dict()
 
 
