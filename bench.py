@@ -299,6 +299,53 @@ def run_streamed(args):
     print(json.dumps(out), flush=True)
 
 
+def time_captured(args, ids_d, off_d, n, opts, flags, B, card, den, J, eager_ms):
+    """The same step as one HIP graph: an encode plan made from these inputs,
+    then plan encode + Gram + finalize captured once and replayed.  The
+    replay's outputs are compared with the eager step's (left in B, den, J)."""
+    import torch
+
+    from paper_1911_04200_amd import jas as cabi
+
+    torch.cuda.synchronize()
+    ref = {"B": B.clone(), "den": den.clone(), "J": J.clone(), "card": card.clone()}
+    t = time.perf_counter()
+    plan = cabi.jas_plan_create(ids_d, off_d, n, opts, headroom=args.plan_headroom)
+    create_s = time.perf_counter() - t
+    db = plan.db
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # eager once on the plan's db: tunes the Gram tiles for its shape
+        cabi.jas_plan_encode(plan, ids_d, off_d, s)
+        cabi.jas_gram(db, flags | (cabi.JAS_TUNE if args.path == "auto" else 0), s, B, card, den, J)
+    s.synchronize()
+    cabi.jas_plan_check(plan, s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        cabi.jas_plan_encode(plan, ids_d, off_d, s)
+        cabi.jas_gram(db, flags, s, B, card, den, J)
+    for w in range(args.warmup):
+        g.replay()
+        torch.cuda.synchronize()
+    log("[bench] captured step: graph built and warmed up")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = cabi.jas_plan_check(plan, s)
+    same = all(torch.equal(ref[k], v) for k, v in (("B", B), ("den", den), ("J", J), ("card", card)))
+    log(f"[bench] {args.steps} captured steps done (outputs equal to the eager step's: {same})")
+    del g
+    plan.close()
+    ms = (t1 - t0) / args.steps * 1e3
+    pairs = n * (n + 1) // 2
+    return {"ms_per_step": ms, "value": pairs / (ms / 1e3), "unit": "pairs/s", "eager_ms_per_step": eager_ms,
+            "speedup_vs_eager": eager_ms / ms, "outputs_equal_eager": same, "plan_headroom": args.plan_headroom,
+            "plan_create_s": create_s, "dense_min_degree": st["dense_min_degree"]}
+
+
 def run_all_pairs(args, workload: str, upper: bool):
     """Time the all-pairs step (encode + Gram, inputs resident in HBM) on one
     full-size workload: (summary dict, encode stats, spec, N)."""
@@ -421,6 +468,14 @@ def run_all_pairs(args, workload: str, upper: bool):
              else None,
              "encode_stats": st, "kernels": kernels, "host_phases": host_phases}
 
+    captured = None
+    if workload == "batching" and args.captured:
+        try:
+            captured = time_captured(args, ids_d, off_d, n, opts, flags, B, card, den, J, sec * 1e3)
+        except Exception as e:  # reported, not fatal to the eager line
+            captured = {"error": repr(e)}
+    extra["captured"] = captured
+
     del ids_d, B, den, J
     cabi.jas_trim()
     summary = {"value": value, "unit": "pairs/s", "ms_per_step": sec * 1e3, "steps": args.steps,
@@ -460,6 +515,9 @@ def main():
     ap.add_argument("--kmer-front-end", action="store_true",
                     help="time the GPU k-mer front end instead (128 genomes of 4 Mbases, k = 31, canonical): "
                          "bases/s, inputs resident in HBM")
+    ap.add_argument("--captured", type=int, default=1,
+                    help="batching form: also time the step as one replayed HIP graph through an encode plan")
+    ap.add_argument("--plan-headroom", type=float, default=0.05, help="capacity headroom of that plan")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied device-to-device before the steps: a plain copy of known size that scales "
                          "the HBM byte counters of a profiler run")
@@ -490,7 +548,7 @@ def main():
         for name in ("precision", "batching"):
             try:
                 r, _, _, _ = run_all_pairs(args, name, name == "batching")
-                r["detail"] = {k: r["detail"][k] for k in ("gram_ms", "gram_autotune_ms", "encode_stats")} | {
+                r["detail"] = {k: r["detail"][k] for k in ("gram_ms", "gram_autotune_ms", "encode_stats", "captured")} | {
                     "kernels": {k: v for k, v in r["detail"]["kernels"].items() if v["ms_per_step"] >= 0.5}}
                 others[name] = r
             except Exception as e:  # reported, not fatal to the main line
