@@ -515,6 +515,8 @@ def main():
     ap.add_argument("--kmer-front-end", action="store_true",
                     help="time the GPU k-mer front end instead (128 genomes of 4 Mbases, k = 31, canonical): "
                          "bases/s, inputs resident in HBM")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving stream (--serving-requests after the warm-up and saturation runs)")
     ap.add_argument("--captured", type=int, default=1,
                     help="batching form: also time the step as one replayed HIP graph through an encode plan")
     ap.add_argument("--plan-headroom", type=float, default=0.05, help="capacity headroom of that plan")
@@ -534,6 +536,13 @@ def main():
     import synth
     from paper_1911_04200_amd import jas as cabi
 
+    if args.serving_only:
+        out = run_serving(args.serving_requests, args.serving_saturation)
+        print(json.dumps({"metric": "serving requests/s (resident db, Poisson arrivals)",
+                          "value": out["requests_per_s"], "unit": "requests/s", "n_gpus": 1,
+                          "higher_is_better": True, "data": "synthetic (seeded counter-based generator, synth/)",
+                          "serving": out}), flush=True)
+        return
     if args.stream_part_bits > 0:
         run_streamed(args)
         return
