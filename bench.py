@@ -97,6 +97,76 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
     return None
 
 
+def kernel_label(name: str) -> str:
+    """The timing label of a HIP kernel's name as rocprofv3 prints it."""
+    base = name.split("::")[-1].split("(")[0]
+    tmpl = base.split("<", 1)[1] if "<" in base else ""
+    base = base.split("<")[0]
+    base = base[2:] if base.startswith("k_") else base
+    if base == "radix_onesweep" and tmpl.startswith("unsigned int"):
+        return "pair_sort"  # the same kernel on 32-bit pair words
+    if base in ("gram_fp4_wide",):
+        return "gram_fp4"
+    if base in ("gram_mfma_wide",):
+        return "gram_mfma"
+    if base == "local_cls" and tmpl.startswith("unsigned long"):
+        return "local_cls_wide"
+    return base
+
+
+def write_traffic(fetch_dir: str, write_dir: str, workload: str, copy_mib: int):
+    """profiles/traffic.json entries of one workload from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, csv) of one bench step with no warm-up and the
+    copy calibration: per kernel label, bytes per dispatch, each counter scaled
+    by what it reads for the calibration copy of copy_mib MiB.  Prints a table."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+        out = {}
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = int(r["Dispatch_Id"])
+            out.setdefault(k, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        return out
+
+    fetch, write = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+    copy_bytes = copy_mib * 1024.0 * 1024.0
+    cf = max(v for name, v in fetch.values() if "copyBuffer" in name) * 1024.0
+    cw = max(v for name, v in write.values() if "copyBuffer" in name) * 1024.0
+    ff, wf = copy_bytes / cf, copy_bytes / cw
+    agg = {}
+    for name, v in fetch.values():
+        if "copyBuffer" in name:
+            continue
+        agg.setdefault(kernel_label(name), [0, 0.0, 0.0])
+        a = agg[kernel_label(name)]
+        a[0] += 1
+        a[1] += v * 1024.0 * ff
+    for name, v in write.values():
+        if "copyBuffer" in name or kernel_label(name) not in agg:
+            continue
+        agg[kernel_label(name)][2] += v * 1024.0 * wf
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(tf)) if os.path.exists(tf) else {}
+    rec = {k: v for k, v in rec.items() if not k.endswith(":" + workload)}
+    print(f"| kernel | dispatches | read GB/dispatch | written GB/dispatch |  (fetch x {ff:.3f}, write x {wf:.3f})")
+    print("|---|---|---|---|")
+    for lab, (c, rd, wr) in sorted(agg.items(), key=lambda kv: -(kv[1][1] + kv[1][2]) / kv[1][0]):
+        if (rd + wr) / c < 0.1e9:
+            continue
+        print(f"| {lab} | {c} | {rd / c / 1e9:.2f} | {wr / c / 1e9:.2f} |")
+        rec[f"{lab}:{workload}"] = {"bytes_per_launch": round((rd + wr) / c / 1e9, 3), "unit": "GB",
+                                    "read_GB": round(rd / c / 1e9, 3), "written_GB": round(wr / c / 1e9, 3),
+                                    "source_hash": kernel_source_hash(lab), "fetch_factor": ff,
+                                    "write_factor": wf}
+    with open(tf, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+
+
 def cpu_baseline(spec, k: int, seed: int = 5):
     """The oracle timed on a bounded sample: k sets of the workload, all k(k+1)/2 pairs."""
     import numpy as np
@@ -520,10 +590,16 @@ def main():
     ap.add_argument("--captured", type=int, default=1,
                     help="batching form: also time the step as one replayed HIP graph through an encode plan")
     ap.add_argument("--plan-headroom", type=float, default=0.05, help="capacity headroom of that plan")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU: write profiles/traffic.json entries of --workload from two rocprofv3 --pmc csv "
+                         "runs (FETCH_SIZE, WRITE_SIZE) of one step with --warmup 0 and --copy-calibration")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied device-to-device before the steps: a plain copy of known size that scales "
                          "the HBM byte counters of a profiler run")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload, args.copy_calibration or 4096)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",

@@ -33,6 +33,22 @@ __global__ void k_fill_i32(int32_t *p, uint64_t len, int32_t v) {
         p[i] = v;
 }
 
+// The chip's 8 XCDs each have their own L2, and workgroups go to them
+// round-robin by linear id (x fastest), so consecutive ids land on different
+// XCDs.  Renumbered so that XCD x runs the ids x*per, x*per + 1, ... in turn,
+// all tile pairs of one K range run on one XCD and read that range's column
+// slabs through its L2 once instead of once per XCD.  A bijection of the
+// grid (ids past the last multiple of 8 keep their own number).
+constexpr uint64_t kXcds = 8;
+__device__ __forceinline__ void xcd_pair_split(uint32_t &pair, uint64_t &split) {
+    const uint64_t nx = gridDim.x, total = nx * gridDim.y;
+    const uint64_t L = (uint64_t)blockIdx.y * nx + blockIdx.x;
+    const uint64_t per = total / kXcds;
+    const uint64_t V = L < per * kXcds ? (L % kXcds) * per + L / kXcds : L;
+    pair = (uint32_t)(V % nx);
+    split = V / nx;
+}
+
 // Thread (ty, tx) of a 16 x 16 grid owns rows 32c + 2ty + e and columns
 // 32c + 2tx + e (c = 0..3, e = 0..1) of the 128 x 128 tile: every LDS read is
 // a 16-byte load, consecutive lanes read consecutive 16-byte pieces.
@@ -41,8 +57,10 @@ __global__ __launch_bounds__(kNT) void k_gram_popc(const uint64_t *__restrict__ 
                                                     int32_t *__restrict__ B, int upper) {
     __shared__ ulonglong2 As[kKC][kT / 2];
     __shared__ ulonglong2 Bs[kKC][kT / 2];
-    // blockIdx.x enumerates the tile pairs I <= J row by row
-    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    // the (renumbered) block enumerates the tile pairs I <= J row by row, then the K ranges
+    uint32_t p, I = 0, rowlen = nt;
+    uint64_t split;
+    xcd_pair_split(p, split);
     while (p >= rowlen) {
         p -= rowlen;
         ++I;
@@ -50,7 +68,7 @@ __global__ __launch_bounds__(kNT) void k_gram_popc(const uint64_t *__restrict__ 
     }
     const uint32_t Jt = I + p;
     const uint32_t I0 = I * kT, J0 = Jt * kT;
-    const uint64_t k0 = (uint64_t)blockIdx.y * kper;
+    const uint64_t k0 = split * kper;
     const uint64_t k1 = min(H, k0 + kper);
     if (k0 >= k1) return;
     const uint32_t tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
@@ -171,9 +189,10 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WP
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
     __shared__ unsigned long long lut[256];
-    // blockIdx.x enumerates the tile pairs I <= J row by row, blockIdx.y the K range
-    const uint64_t split = blockIdx.y;
-    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    // the (renumbered) block enumerates the tile pairs I <= J row by row, then the K ranges
+    uint32_t p, I = 0, rowlen = nt;
+    uint64_t split;
+    xcd_pair_split(p, split);
     while (p >= rowlen) {
         p -= rowlen;
         ++I;
@@ -272,8 +291,9 @@ __global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
     __shared__ unsigned long long lut[256];
-    const uint64_t split = blockIdx.y;
-    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    uint32_t p, I = 0, rowlen = nt;
+    uint64_t split;
+    xcd_pair_split(p, split);
     while (p >= rowlen) {
         p -= rowlen;
         ++I;
@@ -406,8 +426,9 @@ __global__ __launch_bounds__(kMfmaNT) __attribute__((amdgpu_waves_per_eu(WPE, WP
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
     __shared__ uint32_t lut[256 * COPIES];
-    const uint64_t split = blockIdx.y;
-    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    uint32_t p, I = 0, rowlen = nt;
+    uint64_t split;
+    xcd_pair_split(p, split);
     while (p >= rowlen) {
         p -= rowlen;
         ++I;
@@ -496,8 +517,9 @@ __global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
     __shared__ uint32_t lut[256];
-    const uint64_t split = blockIdx.y;
-    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
+    uint32_t p, I = 0, rowlen = nt;
+    uint64_t split;
+    xcd_pair_split(p, split);
     while (p >= rowlen) {
         p -= rowlen;
         ++I;
