@@ -139,14 +139,14 @@ def write_traffic(fetch_dir: str, write_dir: str, workload: str, copy_mib: int):
     ff, wf = copy_bytes / cf, copy_bytes / cw
     agg = {}
     for name, v in fetch.values():
-        if "copyBuffer" in name:
+        if "jas::" not in name:  # the calibration copy, torch's own kernels
             continue
         agg.setdefault(kernel_label(name), [0, 0.0, 0.0])
         a = agg[kernel_label(name)]
         a[0] += 1
         a[1] += v * 1024.0 * ff
     for name, v in write.values():
-        if "copyBuffer" in name or kernel_label(name) not in agg:
+        if "jas::" not in name or kernel_label(name) not in agg:
             continue
         agg[kernel_label(name)][2] += v * 1024.0 * wf
     tf = os.path.join(ROOT, "profiles", "traffic.json")
