@@ -416,6 +416,73 @@ def time_captured(args, ids_d, off_d, n, opts, flags, B, card, den, J, eager_ms)
             "plan_create_s": create_s, "dense_min_degree": st["dense_min_degree"]}
 
 
+def run_occupancy(workloads):
+    """How much of the dense tile work a skip of empty blocks could save: the
+    full-size encoding's words read back, per (K block of word rows x 128
+    columns) whether any word is nonzero, and the executed word pairs of a Gram
+    that skipped the empty blocks, over F; also with the word rows and the
+    columns reordered by their nonzero counts, and with the columns grouped by
+    the generator's cluster (known to the generator only).  One line per case."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1911_04200_amd import jas as cabi
+
+    def skip_cost(nzm, n, nt, KB, T=128):
+        nk = math.ceil(nzm.shape[0] / KB)
+        m = torch.nn.functional.pad(nzm.to(torch.uint8), (0, nt * T - n, 0, nk * KB - nzm.shape[0]))
+        occ = m.view(nk, KB, nt, T).amax(dim=(1, 3)).to(torch.float64)
+        s = occ.sum(dim=1)
+        both = (s * s + s) / 2  # tile pairs I <= J with both blocks occupied (o in {0, 1})
+        return 1.0 - float(occ.mean()), float(both.sum()) * KB * T * T
+
+    out = {}
+    for name in workloads:
+        spec = synth.workload(name)
+        n = spec.n
+        off = synth.offsets(spec)
+        N = int(off[-1])
+        host = torch.empty(N, dtype=torch.int64, pin_memory=True)
+        synth.generate(spec, out=host.numpy().view(np.uint64))
+        ids = host.cuda()
+        offd = torch.from_numpy(off.view(np.int64)).cuda()
+        del host
+        db, st = cabi.jas_encode(ids, offd, n, cabi.jas_encode_opts(spec.universe_bits, synth.BATCH_BITS[name], 0, 0, 0),
+                                 None)
+        del ids
+        H, stride = st["w_rows"], st["w_stride"]
+        rec = {"n": n, "word_rows": H, "threshold": st["dense_min_degree"]}
+        if H == 0:
+            db.close()
+            out[name] = rec
+            continue
+        W = torch.from_numpy(cabi.jas_db_read(db, cabi.JAS_DB_WORDS).view(np.int64)).cuda().view(H, stride)[:, :n]
+        db.close()
+        nz = W != 0
+        del W
+        z = nz.sum(dim=1, dtype=torch.int64)
+        F = int((z * (z + 1) // 2).sum())
+        nt = math.ceil(n / 128)
+        dense = H * (nt * (nt + 1) // 2) * 128 * 128
+        rec.update({"density": float(z.sum()) / (H * n), "F": F, "W_over_F": dense / F})
+        colw = nz.sum(dim=0)
+        cl = torch.tensor([synth.plan(spec, i)[3] for i in range(n)], device=nz.device)
+        orders = {"stored": nz,
+                  "rows and columns by nonzero count": nz[torch.argsort(z, descending=True)][:, torch.argsort(colw, descending=True)],
+                  "columns by cluster, rows by count": nz[torch.argsort(z, descending=True)][:, torch.argsort(cl * (n + 1) + (n - colw.clamp(max=n)), stable=True)]}
+        for oname, m in orders.items():
+            for KB in (4, 16, 64):
+                e, ws = skip_cost(m, n, nt, KB)
+                rec[f"{oname}, {KB} rows"] = {"empty_blocks": e, "W_skip_over_F": ws / F}
+        del nz, orders
+        torch.cuda.empty_cache()
+        cabi.jas_trim()
+        out[name] = rec
+        log(f"[occupancy] {name}: {json.dumps(rec)}")
+    print(json.dumps({"occupancy": out}), flush=True)
+
+
 def run_all_pairs(args, workload: str, upper: bool):
     """Time the all-pairs step (encode + Gram, inputs resident in HBM) on one
     full-size workload: (summary dict, encode stats, spec, N)."""
@@ -585,6 +652,8 @@ def main():
     ap.add_argument("--kmer-front-end", action="store_true",
                     help="time the GPU k-mer front end instead (128 genomes of 4 Mbases, k = 31, canonical): "
                          "bases/s, inputs resident in HBM")
+    ap.add_argument("--occupancy", nargs="+", metavar="WORKLOAD",
+                    help="report the packed words' block occupancy of these full-size workloads (no timing)")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving stream (--serving-requests after the warm-up and saturation runs)")
     ap.add_argument("--captured", type=int, default=1,
@@ -612,6 +681,9 @@ def main():
     import synth
     from paper_1911_04200_amd import jas as cabi
 
+    if args.occupancy:
+        run_occupancy(args.occupancy)
+        return
     if args.serving_only:
         out = run_serving(args.serving_requests, args.serving_saturation)
         print(json.dumps({"metric": "serving requests/s (resident db, Poisson arrivals)",

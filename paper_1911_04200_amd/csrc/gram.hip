@@ -38,7 +38,9 @@ __global__ void k_fill_i32(int32_t *p, uint64_t len, int32_t v) {
 // XCDs.  Renumbered so that XCD x runs the ids x*per, x*per + 1, ... in turn,
 // all tile pairs of one K range run on one XCD and read that range's column
 // slabs through its L2 once instead of once per XCD.  A bijection of the
-// grid (ids past the last multiple of 8 keep their own number).
+// grid (ids past the last multiple of 8 keep their own number).  Used by the
+// 128 x 128 kernels (paperlike fp4: 30.2 -> 4.9 GB fetched, same time); the
+// 256 x 256 kernels measured 2-4 % slower with it and keep launch order.
 constexpr uint64_t kXcds = 8;
 __device__ __forceinline__ void xcd_pair_split(uint32_t &pair, uint64_t &split) {
     const uint64_t nx = gridDim.x, total = nx * gridDim.y;
@@ -291,9 +293,8 @@ __global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
     __shared__ unsigned long long lut[256];
-    uint32_t p, I = 0, rowlen = nt;
-    uint64_t split;
-    xcd_pair_split(p, split);
+    const uint64_t split = blockIdx.y;
+    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
     while (p >= rowlen) {
         p -= rowlen;
         ++I;
@@ -517,9 +518,8 @@ __global__ __launch_bounds__(kWideNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
     const uint64_t *__restrict__ W, uint64_t ldw, uint64_t H, uint64_t kper, uint32_t nt, uint32_t n,
     int32_t *__restrict__ B, int upper) {
     __shared__ uint32_t lut[256];
-    uint32_t p, I = 0, rowlen = nt;
-    uint64_t split;
-    xcd_pair_split(p, split);
+    const uint64_t split = blockIdx.y;
+    uint32_t p = blockIdx.x, I = 0, rowlen = nt;
     while (p >= rowlen) {
         p -= rowlen;
         ++I;
