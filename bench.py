@@ -597,9 +597,9 @@ def run_all_pairs(args, workload: str, upper: bool):
     # word-pair rates of the popcount Gram
     gram_ms = (kt.get("gram_popc", (0, 0.0))[1] + kt.get("gram_mfma", (0, 0.0))[1] +
                kt.get("gram_fp4", (0, 0.0))[1]) / max(args.steps, 1)
-    nt = math.ceil(n / 128)
-    executed = st["n_word_rows"] * (nt * (nt + 1) // 2) * 128 * 128
+    executed = st["word_pairs_W"]  # whole 128 x 128 tiles over every stored word row
     extra = {"gram_ms": gram_ms, "gram_autotune_ms": tune_ms,
+             "word_pairs_W_over_F": (executed / st["word_pairs_F"]) if st["word_pairs_F"] else None,
              "G_bit_ANDs_per_s_executed": (64.0 * executed / (gram_ms / 1e3) / 1e9) if gram_ms else None,
              "G_bit_ANDs_per_s_algorithmic_F": (64.0 * st["word_pairs_F"] / (gram_ms / 1e3) / 1e9) if gram_ms
              else None,

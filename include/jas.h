@@ -44,6 +44,7 @@ typedef enum {
     JAS_ENOMEM = -2,       /* device allocation failed or the HBM budget is exceeded */
     JAS_EOVERFLOW = -3,    /* a set has 2^31 or more distinct IDs (int32 B would overflow) */
     JAS_EDEVICE = -4,      /* a HIP runtime call failed (message names it) */
+    JAS_EBUSY = -5,        /* a shared resource is in use and the caller asked not to wait (JAS_NO_WAIT) */
     JAS_EUNSUPPORTED = -6  /* valid request this build does not support (message says why) */
 } jas_status;
 
@@ -56,6 +57,8 @@ typedef enum {
 #define JAS_TUNE 0x80u          /* jas_gram: time the MFMA tile variants on this db first (see jas_gram) */
 #define JAS_ACCUMULATE 0x100u   /* jas_gram: add this db's counts into B and card (one row batch of many) */
 #define JAS_CANONICAL 0x200u    /* jas_kmers: each k-mer as the smaller of itself and its reverse complement */
+#define JAS_NO_WAIT 0x400u      /* jas_query_noalloc: JAS_EBUSY at once, instead of waiting, while another call
+                                   holds this process's fixed workspace */
 /* jas_gram: run MFMA tile variant v, 0 <= v < jas_gram_variants() (bits 16..23 hold v + 1) */
 #define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)
 
@@ -93,6 +96,11 @@ typedef struct {
     uint64_t w_rows;        /* rows of the stored word array (JAS_DB_WORDS): h for b = 64, ceil(h/2) for 32 */
     uint64_t w_stride;      /* 64-bit elements per stored row (n rounded up to a multiple of 128) */
     uint64_t n_list_pairs;  /* entries of JAS_DB_LIST_PAIRS */
+    uint64_t dense_tiles;   /* work units of the packed Gram: (stored word row, pair I <= J of 128-column
+                               tiles), w_rows * T with T = t(t+1)/2, t = ceil(n/128); 0 without packed rows.
+                               The row lists have no tiles: their work is list_pairs */
+    uint64_t word_pairs_W;  /* 64-bit word pairs those units multiply, dense_tiles * 128^2 (for b = 64 at
+                               least word_pairs_F: whole tiles run, zero words included) */
 } jas_encode_stats;
 
 /*
@@ -307,16 +315,17 @@ jas_status jas_query(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_
  * jas_query_noalloc -- jas_query for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, results and errors as jas_query, with
- * device pointers only (flags must be 0), but every temporary comes from a
+ * device pointers only (flags: 0 or JAS_NO_WAIT), but every temporary comes from a
  * fixed workspace of 136 MiB that the library holds on each device it runs
  * on until the process ends: no device memory is allocated or freed.  It
  * takes at most 65,536 query sets and 2^23 query IDs (entries, repeats
  * included) per call; larger requests fail with JAS_ENOMEM before any work
  * is enqueued.  Calls share the workspace, so the library serialises them
  * (a lock per process) and each returns only after its work on hip_stream
- * has finished (synchronises hip_stream); the workspace keeps the last
- * call's contents, and everything that must start at zero is cleared by the
- * call itself.
+ * has finished (synchronises hip_stream); with JAS_NO_WAIT a call that finds
+ * the workspace in use returns JAS_EBUSY at once, before any work is
+ * enqueued.  The workspace keeps the last call's contents, and everything
+ * that must start at zero is cleared by the call itself.
  */
 jas_status jas_query_noalloc(const jas_db *db, const uint64_t *q_ids, const uint64_t *q_offsets, int32_t nq,
                              uint32_t flags, void *hip_stream, int32_t *B, int64_t *q_card, int64_t *den, double *J);

@@ -440,7 +440,8 @@ jas_status jas_query_noalloc(const jas_db *db, const uint64_t *q_ids, const uint
     return guard([&] {
         if (!db) fail(JAS_EINVAL, "jas_query_noalloc: db is NULL");
         if (!(db->flags & JAS_KEEP_IDS)) fail(JAS_EINVAL, "jas_query_noalloc: db was encoded without JAS_KEEP_IDS");
-        if (flags != 0) fail(JAS_EINVAL, "jas_query_noalloc: takes no flags (device pointers only)");
+        if (flags & ~(uint32_t)JAS_NO_WAIT)
+            fail(JAS_EINVAL, "jas_query_noalloc: takes no flag but JAS_NO_WAIT (device pointers only)");
         if (nq < 0) fail(JAS_EINVAL, "jas_query_noalloc: nq < 0");
         if (nq > 0 && !q_offsets) fail(JAS_EINVAL, "jas_query_noalloc: q_offsets is NULL");
         if (nq > 0 && db->n > 0 && !B) fail(JAS_EINVAL, "jas_query_noalloc: B is NULL");
@@ -458,7 +459,7 @@ jas_status jas_query_noalloc(const jas_db *db, const uint64_t *q_ids, const uint
                                  std::to_string(noalloc_max_ids()) + ")");
         if (NQ > 0 && !q_ids) fail(JAS_EINVAL, "jas_query_noalloc: q_ids is NULL");
         std::unique_lock<std::mutex> lk;
-        Arena ar = noalloc_arena(lk);
+        Arena ar = noalloc_arena(lk, !(flags & JAS_NO_WAIT));
         try {
             query(db, q_ids, q_offsets, nq, NQ, s, B, q_card, den, J, &ar);
         } catch (...) {

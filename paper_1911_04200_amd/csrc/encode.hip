@@ -1797,6 +1797,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     o.word_pairs_F = hst[ST_F];
     o.list_pairs = hst[ST_LISTPAIRS];
     o.device_bytes = db->budget.held;
+    set_tile_stats(o, (uint64_t)n);
 }
 
 // The encode of a plan: the common path of jas_encode (single-pass scatters

@@ -190,6 +190,14 @@ namespace jas {
 // What one eager encode decided and how large its intermediate arrays were:
 // a plan (plan.hip) repeats the same decisions with buffers of these sizes
 // plus headroom.
+// The packed Gram's work units of an encoding: (stored word row, 128-column
+// tile pair I <= J), and the word pairs they multiply.
+inline void set_tile_stats(jas_encode_stats &o, uint64_t n) {
+    const uint64_t t = (n + 127) / 128;
+    o.dense_tiles = o.w_rows * (t * (t + 1) / 2);
+    o.word_pairs_W = o.dense_tiles * 128 * 128;
+}
+
 struct EncodeTrace {
     bool onesweep = false;    // the global sort ran as single-pass scatters
     bool local = false;       // ranges finished in LDS (no global classification)
@@ -375,7 +383,7 @@ uint64_t query_workspace_bytes(const jas_db *db, int32_t nq, uint64_t n_q_ids);
 // lock that serialises its users held in lk.
 uint64_t noalloc_max_ids();
 int32_t noalloc_max_queries();
-Arena noalloc_arena(std::unique_lock<std::mutex> &lk);
+Arena noalloc_arena(std::unique_lock<std::mutex> &lk, bool wait);  // wait = false: JAS_EBUSY if taken
 
 // Sizes of a planned encode, in device memory (plan.hip): kernels read them
 // instead of host values, and every kernel returns at once when PZ_ABORT is

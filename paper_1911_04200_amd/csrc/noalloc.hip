@@ -10,7 +10,8 @@
 // a device looks up that device's copy with hipGetSymbolAddress (with the
 // device current) and keeps the address; kernels get that address.  Calls in
 // one process share the array, so they are serialised by a lock held until
-// their work on the stream has finished.
+// their work on the stream has finished (with JAS_NO_WAIT a call that finds
+// the lock taken returns JAS_EBUSY instead of waiting).
 #include <map>
 #include <mutex>
 
@@ -36,8 +37,13 @@ std::map<int, char *> g_ptr;  // device -> address of its copy of scratch
 uint64_t noalloc_max_ids() { return kNoAllocMaxIds; }
 int32_t noalloc_max_queries() { return kNoAllocMaxQueries; }
 
-Arena noalloc_arena(std::unique_lock<std::mutex> &lk) {
-    lk = std::unique_lock<std::mutex>(g_mu);
+Arena noalloc_arena(std::unique_lock<std::mutex> &lk, bool wait) {
+    if (wait) {
+        lk = std::unique_lock<std::mutex>(g_mu);
+    } else {
+        lk = std::unique_lock<std::mutex>(g_mu, std::try_to_lock);
+        if (!lk.owns_lock()) fail(JAS_EBUSY, "jas_query_noalloc: the fixed workspace is in use (JAS_NO_WAIT)");
+    }
     int dev = 0;
     JAS_HIP(hipGetDevice(&dev));
     auto it = g_ptr.find(dev);

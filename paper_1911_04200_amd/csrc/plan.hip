@@ -272,6 +272,8 @@ jas_status jas_plan_check(jas_plan *plan, void *hip_stream, jas_encode_stats *st
         o.word_pairs_F = cnt[ST_F_];
         o.list_pairs = cnt[ST_LISTPAIRS_];
         o.n_list_pairs = sz[PZ_P];
+        o.w_rows = sz[PZ_H];
+        set_tile_stats(o, (uint64_t)p.n);
         if (stats) *stats = o;
         const uint32_t e = err[0] & ~(p.wide ? 16u : 0u);
         if (e & 1u) fail(JAS_EINVAL, "jas_plan_encode: an ID is >= 2^universe_bits");

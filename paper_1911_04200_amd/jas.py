@@ -16,7 +16,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libjas.so")
 
-JAS_OK, JAS_EINVAL, JAS_ENOMEM, JAS_EOVERFLOW, JAS_EDEVICE, JAS_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+JAS_OK, JAS_EINVAL, JAS_ENOMEM, JAS_EOVERFLOW, JAS_EDEVICE, JAS_EBUSY, JAS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 JAS_HOST_PTRS = 0x1
 JAS_KEEP_IDS = 0x2
 JAS_UPPER = 0x10
@@ -25,6 +25,7 @@ JAS_FORCE_MFMA = 0x40
 JAS_TUNE = 0x80
 JAS_ACCUMULATE = 0x100
 JAS_CANONICAL = 0x200
+JAS_NO_WAIT = 0x400
 JAS_DB_CARD, JAS_DB_WORDS, JAS_DB_LIST_PAIRS, JAS_DB_LIST_PTR, JAS_DB_LIST_SAMPLES, JAS_DB_KEYS = range(6)
 
 
@@ -33,7 +34,7 @@ def JAS_GRAM_VARIANT(v: int) -> int:
     return (int(v) + 1) << 16
 
 STATUS_NAMES = {0: "JAS_OK", -1: "JAS_EINVAL", -2: "JAS_ENOMEM", -3: "JAS_EOVERFLOW", -4: "JAS_EDEVICE",
-                -6: "JAS_EUNSUPPORTED"}
+                -5: "JAS_EBUSY", -6: "JAS_EUNSUPPORTED"}
 
 # Every symbol include/jas.h declares.
 EXPORTS = sorted(["jas_encode", "jas_gram", "jas_finalize", "jas_kmer_offsets", "jas_kmers", "jas_relabel", "jas_gram_variants", "jas_card_limit", "jas_query", "jas_query_noalloc", "jas_query_workspace_bytes",
@@ -61,7 +62,7 @@ class jas_encode_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in
                 ["n_ids", "n_pairs", "n_rows", "n_shared_rows", "n_packed_rows", "n_list_rows", "n_batches",
                  "n_word_rows", "nnz_words", "word_pairs_F", "list_pairs", "device_bytes", "dense_min_degree",
-                 "word_bits", "w_rows", "w_stride", "n_list_pairs"]]
+                 "word_bits", "w_rows", "w_stride", "n_list_pairs", "dense_tiles", "word_pairs_W"]]
 
     def to_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

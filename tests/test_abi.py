@@ -36,6 +36,16 @@ def test_flag_and_status_values_match_the_header():
         assert getattr(jas, name) == int(value), name
 
 
+def test_struct_fields_match_the_header():
+    """The binding's structs list the header's fields, in order and with their widths."""
+    text = open(os.path.join(ROOT, "include", "jas.h")).read()
+    for cname, cls in (("jas_encode_opts", jas.jas_encode_opts), ("jas_encode_stats", jas.jas_encode_stats)):
+        body = re.search(r"typedef struct \{((?:(?!typedef struct).)*?)\} " + cname + ";", text, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = re.findall(r"uint(32|64)_t (\w+);", body)
+        assert [(n, int(w)) for w, n in fields] == [(n, ctypes.sizeof(t) * 8) for n, t in cls._fields_], cname
+
+
 def test_gram_variant_flag_matches_the_header():
     text = open(os.path.join(ROOT, "include", "jas.h")).read()
     assert "#define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)" in text

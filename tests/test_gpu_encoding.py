@@ -46,6 +46,11 @@ def test_stored_encoding_matches_the_model(case, word_bits, dmin):
     s, so = oracle.normalize(ids, off)
     m = encoding_model.model(s, so, bb, spec.universe_bits, word_bits, int(st["dense_min_degree"]))
     assert st["word_bits"] == word_bits and st["w_rows"] == m["w_rows"] and st["w_stride"] == m["stride"]
+    t = (n + 127) // 128  # the packed Gram's work units: (stored word row, 128-column tile pair)
+    assert st["dense_tiles"] == m["w_rows"] * (t * (t + 1) // 2)
+    assert st["word_pairs_W"] == st["dense_tiles"] * 128 * 128
+    if word_bits == 64:  # whole tiles run, zero words included (F counts b-bit words)
+        assert st["word_pairs_W"] >= st["word_pairs_F"]
     for k, v in m["stats"].items():
         assert st[k] == v, f"stats[{k}] = {st[k]}, model {v}"
     assert np.array_equal(cabi.jas_db_read(db, cabi.JAS_DB_CARD), m["card"])

@@ -3,7 +3,9 @@
 Called through the C ABI (raw ctypes), on two requests in a row, the second
 smaller, over one database: every output must equal jas_query's bit for bit,
 the calls must allocate no device memory, and requests beyond the fixed
-workspace must be refused before any work is enqueued.
+workspace must be refused before any work is enqueued.  With JAS_NO_WAIT a
+call either runs as usual or, while another thread's call holds the
+workspace, returns JAS_EBUSY without enqueueing anything.
 """
 import ctypes
 
@@ -122,3 +124,69 @@ def test_noalloc_query_refuses_what_the_workspace_cannot_hold():
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(o2, o3))
     db.close()
+
+
+def test_noalloc_no_wait_is_busy_or_the_same_result():
+    """With JAS_NO_WAIT a call runs as usual, or, while another thread's call
+    holds the fixed workspace, returns JAS_EBUSY at once and enqueues nothing
+    (its outputs keep their fill)."""
+    import threading
+
+    spec = synth.scaled(synth.workload("serving_db"), n=300, size_scale=0.01, pool_scale=0.005)
+    ids, off = synth.generate(spec)
+    n = spec.n
+    db, _ = cabi.jas_encode(dev(ids), dev(off), n, cabi.jas_encode_opts(spec.universe_bits, 26, 0,
+                                                                        cabi.JAS_KEEP_IDS, 0), None)
+    qids, qoff = request(spec, ids, off, 1, 40, 0.05)
+    nq = qoff.size - 1
+    dq, dqo = dev(qids), dev(qoff)
+    want = outputs(nq, n)
+    assert call("jas_query", db, dq, dqo, nq, want) == cabi.JAS_OK
+    torch.cuda.synchronize()
+    want = [x.cpu() for x in want]
+    o = outputs(nq, n)
+    assert call("jas_query_noalloc", db, dq, dqo, nq, o, cabi.JAS_NO_WAIT) == cabi.JAS_OK, cabi.jas_last_error()
+    torch.cuda.synchronize()
+    assert all(torch.equal(g.cpu(), w) for g, w in zip(o, want))
+
+    stop, errors = threading.Event(), []
+
+    def worker():  # keeps the workspace busy with waiting calls on its own stream
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(200):
+                    if stop.is_set():
+                        break
+                    st = call("jas_query_noalloc", db, dq, dqo, nq, outputs(nq, n))
+                    if st != cabi.JAS_OK:
+                        errors.append(st)
+                        break
+        except Exception as e:  # reported by the main thread
+            errors.append(repr(e))
+
+    t = threading.Thread(target=worker)
+    t.start()
+    busy = 0
+    try:
+        for _ in range(400):
+            o = outputs(nq, n)
+            torch.cuda.synchronize()
+            st = call("jas_query_noalloc", db, dq, dqo, nq, o, cabi.JAS_NO_WAIT)
+            torch.cuda.synchronize()
+            if st == cabi.JAS_EBUSY:
+                busy += 1
+                assert "in use" in cabi.jas_last_error()
+                assert bool((o[0] == -7).all()) and bool((o[1] == -7).all()), "a refused call wrote its outputs"
+            else:
+                assert st == cabi.JAS_OK, cabi.jas_last_error()
+                assert all(torch.equal(g.cpu(), w) for g, w in zip(o, want))
+            if busy >= 3 or not t.is_alive():
+                break
+    finally:
+        stop.set()
+        t.join()
+    assert not errors, errors
+    db.close()
+    if busy == 0:
+        pytest.skip("no call overlapped the other thread's calls")
