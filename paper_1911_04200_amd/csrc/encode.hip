@@ -394,7 +394,6 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
     __shared__ KT A[kLocalCapKeys];
     __shared__ uint32_t wcnt[kLWaves][256];
     __shared__ uint64_t T[kLWaves][256];  // per wave: lanes of the current round with digit d
-    __shared__ uint32_t tdp[256];
     __shared__ uint64_t sh[kLWaves];
     __shared__ uint32_t wc[3][kLWaves];
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
@@ -513,9 +512,8 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
                 for (int k = 0; k < kLWaves; ++k) tc += wcnt[k][tid];
             uint64_t all;
             const uint32_t ex = (uint32_t)block_excl_scan<kLNT>(tc, sh, &all);
-            if (tid < 256) {
-                tdp[tid] = ex;
-                uint32_t run = 0;
+            if (tid < 256) {  // wcnt[w][d] becomes where wave w's keys of digit d start in the range
+                uint32_t run = ex;
                 for (int k = 0; k < kLWaves; ++k) {
                     const uint32_t v = wcnt[k][tid];
                     wcnt[k][tid] = run;
@@ -527,7 +525,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
             for (uint32_t j = 0; j < kLRounds; ++j)
                 if (j < rounds && wb + j * kWave + lane < L) {
                     const uint32_t d = (uint32_t)(key[j] >> dsh) & 255u;
-                    A[tdp[d] + wcnt[w][d] + rank[j]] = key[j];
+                    A[wcnt[w][d] + rank[j]] = key[j];
                 }
             __syncthreads();
         }

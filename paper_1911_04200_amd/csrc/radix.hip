@@ -282,9 +282,9 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
         // reorder the tile in LDS by digit (local offsets only)
         uint64_t tot;
         const uint32_t ex = (uint32_t)block_excl_scan<kOsNT>(tc, sh, &tot);
-        if (digit) {
+        if (digit) {  // wcnt[w][d] becomes where wave w's keys of digit d start in the tile
             tdp[tid] = ex;
-            uint32_t run = 0;
+            uint32_t run = ex;
 #pragma unroll
             for (int k = 0; k < kOsWaves; ++k) {
                 const uint32_t v = wcnt[k][tid];
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             const uint64_t t = wb + (uint64_t)j * kWave + lane;
             if (t < c1) {
                 const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
-                stage[tdp[d] + wcnt[w][d] + rank[j]] = key[j];
+                stage[wcnt[w][d] + rank[j]] = key[j];
             }
         }
         // then look back for the digit's global offset: kLookWindow
