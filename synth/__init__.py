@@ -60,22 +60,31 @@ class _Spec(ctypes.Structure):
     ]
 
 
+def _bind(lib):
+    P = ctypes.POINTER
+    lib.synth_offsets.argtypes = [P(_Spec), P(ctypes.c_uint64)]
+    lib.synth_plan.argtypes = [P(_Spec), ctypes.c_int32, P(ctypes.c_uint64)]
+    lib.synth_fill.argtypes = [P(_Spec), ctypes.c_int32, ctypes.c_int32, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+    lib.synth_fill_list.argtypes = [P(_Spec), ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_uint64),
+                                    P(ctypes.c_uint64)]
+    lib.synth_rmat.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+    lib.synth_rmat.restype = ctypes.c_int64
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         build()
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.POINTER
-        lib.synth_offsets.argtypes = [P(_Spec), P(ctypes.c_uint64)]
-        lib.synth_plan.argtypes = [P(_Spec), ctypes.c_int32, P(ctypes.c_uint64)]
-        lib.synth_fill.argtypes = [P(_Spec), ctypes.c_int32, ctypes.c_int32, P(ctypes.c_uint64), P(ctypes.c_uint64)]
-        lib.synth_fill_list.argtypes = [P(_Spec), ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_uint64),
-                                        P(ctypes.c_uint64)]
-        lib.synth_rmat.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_double, P(ctypes.c_uint64), P(ctypes.c_uint64)]
-        lib.synth_rmat.restype = ctypes.c_int64
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+def use_library(path: str) -> None:
+    """Generate with another build of synth.c from now on (e.g. one built with sanitizers)."""
+    global _lib
+    _lib = _bind(ctypes.CDLL(path))
 
 
 @dataclasses.dataclass(frozen=True)
