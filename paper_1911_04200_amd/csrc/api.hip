@@ -452,14 +452,15 @@ jas_status jas_query_noalloc(const jas_db *db, const uint64_t *q_ids, const uint
                                  std::to_string(noalloc_max_queries()) + ")");
         if (nq == 0) return;
         hipStream_t s = (hipStream_t)hip_stream;
+        // the workspace first: with JAS_NO_WAIT a refused call has touched nothing
+        std::unique_lock<std::mutex> lk;
+        Arena ar = noalloc_arena(lk, !(flags & JAS_NO_WAIT));
         const std::vector<uint64_t> hoff = host_offsets(q_offsets, nq, false, s, "jas_query_noalloc");
         const uint64_t NQ = hoff[nq];
         if (NQ > noalloc_max_ids())
             fail(JAS_ENOMEM, "jas_query_noalloc: " + std::to_string(NQ) + " query IDs exceed the fixed workspace (at most " +
                                  std::to_string(noalloc_max_ids()) + ")");
         if (NQ > 0 && !q_ids) fail(JAS_EINVAL, "jas_query_noalloc: q_ids is NULL");
-        std::unique_lock<std::mutex> lk;
-        Arena ar = noalloc_arena(lk, !(flags & JAS_NO_WAIT));
         try {
             query(db, q_ids, q_offsets, nq, NQ, s, B, q_card, den, J, &ar);
         } catch (...) {
