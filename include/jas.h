@@ -45,7 +45,7 @@ typedef enum {
     JAS_EOVERFLOW = -3,    /* a set has 2^31 or more distinct IDs (int32 B would overflow) */
     JAS_EDEVICE = -4,      /* a HIP runtime call failed (message names it) */
     JAS_EBUSY = -5,        /* a shared resource is in use and the caller asked not to wait (JAS_NO_WAIT) */
-    JAS_EUNSUPPORTED = -6  /* valid request this build does not support (message says why) */
+    JAS_EUNSUPPORTED = -6  /* valid request the library does not support (message says why) */
 } jas_status;
 
 /* ---- flags ---------------------------------------------------------------- */
@@ -342,7 +342,7 @@ jas_status jas_db_stats(const jas_db *db, jas_encode_stats *stats);
 
 /*
  * jas_db_part_size / jas_db_read -- the db's arrays, read back to the host
- * (for checking or keeping an encoding; the layout is that of this build).
+ * (for checking or keeping an encoding; the layout is that of this library version).
  *  JAS_DB_CARD          int64[n]: |X_i| (the column sums of Eq. (4)).
  *  JAS_DB_WORDS         uint64[w_rows * w_stride]: the bitmask words (Sec. III-B) of
  *                       the rows shared by >= dense_min_degree sets, batch by batch
