@@ -159,3 +159,26 @@ def test_tuned_threshold_is_timed_and_exact():
     torch.cuda.synchronize()
     check(out, oracle.all_pairs(ids, off), "tuned")
     plan.close()
+
+
+def test_plan_refuses_a_collection_that_needs_the_fallback_sort():
+    """One ID repeated 20,000 times makes a bucket too large to finish in LDS:
+    the eager encode takes the full sort (checked against the oracle), and a
+    plan, which prepares only the single-pass path, is refused up front."""
+    rng = np.random.default_rng(3)
+    sets = [rng.integers(0, 1 << 32, 2000, dtype=np.uint64) for _ in range(40)]
+    sets[7] = np.concatenate([sets[7], np.full(20000, 12345, np.uint64)])
+    sets[9] = np.concatenate([sets[9], np.array([12345], np.uint64)])
+    off = np.zeros(len(sets) + 1, np.uint64)
+    off[1:] = np.cumsum([s.size for s in sets])
+    ids = np.concatenate(sets)
+    opts = cabi.jas_encode_opts(32, 0, 0, 0, 0)
+    db, _ = cabi.jas_encode(dev(ids), dev(off), 40, opts, None)
+    out = gram_upper(db, 40)
+    torch.cuda.synchronize()
+    check(out, oracle.all_pairs(ids, off), "eager with the fallback sort")
+    db.close()
+    with pytest.raises(cabi.JasError) as e:
+        cabi.jas_plan_create(dev(ids), dev(off), 40, opts, headroom=0.5)
+    assert e.value.status == cabi.JAS_EUNSUPPORTED
+    assert "fallback" in e.value.message
