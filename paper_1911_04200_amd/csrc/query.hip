@@ -17,7 +17,7 @@ namespace jas {
 namespace {
 
 constexpr int kNT = 256;
-constexpr uint64_t kQChunk = 16384;  // query entries per block
+constexpr uint64_t kQChunk = 2048;  // query entries per block (more blocks than CUs for typical requests)
 constexpr int32_t kHistMax = 16384;
 
 // Keys (q << U) | id of 4096 entries per block, and the totals of every
