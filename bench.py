@@ -216,7 +216,8 @@ def run_serving(n_requests: int, n_saturation: int, n_warmup: int = 200, pool: i
     off_d = torch.from_numpy(off.view(np.int64)).cuda()
     del host
     torch.cuda.synchronize()
-    opts = cabi.jas_encode_opts(spec.universe_bits, synth.BATCH_BITS["serving_db"], 0, cabi.JAS_KEEP_IDS, 0)
+    opts = cabi.jas_encode_opts(spec.universe_bits, synth.BATCH_BITS["serving_db"], 0,
+                                cabi.JAS_KEEP_IDS | cabi.JAS_QUERY_ONLY, 0)
     t = time.perf_counter()
     db, st = cabi.jas_encode(ids_d, off_d, spec.n, opts, None)
     enc_s = time.perf_counter() - t

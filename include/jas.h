@@ -59,6 +59,9 @@ typedef enum {
 #define JAS_CANONICAL 0x200u    /* jas_kmers: each k-mer as the smaller of itself and its reverse complement */
 #define JAS_NO_WAIT 0x400u      /* jas_query_noalloc: JAS_EBUSY at once, instead of waiting, while another call
                                    holds this process's fixed workspace */
+#define JAS_QUERY_ONLY 0x800u   /* jas_encode, with JAS_KEEP_IDS: keep only what jas_query reads (the distinct
+                                   keys, their bucket table, |X_i|); no packed words or row lists are built, and
+                                   jas_gram refuses the db */
 /* jas_gram: run MFMA tile variant v, 0 <= v < jas_gram_variants() (bits 16..23 hold v + 1) */
 #define JAS_GRAM_VARIANT(v) ((((uint32_t)(v)) + 1u) << 16)
 
@@ -71,7 +74,7 @@ typedef struct {
                                   rows shared by 2..this-1 sets are kept as plain row lists;
                                   0 = chosen by the library from the row degree histogram
                                   (cost model of the two Gram paths); 2 = pack every shared row */
-    uint32_t flags;            /* JAS_HOST_PTRS, JAS_KEEP_IDS */
+    uint32_t flags;            /* JAS_HOST_PTRS, JAS_KEEP_IDS, JAS_QUERY_ONLY */
     uint64_t hbm_budget_bytes; /* cap on device memory this call may hold at once; 0 = none */
     uint32_t word_bits;        /* b, rows per bitmask word (Sec. III-B): 32 or 64; 0 = 64.  B does
                                   not depend on it (every word's popcount sums its rows) */

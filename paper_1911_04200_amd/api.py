@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import torch
 
-from .jas import (JAS_KEEP_IDS, JAS_UPPER, jas_encode, jas_encode_opts, jas_gram, jas_query)
+from .jas import (JAS_KEEP_IDS, JAS_QUERY_ONLY, JAS_UPPER, jas_encode, jas_encode_opts, jas_gram, jas_query)
 
 
 def _dev_u64(x, device):
@@ -14,13 +14,14 @@ def _dev_u64(x, device):
 
 
 def encode(ids, offsets, universe_bits: int, batch_bits: int = 0, dense_min_degree: int = 0, keep_ids: bool = False,
-           hbm_budget_bytes: int = 0, word_bits: int = 64, device="cuda", stream=None):
-    """Encode n CSR sets (device tensors, or anything torch.as_tensor accepts)."""
+           hbm_budget_bytes: int = 0, word_bits: int = 64, device="cuda", stream=None, query_only: bool = False):
+    """Encode n CSR sets (device tensors, or anything torch.as_tensor accepts).  query_only
+    (with keep_ids) keeps only what queries need."""
     ids_t = _dev_u64(ids, device)
     off_t = _dev_u64(offsets, device)
     n = off_t.numel() - 1
-    opts = jas_encode_opts(universe_bits, batch_bits, dense_min_degree, JAS_KEEP_IDS if keep_ids else 0,
-                           hbm_budget_bytes, word_bits)
+    flags = (JAS_KEEP_IDS if keep_ids else 0) | (JAS_QUERY_ONLY if query_only else 0)
+    opts = jas_encode_opts(universe_bits, batch_bits, dense_min_degree, flags, hbm_budget_bytes, word_bits)
     return jas_encode(ids_t, off_t, n, opts, stream)
 
 

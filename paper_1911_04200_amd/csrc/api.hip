@@ -188,6 +188,8 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
             fail(JAS_EINVAL, "jas_encode: word_bits must be 32, 64 or 0 (= 64)");
         const uint32_t sbits = ceil_log2_u64((uint64_t)std::max<int32_t>(n, 1));
         if (U + sbits > 64) fail(JAS_EINVAL, "jas_encode: universe_bits + ceil(log2 n) exceeds 64");
+        if ((opts->flags & JAS_QUERY_ONLY) && !(opts->flags & JAS_KEEP_IDS))
+            fail(JAS_EINVAL, "jas_encode: JAS_QUERY_ONLY needs JAS_KEEP_IDS");
         const bool host = opts->flags & JAS_HOST_PTRS;
         hipStream_t s = (hipStream_t)hip_stream;
         // host arrays are validated before the device is touched
@@ -290,6 +292,7 @@ jas_status jas_gram(const jas_db *db, uint32_t flags, void *hip_stream, int32_t 
                     double *J) {
     return guard([&] {
         if (!db) fail(JAS_EINVAL, "jas_gram: db is NULL");
+        if (db->flags & JAS_QUERY_ONLY) fail(JAS_EINVAL, "jas_gram: the db was encoded with JAS_QUERY_ONLY");
         if (!B && db->n > 0) fail(JAS_EINVAL, "jas_gram: B is NULL");
         if ((flags & JAS_FORCE_POPCOUNT) && (flags & JAS_FORCE_MFMA))
             fail(JAS_EINVAL, "jas_gram: JAS_FORCE_POPCOUNT and JAS_FORCE_MFMA are exclusive");

@@ -1319,6 +1319,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     const uint32_t sbits = db->sbits;
     const uint64_t smask = sbits ? ((uint64_t(1) << sbits) - 1) : 0;
     const bool keep = db->flags & JAS_KEEP_IDS;
+    const bool query_only = db->flags & JAS_QUERY_ONLY;  // no packed words or row lists
 
     DevBuf<unsigned long long> st;
     st.alloc(ST_N, s, tb, true, "encode counters");
@@ -1534,7 +1535,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     // --- split rows by degree ------------------------------------------------
     uint64_t QD = 0, QL = 0;
     DevBuf<uint64_t> Drow, Lrow;
-    if (R > 0 && db->dmin == 0) {
+    if (R > 0 && !query_only && db->dmin == 0) {
         // choose the degree threshold from the row degree histogram
         JAS_HOST_TIMED("choose_dmin");
         const uint32_t nb = (uint32_t)n + 2;
@@ -1563,7 +1564,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         db->dmin = choose_dense_min_degree(hh, (uint32_t)n, nbatches, cap);
     }
     db->stats.dense_min_degree = db->dmin;
-    if (R > 0) {
+    if (R > 0 && !query_only) {
         const uint64_t nt = div_up(R, kSplitTile);
         if (nt > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many rows");
         DevBuf<uint32_t> tcnt;

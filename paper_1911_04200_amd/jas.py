@@ -26,6 +26,7 @@ JAS_TUNE = 0x80
 JAS_ACCUMULATE = 0x100
 JAS_CANONICAL = 0x200
 JAS_NO_WAIT = 0x400
+JAS_QUERY_ONLY = 0x800
 JAS_DB_CARD, JAS_DB_WORDS, JAS_DB_LIST_PAIRS, JAS_DB_LIST_PTR, JAS_DB_LIST_SAMPLES, JAS_DB_KEYS = range(6)
 
 

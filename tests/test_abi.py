@@ -152,3 +152,11 @@ def test_encode_rejects_a_bad_word_width():
         with pytest.raises(jas.JasError) as e:
             jas.jas_encode(ids, np.array([0, 3], dtype=np.uint64), 1, opts)
         assert e.value.status == jas.JAS_EINVAL and "word_bits" in e.value.message
+
+
+def test_query_only_needs_the_query_index():
+    ids = np.arange(3, dtype=np.uint64)
+    opts = jas.jas_encode_opts(24, 0, 0, jas.JAS_HOST_PTRS | jas.JAS_QUERY_ONLY, 0)
+    with pytest.raises(jas.JasError) as e:
+        jas.jas_encode(ids, np.array([0, 3], dtype=np.uint64), 1, opts)
+    assert e.value.status == jas.JAS_EINVAL and "JAS_KEEP_IDS" in e.value.message

@@ -485,11 +485,23 @@ def test_repeat_runs_are_identical():
 
 
 # --- query path -------------------------------------------------------------
-def test_query_matches_oracle():
+@pytest.mark.parametrize("query_only", [False, True])
+def test_query_matches_oracle(query_only):
+    """A query against every database set; with JAS_QUERY_ONLY the db holds only the
+    query index (less device memory, the same answers) and jas_gram refuses it."""
     spec = synth.scaled(synth.workload("serving_db"), n=150, size_scale=0.01, pool_scale=0.005)
     ids, off = synth.generate(spec)
-    db, _ = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, batch_bits=26, keep_ids=True,
-                       dense_min_degree=5)
+    db, st = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, batch_bits=26, keep_ids=True,
+                        dense_min_degree=5, query_only=query_only)
+    if query_only:
+        full, st_full = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, batch_bits=26,
+                                   keep_ids=True, dense_min_degree=5)
+        assert st["device_bytes"] < st_full["device_bytes"]
+        assert st["n_packed_rows"] == 0 and st["n_list_rows"] == 0 and st["n_pairs"] == st_full["n_pairs"]
+        full.close()
+        with pytest.raises(cabi.JasError) as e:
+            jas.gram(db)
+        assert e.value.status == cabi.JAS_EINVAL
     qspec = synth.scaled(synth.query_spec(spec, 0, 9), size_scale=0.01)
     qi, qo = synth.generate(qspec)
     # add DB sets 0 and 7, an empty set, and a set with repeats and IDs absent from the DB
