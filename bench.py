@@ -638,7 +638,7 @@ def main():
     ap.add_argument("--dmin", type=int, default=0, help="dense_min_degree (0: library default)")
     ap.add_argument("--upper", action="store_true", help="packed upper-triangle outputs")
     ap.add_argument("--path", default="auto", choices=["auto", "popcount", "mfma"], help="Gram path for packed tiles")
-    ap.add_argument("--cpu-sample", type=int, default=64, help="sets in the oracle's timed sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=192, help="sets in the oracle's timed sample (0: skip)")
     ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing in the timed region")
     ap.add_argument("--extra-configs", type=int, default=1,
                     help="with the paperlike workload: also time the precision and batching forms (0: skip)")
