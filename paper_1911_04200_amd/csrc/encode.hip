@@ -297,24 +297,21 @@ __global__ __launch_bounds__(kNT) void k_cls_write(const uint64_t *__restrict__ 
 // bucket, still in input order (every pass was stable, so entries of one ID
 // are in ascending sample order).  Range c runs from the first bucket edge at
 // or after c*stride to the first at or after (c+1)*stride (k_range_starts);
-// the encoder tries the strides of kLStrides in turn, longest first, until
-// no range exceeds kLocalCapKeys.
+// the encoder tries the strides of kLocalStrides in turn until no range
+// exceeds kLocalCapKeys, and launches the kernel built for kLocalShortCap keys
+// when every range fits it, else the one for kLocalCapKeys.
 // A range is made of whole buckets, so it holds whole rows of A and needs no
-// halo.  One block loads a range (<= kLocalCapKeys keys) into LDS, finishes
+// halo.  One block loads a range (<= Cap keys) into LDS, finishes
 // the sort there (stable LSD passes over the ID bits below the range's first
 // bucket), classifies as k_cls_count/k_cls_write do, and writes its results
 // at the range's own position (distinct keys in place over the range, shared
 // pairs at the range start, rows at half the range start) with its counts;
 // k_local_move then packs them after a scan of the counts.  A range longer
-// than kLocalCapKeys (a bucket with very many keys) sets err bit 8 before any
-// block writes; when it does at every stride the caller sorts every ID bit
+// than the cap (a bucket with very many keys) sets err bit 8 before any
+// block writes; when it does at every try the caller sorts every ID bit
 // and uses k_cls_count/k_cls_write.
 constexpr int kLNT = 512;
 constexpr int kLWaves = kLNT / kWave;
-constexpr uint32_t kLRounds = (kLocalCapKeys + kLNT - 1) / kLNT;  // keys per thread
-// Longer ranges fill the blocks better (4096 measured faster than 3072);
-// shorter ones leave room for larger buckets.
-constexpr uint64_t kLStrides[] = {4096, 3072, 2048};
 
 __device__ __forceinline__ uint64_t bucket_of(uint64_t key, uint32_t bsh) { return bsh >= 64 ? 0 : key >> bsh; }
 __device__ __forceinline__ uint64_t div_up_dev(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -322,10 +319,11 @@ __device__ __forceinline__ uint32_t dev_ceil_log2(uint64_t v) { return v <= 1 ? 
 
 // rs[c] = first bucket edge at or after c*stride, c in [0, nlc]; positions
 // 0 and N are edges.  One wave per c, 256 keys per step.  An edge more than
-// kLocalCapKeys keys away is not looked for: rs[c] = ~0 and err |= 8.
+// cap keys away is not looked for: rs[c] = ~0 and err |= 8.
 __global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict__ K, uint64_t N, uint32_t bsh,
                                                        uint64_t stride, uint64_t nlc, uint64_t *__restrict__ rs,
-                                                       uint32_t *err, const uint64_t *__restrict__ dsz) {
+                                                       uint32_t *err, const uint64_t *__restrict__ dsz,
+                                                       uint32_t cap) {
     if (plan_aborted(dsz)) return;
     if (dsz) {
         N = dsz[PZ_N];
@@ -340,7 +338,7 @@ __global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict
         return;
     }
     const uint64_t b0 = bucket_of(K[x - 1], bsh);
-    for (uint64_t y = x; y < x + kLocalCapKeys; y += 4 * kWave) {
+    for (uint64_t y = x; y < x + cap; y += 4 * kWave) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint64_t t = y + k * kWave + lane;
@@ -357,42 +355,52 @@ __global__ __launch_bounds__(256) void k_range_starts(const uint64_t *__restrict
     }
 }
 
-// Checks every range (err |= 8 as above) and whether its keys fit 32 bits
-// once made relative to the range's first bucket: ((id - rbase) << sbits) |
-// sample, with rbase = first bucket << lowbits, needs lowbits + ceil_log2(the
-// number of bucket values spanned) + sbits bits; err |= 16 where that exceeds 32.
+// Checks every range (err |= 8 as above), whether it is longer than
+// kLocalShortCap (err |= 128) and whether its keys fit 32 bits once made
+// relative to the range's first bucket: ((id - rbase) << sbits) | sample, with
+// rbase = first bucket << lowbits, needs lowbits + ceil_log2(the number of
+// bucket values spanned) + sbits bits; err |= 16 where that exceeds 32.
 // The flags of a thread's ranges are gathered first and set with one atomic
-// per wave (every range may set bit 16).
+// per wave (every range may set bits 16 and 128).
 __global__ void k_range_check(const uint64_t *__restrict__ K, const uint64_t *rs, uint64_t nlc, uint32_t bsh,
                               uint32_t lowbits, uint32_t sbits, uint32_t *err, const uint64_t *__restrict__ dsz,
-                              uint64_t stride) {
+                              uint64_t stride, uint32_t cap) {
     if (plan_aborted(dsz)) return;
     if (dsz) nlc = div_up_dev(dsz[PZ_N], stride);
     uint32_t f = 0;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nlc; c += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t a = rs[c], b = rs[c + 1];
-        if (a == ~0ull || b == ~0ull || b < a || b - a > kLocalCapKeys) {
+        if (a == ~0ull || b == ~0ull || b < a || b - a > cap) {
             f |= 8u;
         } else if (b > a) {
+            if (b - a > kLocalShortCap) f |= 128u;
             const uint64_t bf = bucket_of(K[a], bsh), bl = bucket_of(K[b - 1], bsh);
             if (lowbits + dev_ceil_log2(bl - bf + 1) + sbits > 32) f |= 16u;
         }
     }
-    const uint64_t m8 = __ballot((f & 8u) != 0), m16 = __ballot((f & 16u) != 0);
-    if (lane_id() == 0 && (m8 | m16)) atomicOr(err, (m8 ? 8u : 0u) | (m16 ? 16u : 0u));
+    const uint64_t m8 = __ballot((f & 8u) != 0), m16 = __ballot((f & 16u) != 0), m128 = __ballot((f & 128u) != 0);
+    if (lane_id() == 0 && (m8 | m16 | m128))
+        atomicOr(err, (m8 ? 8u : 0u) | (m16 ? 16u : 0u) | (m128 ? 128u : 0u));
 }
 
 // KT is the LDS form of a key, relative to the range's first bucket:
 // uint32_t when every range fits 32 bits (k_range_check), else uint64_t.
-// The narrow form halves the LDS footprint, so three blocks share a CU.
-template <class KT>
-__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT) == 4 ? 6 : 4))) void k_local_cls(
+// Cap is the most keys of a range.  Blocks per CU (by LDS): 4 for 32-bit keys
+// and Cap 4096, 3 for 32-bit keys and Cap 6144 or 64-bit keys and Cap 4096,
+// 2 for 64-bit keys and Cap 6144; the register budget matches.
+constexpr int local_cls_waves(size_t kt, uint32_t cap) { return kt == 4 ? (cap <= 4096 ? 8 : 6) : (cap <= 4096 ? 6 : 4); }
+template <class KT, uint32_t Cap>
+__global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(local_cls_waves(sizeof(KT), Cap)))) void k_local_cls(
     uint64_t *__restrict__ K, uint32_t sbits, uint64_t smask, uint32_t bsh, uint32_t lowbits,
     const uint64_t *__restrict__ rs, uint32_t nlc, uint32_t *__restrict__ cnt, int keep, uint32_t *__restrict__ Sg,
     uint64_t *__restrict__ rid_g, uint64_t *__restrict__ rptr_g, unsigned long long *__restrict__ dupc,
     unsigned long long *__restrict__ rows_rep, const uint64_t *__restrict__ dsz, uint64_t stride, uint32_t *err) {
-    __shared__ KT A[kLocalCapKeys];
-    __shared__ uint32_t wcnt[kLWaves][256];
+    static_assert(Cap <= kLocalCapKeys && Cap % kLNT == 0, "range cap");
+    constexpr uint32_t kLRounds = Cap / kLNT;  // keys per thread
+    __shared__ KT A[Cap];
+    // per wave and digit d: a 16-bit count (then start) in half d & 1 of word d >> 1
+    // (positions < 2^16; counts per wave <= Cap / kLWaves rounded up to 64 < 2^10)
+    __shared__ uint32_t wcnt[kLWaves][128];
     __shared__ uint64_t T[kLWaves][256];  // per wave: lanes of the current round with digit d
     __shared__ uint64_t sh[kLWaves];
     __shared__ uint32_t wc[3][kLWaves];
@@ -400,12 +408,12 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
     const uint64_t lt = lanemask_lt();
     const uint32_t c = blockIdx.x;
     if (plan_aborted(dsz)) return;
-    if (dsz) {
+    {
         // a planned launch covers the most ranges; the others count nothing,
-        // and a range the planned stride cannot hold is flagged and skipped
-        const bool beyond = c >= div_up_dev(dsz[PZ_N], stride);
+        // and a range this kernel cannot hold is flagged and skipped
+        const bool beyond = dsz && c >= div_up_dev(dsz[PZ_N], stride);
         const bool bad = !beyond && (rs[c] == ~0ull || rs[c + 1] == ~0ull || rs[c + 1] < rs[c] ||
-                                     rs[c + 1] - rs[c] > kLocalCapKeys);
+                                     rs[c + 1] - rs[c] > Cap);
         if (beyond || bad) {
             if (tid == 0) {
                 cnt[c] = 0;
@@ -418,7 +426,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
     }
     for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&T[0][0])[i] = 0;
     const uint64_t s0 = rs[c], s1 = rs[c + 1];
-    const uint32_t L = (uint32_t)(s1 - s0);  // <= kLocalCapKeys (k_range_check)
+    const uint32_t L = (uint32_t)(s1 - s0);  // <= Cap (k_range_check)
     // relative keys: key - kbase = ((id - rbase) << sbits) | sample < 2^(nb + sbits)
     uint64_t kbase = 0;
     uint32_t nb = 0;
@@ -451,7 +459,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
     if (L > 1) {
         for (uint32_t p = 0; p < nb; p += 8) {
             const uint32_t dsh = sbits + p;
-            for (uint32_t i = tid; i < kLWaves * 256; i += kLNT) (&wcnt[0][0])[i] = 0;
+            for (uint32_t i = tid; i < kLWaves * 128; i += kLNT) (&wcnt[0][0])[i] = 0;
             KT key[kLRounds];
             uint32_t rank[kLRounds];
 #pragma unroll
@@ -493,8 +501,8 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
                         const uint32_t leader = pr ? (uint32_t)__builtin_ctzll(pr) : lane;
                         uint32_t old = 0;
                         if (pr && before == 0) {
-                            const uint32_t d = (uint32_t)(key[j] >> dsh) & 255u;
-                            old = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(pr));
+                            const uint32_t d = (uint32_t)(key[j] >> dsh) & 255u, hs = (d & 1u) * 16u;
+                            old = (atomicAdd(&wcnt[w][d >> 1], (uint32_t)__popcll(pr) << hs) >> hs) & 0xFFFFu;
                         }
                         rank[j] = old | (leader << 10) | (before << 16);
                     }
@@ -507,17 +515,23 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
                     rank[j] = ((uint32_t)__shfl((int)f, (int)((f >> 10) & 63u), kWave) & 1023u) + (f >> 16);
                 }
             __syncthreads();
-            uint32_t tc = 0;
-            if (tid < 256)
-                for (int k = 0; k < kLWaves; ++k) tc += wcnt[k][tid];
-            uint64_t all;
-            const uint32_t ex = (uint32_t)block_excl_scan<kLNT>(tc, sh, &all);
-            if (tid < 256) {  // wcnt[w][d] becomes where wave w's keys of digit d start in the range
-                uint32_t run = ex;
+            // thread tid < 128 owns digits 2 tid and 2 tid + 1
+            uint32_t tlo = 0, thi = 0;
+            if (tid < 128)
                 for (int k = 0; k < kLWaves; ++k) {
                     const uint32_t v = wcnt[k][tid];
-                    wcnt[k][tid] = run;
-                    run += v;
+                    tlo += v & 0xFFFFu;
+                    thi += v >> 16;
+                }
+            uint64_t all;
+            const uint32_t ex = (uint32_t)block_excl_scan<kLNT>(tlo + thi, sh, &all);
+            if (tid < 128) {  // the halves become where wave k's keys of each digit start in the range
+                uint32_t rlo = ex, rhi = ex + tlo;
+                for (int k = 0; k < kLWaves; ++k) {
+                    const uint32_t v = wcnt[k][tid];
+                    wcnt[k][tid] = rlo | (rhi << 16);
+                    rlo += v & 0xFFFFu;
+                    rhi += v >> 16;
                 }
             }
             __syncthreads();
@@ -525,7 +539,7 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
             for (uint32_t j = 0; j < kLRounds; ++j)
                 if (j < rounds && wb + j * kWave + lane < L) {
                     const uint32_t d = (uint32_t)(key[j] >> dsh) & 255u;
-                    A[wcnt[w][d] + rank[j]] = key[j];
+                    A[((wcnt[w][d >> 1] >> ((d & 1u) * 16u)) & 0xFFFFu) + rank[j]] = key[j];
                 }
             __syncthreads();
         }
@@ -606,6 +620,19 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(sizeof(KT)
         pD += __popcll(bd);
         pS += __popcll(bs);
         pR += __popcll(br);
+    }
+}
+
+// Launches the k_local_cls built for the key width and the range cap.
+template <class... Args>
+void launch_local_cls(bool wide, uint32_t cap, uint32_t grid, hipStream_t s, Args... args) {
+    if (cap != kLocalShortCap && cap != kLocalCapKeys) fail(JAS_EDEVICE, "local classify: no kernel for this range cap");
+    if (wide) {
+        if (cap == kLocalShortCap) k_local_cls<uint64_t, kLocalShortCap><<<grid, kLNT, 0, s>>>(args...);
+        else k_local_cls<uint64_t, kLocalCapKeys><<<grid, kLNT, 0, s>>>(args...);
+    } else {
+        if (cap == kLocalShortCap) k_local_cls<uint32_t, kLocalShortCap><<<grid, kLNT, 0, s>>>(args...);
+        else k_local_cls<uint32_t, kLocalCapKeys><<<grid, kLNT, 0, s>>>(args...);
     }
 }
 
@@ -1347,7 +1374,7 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     bool done = N == 0;
 
     // --- classify each range of whole buckets in LDS ------------------------
-    constexpr uint64_t kMinStride = kLStrides[sizeof(kLStrides) / sizeof(kLStrides[0]) - 1];
+    constexpr uint64_t kMinStride = kLocalStrides[sizeof(kLocalStrides) / sizeof(kLocalStrides[0]) - 1];
     if (!done && div_up(N, kMinStride) <= 0xFFFFFFFFull && alt.n >= N + 2) {
         const uint32_t lowbits = db->U - plan.top_bits;
         const uint32_t bsh = sbits + lowbits;
@@ -1356,7 +1383,8 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         flags.alloc(1, s, tb, true, "range error flag");
         uint32_t *errL = reinterpret_cast<uint32_t *>(flags.p);
         uint64_t herr = 8, nlc = 0;
-        for (uint64_t stride : kLStrides) {
+        uint32_t cap = kLocalCapKeys;
+        for (const uint64_t stride : kLocalStrides) {
             nlc = div_up(N, stride);
             {
                 JAS_TIMED("fill_u64", s);
@@ -1365,15 +1393,17 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             {
                 JAS_TIMED("range_starts", s);
                 k_range_starts<<<(uint32_t)div_up(nlc + 1, 256 / kWave), 256, 0, s>>>(keys.p, N, bsh, stride, nlc,
-                                                                                       rs.p, errL, nullptr);
+                                                                                       rs.p, errL, nullptr, cap);
                 k_range_check<<<(uint32_t)std::min<uint64_t>(div_up(nlc, 256), 4096), 256, 0, s>>>(
-                    keys.p, rs.p, nlc, bsh, lowbits, sbits, errL, nullptr, 0);
+                    keys.p, rs.p, nlc, bsh, lowbits, sbits, errL, nullptr, 0, cap);
             }
             check_launch("range starts");
             JAS_HIP(hipMemcpyAsync(&herr, flags.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
             if ((herr & 8u) == 0) {
+                cap = herr & 128u ? kLocalCapKeys : kLocalShortCap;
                 db->trace.stride = stride;
+                db->trace.lcap = cap;
                 break;
             }
         }
@@ -1397,16 +1427,9 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             uint64_t *rptr_g = alt.p + div_up(N, 2);
             {
                 JAS_TIMED(herr & 16u ? "local_cls_wide" : "local_cls", s);
-                if (herr & 16u)
-                    k_local_cls<uint64_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
-                                                                         (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
-                                                                         rid_g.p, rptr_g, dupc.p, rowsrep, nullptr, 0,
-                                                                         nullptr);
-                else
-                    k_local_cls<uint32_t><<<(uint32_t)nlc, kLNT, 0, s>>>(keys.p, sbits, smask, bsh, lowbits, rs.p,
-                                                                         (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg,
-                                                                         rid_g.p, rptr_g, dupc.p, rowsrep, nullptr, 0,
-                                                                         nullptr);
+                launch_local_cls((herr & 16u) != 0, cap, (uint32_t)nlc, s, keys.p, sbits, smask, bsh, lowbits,
+                                 (const uint64_t *)rs.p, (uint32_t)nlc, cnt.p, keep ? 1 : 0, Sg, rid_g.p, rptr_g,
+                                 dupc.p, rowsrep, (const uint64_t *)nullptr, (uint64_t)0, errL);
                 k_sum_replicas<<<1, 64, 0, s>>>(rowsrep, kStatReplicas, st.p + ST_ROWS);
             }
             check_launch("local classify");
@@ -1421,7 +1444,9 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
             JAS_HIP(hipMemcpyAsync(&t3[0], offD.p + nlc, 8, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipMemcpyAsync(&t3[1], offS.p + nlc, 8, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipMemcpyAsync(&t3[2], offR.p + nlc, 8, hipMemcpyDeviceToHost, s));
+            JAS_HIP(hipMemcpyAsync(&herr, flags.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
+            if (herr & 8u) fail(JAS_EDEVICE, "local classify: a range exceeds the kernel's capacity");
             NDk = t3[0];
             NS = t3[1];
             R = t3[2];
@@ -1854,9 +1879,9 @@ void encode_planned(PlanState &p, const uint64_t *ids, const uint64_t *offsets, 
     {
         JAS_TIMED("range_starts", s);
         k_range_starts<<<(uint32_t)div_up(nlc + 1, 256 / kWave), 256, 0, s>>>(K, Ncap, bsh, p.stride, nlc, p.rs.p,
-                                                                               err, dsz);
+                                                                               err, dsz, p.lcap);
         k_range_check<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(nlc, 256), 4096)), 256, 0, s>>>(
-            K, p.rs.p, nlc, bsh, lowbits, sbits, err, dsz, p.stride);  // bit 16 matters only to narrow plans
+            K, p.rs.p, nlc, bsh, lowbits, sbits, err, dsz, p.stride, p.lcap);  // bit 16 matters only to narrow plans
     }
     check_launch("range starts (planned)");
     const uint64_t ndup = (uint64_t)std::max<int32_t>(n, 1);
@@ -1865,14 +1890,8 @@ void encode_planned(PlanState &p, const uint64_t *ids, const uint64_t *offsets, 
     uint64_t *rptr_g = F + div_up(Ncap, 2);
     {
         JAS_TIMED(p.wide ? "local_cls_wide" : "local_cls", s);
-        if (p.wide)
-            k_local_cls<uint64_t><<<(uint32_t)nlc, kLNT, 0, s>>>(K, sbits, smask, bsh, lowbits, p.rs.p, (uint32_t)nlc,
-                                                                 p.cnt.p, 0, Sg, p.rid_g.p, rptr_g, p.dupc.p, rowsrep,
-                                                                 dsz, p.stride, err);
-        else
-            k_local_cls<uint32_t><<<(uint32_t)nlc, kLNT, 0, s>>>(K, sbits, smask, bsh, lowbits, p.rs.p, (uint32_t)nlc,
-                                                                 p.cnt.p, 0, Sg, p.rid_g.p, rptr_g, p.dupc.p, rowsrep,
-                                                                 dsz, p.stride, err);
+        launch_local_cls(p.wide, p.lcap, (uint32_t)nlc, s, K, sbits, smask, bsh, lowbits, (const uint64_t *)p.rs.p,
+                         (uint32_t)nlc, p.cnt.p, 0, Sg, p.rid_g.p, rptr_g, p.dupc.p, rowsrep, dsz, p.stride, err);
         k_sum_replicas<<<1, 64, 0, s>>>(rowsrep, kStatReplicas, p.st.p + ST_ROWS);
     }
     check_launch("local classify (planned)");

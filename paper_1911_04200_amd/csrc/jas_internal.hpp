@@ -204,6 +204,7 @@ struct EncodeTrace {
     bool wide = false;        // 64-bit keys in LDS
     bool pairs = false;       // row lists as sorted pair words
     uint64_t stride = 0;      // range stride used
+    uint32_t lcap = 0;        // most keys per range of the LDS kernel used
     uint64_t N = 0, nlc = 0, ND = 0, NS = 0, R = 0, QD = 0, QL = 0, nb = 0, Hw = 0, H = 0, P = 0;
 };
 }  // namespace jas
@@ -309,7 +310,11 @@ struct SortPlan {
 };
 constexpr uint64_t kBucketKeys = 512;
 constexpr int32_t kSampleMajorMaxN = 10240;  // LDS row of per-sample counters (6 bytes each); < 2^16
-constexpr uint32_t kLocalCapKeys = 6144;  // keys one LDS range can hold
+constexpr uint32_t kLocalCapKeys = 6144;   // most keys one LDS range can hold
+constexpr uint32_t kLocalShortCap = 4096;  // ranges no longer than this run four blocks per CU (else three)
+// Range strides the encoder tries in turn until no range exceeds
+// kLocalCapKeys; shorter ones leave room for larger buckets.
+constexpr uint64_t kLocalStrides[2] = {3072, 2048};
 SortPlan sort_plan(uint64_t N, uint32_t U);
 
 // Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;
@@ -331,6 +336,7 @@ struct PlanState {
     uint32_t U = 0, sbits = 0, batch_bits = 0, word_bits = 64, dmin = 2;
     SortPlan sort;
     uint64_t stride = 4096;
+    uint32_t lcap = kLocalCapKeys;
     bool wide = false;
     // capacities
     uint64_t Ncap = 0, nlc_cap = 0, Rcap = 0, QDcap = 0, QLcap = 0, Hwcap = 0, Hcap = 0, Pcap = 0, tile_cap = 0,

@@ -131,7 +131,8 @@ jas_status jas_plan_create(const uint64_t *ids, const uint64_t *offsets, int32_t
         p.word_bits = wb;
         p.dmin = dmin;
         p.sort = sort_plan(tr.N, U);
-        p.stride = tr.stride ? tr.stride : 4096;
+        p.stride = tr.stride ? tr.stride : kLocalStrides[0];
+        p.lcap = tr.lcap ? tr.lcap : kLocalShortCap;
         p.wide = tr.wide;
         p.ldw = div_up((uint64_t)n, 128) * 128;
         p.Ncap = std::max<uint64_t>(grow(tr.N, headroom, 64), kLocalCapKeys + 1);

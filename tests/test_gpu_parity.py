@@ -230,20 +230,27 @@ def max_range_len(ids, off, U, stride):
     return int(np.max(np.diff(starts)))
 
 
-def test_shorter_ranges_when_a_bucket_is_large():
-    """Clusters of IDs make buckets of ~2500 keys: with 4096-key strides some
-    range exceeds the 6144 keys one block holds, so the encoder tries 3072 and
-    finishes in LDS all the same."""
+@pytest.mark.parametrize("U,per_cluster,tries", [(36, 26, 1), (36, 36, 2), (28, 36, 1)])
+def test_longer_ranges_when_a_bucket_is_large(U, per_cluster, tries):
+    """Clusters of IDs make buckets of 90 * per_cluster keys.  With 26 per
+    cluster (~2300 keys) some 3072-key-stride range exceeds the 4096 keys the
+    four-blocks-per-CU kernel holds, so the kernel for 6144-key ranges runs;
+    with 36 (~3200 keys) and U = 36 some range exceeds even 6144 keys at that
+    stride and the encoder tries 2048.  Either way the ranges are finished in
+    LDS, with keys held in 64 bits there for U = 36 and in 32 for U = 28."""
     rng = np.random.default_rng(11)
-    U, n = 36, 90
+    n = 90
     sets = []
     for _ in range(n):
         parts = [rng.integers(0, 1 << U, 2000, dtype=np.uint64)]
         for k in range(8):
-            parts.append((np.uint64(k << 32) + rng.choice(1 << 20, 26, replace=False)).astype(np.uint64))
+            parts.append((np.uint64(k << (U - 4)) + rng.choice(1 << 20, per_cluster, replace=False)).astype(np.uint64))
         sets.append(np.concatenate(parts))
     ids, off = csr(sets)
-    assert max_range_len(ids, off, U, 4096) > 6144 >= max_range_len(ids, off, U, 3072)
+    if tries == 1:
+        assert 6144 >= max_range_len(ids, off, U, 3072) > 4096
+    else:
+        assert max_range_len(ids, off, U, 3072) > 6144 >= max_range_len(ids, off, U, 2048) > 4096
     ref = oracle.all_pairs(ids, off)
     cabi.jas_timing_report()
     cabi.jas_timing_enable(True)
@@ -253,7 +260,8 @@ def test_shorter_ranges_when_a_bucket_is_large():
         rep = cabi.jas_timing_report()
         cabi.jas_timing_enable(False)
     assert_matches(res, ref)
-    assert rep["range_starts"][0] == 2 and "local_cls_wide" in rep and "host:classify_fallback" not in rep
+    assert rep["range_starts"][0] == tries and "host:classify_fallback" not in rep
+    assert ("local_cls_wide" if U == 36 else "local_cls") in rep
 
 
 @pytest.mark.parametrize("case", ["uniform", "uniform_u24", "narrow_ids"])
