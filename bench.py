@@ -38,7 +38,7 @@ def kernel_source_hash(kernel: str) -> str:
            "pair_count": "gram.hip", "cls_count": "encode.hip", "cls_write": "encode.hip",
            "local_cls": "encode.hip", "local_cls_wide": "encode.hip", "local_move": "encode.hip", "pair_emit": "encode.hip",
            "pair_sort": "radix.hip",
-           "pack": "encode.hip", "build_keys": "encode.hip"}.get(kernel)
+           "pack": "encode.hip", "build_keys": "encode.hip", "count_digits": "encode.hip"}.get(kernel)
     if src is None:
         return ""
     h = hashlib.sha256()
@@ -55,6 +55,8 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
         return "hbm", 8.0 * N / 1e9, "GB/s", "8 B per key per pass (read)"
     if kernel == "build_keys":
         return "hbm", 16.0 * N / 1e9, "GB/s", "16 B per entry (read ID 8 + write key 8)"
+    if kernel == "count_digits":
+        return "hbm", 8.0 * N / 1e9, "GB/s", "8 B per entry (read ID)"
     if kernel == "cls_count":
         return "hbm", 8.0 * N / 1e9, "GB/s", "8 B per sorted key (read)"
     if kernel == "cls_write":

@@ -8,6 +8,7 @@
 #include <set>
 
 #include "jas_internal.hpp"
+#include "onesweep_index.hpp"
 
 namespace jas {
 
@@ -72,6 +73,15 @@ void check_hip(hipError_t e, const char *what) {
 uint64_t card_limit() {
     constexpr uint64_t kLimit = uint64_t(1) << 31;
     const char *e = std::getenv("JAS_TEST_CARD_LIMIT");
+    if (!e || !*e) return kLimit;
+    char *end = nullptr;
+    const unsigned long long v = std::strtoull(e, &end, 10);
+    return (end && *end == 0 && v > 0 && v < kLimit) ? (uint64_t)v : kLimit;
+}
+
+uint64_t scatter_count_limit() {
+    constexpr uint64_t kLimit = onesweep::kValMask;
+    const char *e = std::getenv("JAS_TEST_SCATTER_LIMIT");
     if (!e || !*e) return kLimit;
     char *end = nullptr;
     const unsigned long long v = std::strtoull(e, &end, 10);
@@ -251,20 +261,29 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
                 JAS_TIMED("zero_u32", s);
                 k_zero_u64<<<64, 256, 0, s>>>(ghist.p, (uint64_t)kGhistReplicas * kMaxPasses * 256);
             }
-            build_keys(dids, doff, n, N, sbits, U, plan, keys.p, err.p, ghist.p, s);
+            // with a global sort its first pass forms the keys from the IDs
+            const bool from_ids = plan.top_bits > 0 && N > 1;
+            build_keys(dids, doff, n, N, sbits, U, plan, from_ids ? nullptr : keys.p, err.p, ghist.p, s);
             uint32_t herr = 0;
             JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
             if (herr) fail(JAS_EINVAL, "jas_encode: an ID is >= 2^universe_bits");
-            ids_d.release();
             JAS_HOST_TIMED("sort_enqueue");
             const uint32_t lo = sbits + U - plan.top_bits, hi = sbits + U;
-            db->trace.onesweep = plan.top_bits == 0 ||
-                                 radix_sort_onesweep(keys, alt, N, lo, hi, plan.width, ghist.p, err.p, s, &tb);
+            KeySource src;
+            src.ids = dids;
+            src.off = doff;
+            src.n = n;
+            src.sbits = sbits;
+            db->trace.onesweep = !from_ids || radix_sort_onesweep(keys, alt, N, lo, hi, plan.width, ghist.p, err.p,
+                                                                  s, &tb, nullptr, &src);
             if (!db->trace.onesweep) {
+                // the single-pass sort declined before any pass: form the keys, then sort them
+                build_keys(dids, doff, n, N, sbits, U, plan, keys.p, err.p, ghist.p, s);
                 RadixWork rw;
                 radix_sort_u64(keys, alt, N, lo, hi, rw, s, &tb);
             }
+            ids_d.release();
             JAS_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
             JAS_HIP(hipStreamSynchronize(s));
             if (herr) fail(JAS_EDEVICE, "jas_encode: the radix sort's look-back waited too long (result discarded)");

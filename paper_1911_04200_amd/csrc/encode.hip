@@ -56,13 +56,15 @@ static_assert(kStatReplicas == kStatReplicasPub, "counter replicas");
 // Keys of one chunk (kChunk entries) per block, and the totals of every digit
 // of every global sort pass (ghist, kGhistReplicas copies summed later), which
 // the single-pass scatter needs.  Pass q's digit is ID bits
-// [idlo + width*q, idlo + width*(q+1)).
-__global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__ ids,
-                                                     const uint64_t *__restrict__ off, int32_t n, uint64_t N,
-                                                     uint32_t sbits, uint64_t hi_mask, uint64_t *__restrict__ keys,
-                                                     uint32_t *err, uint32_t npass, uint32_t idlo, uint32_t width,
-                                                     unsigned long long *__restrict__ ghist,
-                                                     const uint64_t *__restrict__ dsz) {
+// [idlo + width*q, idlo + width*(q+1)).  k_count_digits only counts (and
+// checks the IDs): the sort's first pass then forms the keys itself.
+template <bool kWrite>
+__device__ __forceinline__ void build_keys_chunk(const uint64_t *__restrict__ ids, const uint64_t *__restrict__ off,
+                                                 int32_t n, uint64_t N, uint32_t sbits, uint64_t hi_mask,
+                                                 uint64_t *__restrict__ keys, uint32_t *err, uint32_t npass,
+                                                 uint32_t idlo, uint32_t width,
+                                                 unsigned long long *__restrict__ ghist,
+                                                 const uint64_t *__restrict__ dsz) {
     __shared__ int32_t s_lo, s_hi;
     __shared__ uint32_t gh[kMaxPasses][256];
     const uint32_t tid = threadIdx.x;
@@ -74,18 +76,20 @@ __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__
     const uint32_t dmask = (1u << width) - 1u;
 #pragma unroll
     for (int k = 0; k < kMaxPasses; ++k) gh[k][tid] = 0;
-    if (tid == 0) {
+    if (kWrite && tid == 0) {
         s_lo = find_sample(off, 0, n - 1, b0);
         s_hi = find_sample(off, s_lo, n - 1, b1 - 1);
     }
     __syncthreads();
     uint32_t bad = 0;
-    int32_t lo = s_lo;
+    int32_t lo = kWrite ? s_lo : 0;
     for (uint64_t t = b0 + tid; t < b1; t += kNT) {
-        lo = find_sample(off, lo, s_hi, t);  // t only grows, so the search range only shrinks
         const uint64_t id = ids[t];
         bad |= (id & hi_mask) != 0;
-        keys[t] = (id << sbits) | (uint64_t)lo;
+        if constexpr (kWrite) {
+            lo = find_sample(off, lo, s_hi, t);  // t only grows, so the search range only shrinks
+            keys[t] = (id << sbits) | (uint64_t)lo;
+        }
         for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(uint32_t)(id >> (idlo + width * q)) & dmask], 1u);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1u);
@@ -93,6 +97,22 @@ __global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__
     unsigned long long *g = ghist + (uint64_t)(blockIdx.x % kGhistReplicas) * kMaxPasses * 256;
     for (uint32_t q = 0; q < npass; ++q)
         if (gh[q][tid]) atomicAdd(&g[q * 256 + tid], (unsigned long long)gh[q][tid]);
+}
+
+__global__ __launch_bounds__(kNT) void k_build_keys(const uint64_t *__restrict__ ids,
+                                                     const uint64_t *__restrict__ off, int32_t n, uint64_t N,
+                                                     uint32_t sbits, uint64_t hi_mask, uint64_t *__restrict__ keys,
+                                                     uint32_t *err, uint32_t npass, uint32_t idlo, uint32_t width,
+                                                     unsigned long long *__restrict__ ghist,
+                                                     const uint64_t *__restrict__ dsz) {
+    build_keys_chunk<true>(ids, off, n, N, sbits, hi_mask, keys, err, npass, idlo, width, ghist, dsz);
+}
+
+__global__ __launch_bounds__(kNT) void k_count_digits(const uint64_t *__restrict__ ids, uint64_t N, uint64_t hi_mask,
+                                                       uint32_t *err, uint32_t npass, uint32_t idlo, uint32_t width,
+                                                       unsigned long long *__restrict__ ghist,
+                                                       const uint64_t *__restrict__ dsz) {
+    build_keys_chunk<false>(ids, nullptr, 0, N, 0, hi_mask, nullptr, err, npass, idlo, width, ghist, dsz);
 }
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t len, uint64_t v) {
@@ -1332,10 +1352,14 @@ void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_
     const uint64_t hi_mask = U >= 64 ? 0 : ~((uint64_t(1) << U) - 1);
     const uint64_t blocks = div_up(N, kChunk);
     if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "too many IDs");
-    {
+    if (keys) {
         JAS_TIMED("build_keys", s);
         k_build_keys<<<(uint32_t)blocks, kNT, 0, s>>>(ids, offsets, n, N, sbits, hi_mask, keys, err, plan.npass,
                                                       U - plan.top_bits, plan.width, ghist, nullptr);
+    } else {
+        JAS_TIMED("count_digits", s);
+        k_count_digits<<<(uint32_t)blocks, kNT, 0, s>>>(ids, N, hi_mask, err, plan.npass, U - plan.top_bits,
+                                                        plan.width, ghist, nullptr);
     }
     check_launch("build keys");
 }
@@ -1854,7 +1878,12 @@ void encode_planned(PlanState &p, const uint64_t *ids, const uint64_t *offsets, 
     check_launch("plan begin");
     // keys and the global sort on the top ID bits
     const uint64_t hi_mask = U >= 64 ? 0 : ~((uint64_t(1) << U) - 1);
-    {
+    if (p.sort.top_bits > 0) {  // the sort's first pass forms the keys
+        JAS_TIMED("count_digits", s);
+        k_count_digits<<<(uint32_t)div_up(Ncap, kChunk), kNT, 0, s>>>(ids, Ncap, hi_mask, err, p.sort.npass,
+                                                                       U - p.sort.top_bits, p.sort.width, p.ghist.p,
+                                                                       dsz);
+    } else {
         JAS_TIMED("build_keys", s);
         k_build_keys<<<(uint32_t)div_up(Ncap, kChunk), kNT, 0, s>>>(ids, offsets, n, Ncap, sbits, hi_mask, p.keys.p,
                                                                      err, p.sort.npass, U - p.sort.top_bits,
@@ -1869,8 +1898,15 @@ void encode_planned(PlanState &p, const uint64_t *ids, const uint64_t *offsets, 
         ob.status = p.os_status.p;
         ob.ticket = p.os_ticket.p;
         ob.status_words = p.os_status.n;
+        KeySource src;
+        src.ids = ids;
+        src.off = offsets;
+        src.n = n;
+        src.sbits = sbits;
+        src.tinfo = p.os_tinfo.p;
+        src.tinfo_words = p.os_tinfo.n;
         const uint32_t lo = sbits + U - p.sort.top_bits, hi = sbits + U;
-        radix_sort_onesweep_planned(K, F, dsz + PZ_N, Ncap, lo, hi, p.sort.width, p.ghist.p, err, ob, s);
+        radix_sort_onesweep_planned(K, F, dsz + PZ_N, Ncap, lo, hi, p.sort.width, p.ghist.p, err, ob, s, &src);
     }
     // ranges of whole buckets, finished in LDS
     const uint32_t lowbits = U - p.sort.top_bits;

@@ -272,9 +272,23 @@ void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, u
 // sets bit 1 of err[0] (the result is then invalid).
 constexpr uint32_t kMaxPasses = 8;
 constexpr uint32_t kGhistReplicas = 32;
+// Where a sort's first pass takes its keys from when it forms them from CSR
+// sets itself (key = id << sbits | sample): the IDs and offsets of the n >= 1
+// sets, and a device buffer of 2 words per 8192-key tile (the samples holding
+// the tile's first and last entries), which the sort fills first.  The eager
+// sort allocates tinfo itself.
+struct KeySource {
+    const uint64_t *ids = nullptr, *off = nullptr;
+    int32_t n = 0;
+    uint32_t sbits = 0;
+    uint32_t *tinfo = nullptr;
+    uint64_t tinfo_words = 0;
+};
+uint64_t onesweep_tile_keys_u64();  // entries per tile of the 64-bit sort
+// With src, keys.p is not read: the first pass forms the keys from src.
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
                          uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
-                         hipStream_t s, Budget *b, Arena *ar = nullptr);
+                         hipStream_t s, Budget *b, Arena *ar = nullptr, const KeySource *src = nullptr);
 bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,
                              uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
                              hipStream_t s, Budget *b, Arena *ar = nullptr);
@@ -291,7 +305,8 @@ uint64_t onesweep_status_words(uint64_t N, bool u32);
 // is too large, err |= 2 when a look-back gave up.
 void radix_sort_onesweep_planned(uint64_t *&keys, uint64_t *&alt, const uint64_t *dN, uint64_t Ncap,
                                  uint32_t lo_bit, uint32_t hi_bit, uint32_t width, const unsigned long long *ghist,
-                                 uint32_t *err, const OnesweepBufs &b, hipStream_t s);
+                                 uint32_t *err, const OnesweepBufs &b, hipStream_t s,
+                                 const KeySource *src = nullptr);
 void radix_sort_onesweep_u32_planned(uint32_t *&keys, uint32_t *&alt, const uint64_t *dN, uint64_t Ncap,
                                      uint32_t lo_bit, uint32_t hi_bit, uint32_t width,
                                      const unsigned long long *ghist, uint32_t *err, const OnesweepBufs &b,
@@ -319,6 +334,8 @@ SortPlan sort_plan(uint64_t N, uint32_t U);
 
 // Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;
 // ghist: totals of every digit of the plan's passes (kGhistReplicas copies).
+// With keys == nullptr only the IDs are checked and the digits counted (the
+// sort then forms the keys from the IDs in its first pass).
 void build_keys(const uint64_t *ids, const uint64_t *offsets, int32_t n, uint64_t N, uint32_t sbits, uint32_t U,
                 const SortPlan &plan, uint64_t *keys, uint32_t *err, unsigned long long *ghist, hipStream_t s);
 
@@ -348,7 +365,7 @@ struct PlanState {
     DevBuf<uint32_t> err, cnt, rdeg, tcnt, bs, pk, palt;
     DevBuf<unsigned long long> ghist, gh, dupc, lprep, st;
     DevBuf<uint64_t> os_gstart, os_maxima, os2_gstart, os2_maxima;
-    DevBuf<uint32_t> os_status, os_ticket, os2_status, os2_ticket;
+    DevBuf<uint32_t> os_status, os_ticket, os2_status, os2_ticket, os_tinfo;
     DevBuf<int64_t> card;
     DevBuf<uint64_t> W;
     uint32_t *pairs_final = nullptr;  // the buffer holding the sorted pair words after the pair sort
@@ -403,6 +420,11 @@ __device__ __forceinline__ bool plan_aborted(const uint64_t *dsz) { return dsz &
 // integer below 2^31, read on the host at every check) lowers the bound so
 // tests can reach the overflow error with small inputs.
 uint64_t card_limit();
+// Largest digit total the eager single-pass sort takes (larger ones exceed
+// its 30-bit look-back counts and the sort declines, for the reduce-then-scan
+// passes).  JAS_TEST_SCATTER_LIMIT (a positive integer, read on the host at
+// every sort) lowers it so tests reach the declined path with small inputs.
+uint64_t scatter_count_limit();
 
 inline uint32_t ceil_log2_u64(uint64_t v) {
     uint32_t b = 0;

@@ -166,6 +166,8 @@ jas_status jas_plan_create(const uint64_t *ids, const uint64_t *offsets, int32_t
         plan_buf(p.os_maxima, kMaxPasses, s, &bud, "plan digit maxima");
         plan_buf(p.os_status, onesweep_status_words(p.Ncap, false), s, &bud, "plan look-back status");
         plan_buf(p.os_ticket, 1, s, &bud, "plan tile ticket");
+        if (p.sort.top_bits > 0)
+            plan_buf(p.os_tinfo, 2 * div_up(p.Ncap, onesweep_tile_keys_u64()), s, &bud, "plan tile samples");
         plan_buf(p.rs, p.nlc_cap + 1, s, &bud, "plan range starts");
         plan_buf(p.dupc, (uint64_t)n + kStatReplicasPub, s, &bud, "plan repeat counts");
         plan_buf(p.cnt, 3 * p.nlc_cap, s, &bud, "plan range counts");

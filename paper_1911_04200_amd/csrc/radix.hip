@@ -153,6 +153,14 @@ __global__ __launch_bounds__(kNT) void k_radix_scatter(const uint64_t *__restric
 // a 30-bit count; the caller guarantees every digit total is < 2^30.  The
 // same kernel sorts 64-bit keys (the encoder and the query path) and 32-bit
 // row-list pair words.
+// A load the compiler may issue through the scalar cache: the data stays
+// unchanged while the kernel runs (written by an earlier launch) and the
+// address is the same across the wave.
+template <class T>
+__device__ __forceinline__ T const_load(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)(p);
+}
+
 using onesweep::kFlagA;
 using onesweep::kFlagP;
 using onesweep::kValMask;
@@ -170,11 +178,18 @@ __device__ __forceinline__ uint32_t status_load(const uint32_t *p) {
 constexpr int kOsNT = 512;  // 512 x 16 keys measured best of 512 x 8/12/16 and 1024 x 16 (one block per CU)
 constexpr int kOsWaves = kOsNT / kWave;
 
-template <class K, int R, bool kTable>
+// With kFromIds the pass reads CSR IDs and forms each key id << src.sbits |
+// sample itself.  Its digit is ID bits only (shift >= src.sbits), so the IDs
+// are ranked as loaded (each rank starts as soon as its load arrives) and the
+// sample joins a key when it is placed in LDS: src.tinfo holds the samples of
+// the tile's first and last entries (k_tile_samples), and an entry's sample is
+// the first one plus the sample starts inside the tile at or before it (a
+// uniform loop of scalar loads, run only by tiles that span several samples).
+template <class K, int R, bool kTable, bool kFromIds = false>
 __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_onesweep(
     const K *__restrict__ in, K *__restrict__ out, uint64_t N, uint32_t shift, uint32_t nbits,
     const uint64_t *__restrict__ gstart, uint32_t *__restrict__ status, uint32_t *__restrict__ ticket,
-    uint32_t ntiles, uint32_t *__restrict__ err, const uint64_t *__restrict__ dN) {
+    uint32_t ntiles, uint32_t *__restrict__ err, const uint64_t *__restrict__ dN, KeySource src) {
     __shared__ K stage[kOsNT * R];
     __shared__ uint32_t wcnt[kOsWaves][kRadix];
     __shared__ uint32_t tdp[kRadix];
@@ -188,6 +203,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
     }
     const bool digit = tid < kRadix;  // this thread owns digit tid
     const uint32_t mask = (1u << nbits) - 1u;
+    const uint32_t dshift = kFromIds ? shift - src.sbits : shift;  // digit position in a loaded value
     const uint64_t lt = lanemask_lt();
     const uint64_t gs = digit ? gstart[tid] : 0;
     // while ranking, the first kOsWaves*256 words of stage are per-wave tables
@@ -203,13 +219,16 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             if constexpr (kTable) reinterpret_cast<uint64_t *>(stage)[i] = 0;
         }
         __syncthreads();
-        const uint32_t tile = tile_sh;
+        const uint32_t tile = __builtin_amdgcn_readfirstlane(tile_sh);  // uniform: every thread reads the same ticket
         if (tile >= ntiles) break;  // uniform: every thread read the same ticket
         const uint64_t t0 = onesweep::tile_first(tile, kOsNT * R);
         const uint64_t c1 = onesweep::tile_end(tile, kOsNT * R, N);
         const uint64_t wb = t0 + (uint64_t)w * ((kOsNT * R) / kOsWaves);
         K key[R];
         uint32_t rank[R];
+        static_assert(!kFromIds || sizeof(K) == 8, "keys formed from IDs are 64-bit");
+        uint64_t tsmp = 0;  // samples of the tile's first and last entries (low, high half), loaded ahead
+        if constexpr (kFromIds) tsmp = const_load(reinterpret_cast<const uint64_t *>(src.tinfo) + tile);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const uint64_t t = wb + (uint64_t)j * kWave + lane;
@@ -229,7 +248,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
                 for (int j = h * (R / 2); j < (h + 1) * (R / 2); ++j) {
                     const uint64_t t = wb + (uint64_t)j * kWave + lane;
                     const bool valid = t < c1;
-                    const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
+                    const uint32_t d = (uint32_t)(key[j] >> dshift) & mask;
                     uint64_t peers = 0;
                     if (valid) {
                         atomicOr((unsigned long long *)&T[d], 1ull << lane);
@@ -256,7 +275,7 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             for (int j = 0; j < R; ++j) {
                 const uint64_t t = wb + (uint64_t)j * kWave + lane;
                 const bool valid = t < c1;
-                const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
+                const uint32_t d = (uint32_t)(key[j] >> dshift) & mask;
                 uint64_t peers = __ballot(valid);
                 for (uint32_t b = 0; b < nbits; ++b) {
                     const bool bit = (d >> b) & 1u;
@@ -293,12 +312,29 @@ __global__ __launch_bounds__(kOsNT) __attribute__((amdgpu_waves_per_eu(4))) void
             }
         }
         __syncthreads();
+        if constexpr (kFromIds) {
+            // the sample starts inside the tile lie in (t0, c1), so tile-relative
+            // positions compare in 32 bits
+            const uint32_t s0 = (uint32_t)tsmp, s1 = (uint32_t)(tsmp >> 32);
+            const uint32_t cnt = (uint32_t)(c1 - t0), wl = (uint32_t)(wb - t0) + lane;
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const uint64_t t = wb + (uint64_t)j * kWave + lane;
-            if (t < c1) {
-                const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
-                stage[wcnt[w][d] + rank[j]] = key[j];
+            for (int j = 0; j < R; ++j) {
+                const uint32_t li = wl + j * kWave;  // position in the tile
+                if (li < cnt) {
+                    const uint32_t d = (uint32_t)(key[j] >> dshift) & mask;
+                    uint32_t smp = s0;
+                    for (uint32_t k = s0 + 1; k <= s1; ++k) smp += li >= (uint32_t)(const_load(src.off + k) - t0);
+                    stage[wcnt[w][d] + rank[j]] = (key[j] << src.sbits) | smp;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const uint64_t t = wb + (uint64_t)j * kWave + lane;
+                if (t < c1) {
+                    const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
+                    stage[wcnt[w][d] + rank[j]] = key[j];
+                }
             }
         }
         // then look back for the digit's global offset: kLookWindow
@@ -375,6 +411,20 @@ __global__ void k_fill32(uint32_t *p, uint64_t len) {
         p[i] = 0;
 }
 
+// Per tile of tile_keys entries: tinfo[2 t] and tinfo[2 t + 1] = the samples
+// holding the tile's first and last entries.
+__global__ void k_tile_samples(const uint64_t *__restrict__ off, int32_t n, uint64_t N, uint32_t tile_keys,
+                               uint32_t *__restrict__ tinfo, const uint64_t *__restrict__ dN) {
+    if (dN) N = min(N, *dN);
+    const uint64_t ntiles = onesweep::num_tiles(N, tile_keys);
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const int32_t s0 = find_sample(off, 0, n - 1, onesweep::tile_first(t, tile_keys));
+        tinfo[2 * t] = (uint32_t)s0;
+        tinfo[2 * t + 1] = (uint32_t)find_sample(off, s0, n - 1, onesweep::tile_end(t, tile_keys, N) - 1);
+    }
+}
+
 }  // namespace
 
 SortPlan sort_plan(uint64_t N, uint32_t U) {
@@ -432,10 +482,44 @@ void radix_sort_u64(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, u
 namespace jas {
 
 namespace {
+// Fills src.tinfo for tiles of tile_keys entries (after checking its size).
+void tile_samples(const KeySource &src, uint64_t Ncap, uint32_t tile_keys, const uint64_t *dN, hipStream_t s) {
+    const uint64_t ntiles = onesweep::num_tiles(Ncap, tile_keys);
+    if (!src.ids || !src.off || !src.tinfo || src.n < 1 || src.tinfo_words < 2 * ntiles)
+        fail(JAS_EDEVICE, "sort from IDs: tile sample buffer does not cover the tiles");
+    {
+        JAS_TIMED("tile_samples", s);
+        k_tile_samples<<<(uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(ntiles, 256), 4096)), 256, 0, s>>>(
+            src.off, src.n, Ncap, tile_keys, src.tinfo, dN);
+    }
+    check_launch("tile samples");
+}
+
+// Launches one pass; the first reads src.ids when the keys are formed from IDs.
+template <class K, int Rounds, bool Table>
+void onesweep_pass(bool from_ids, const K *in, K *out, uint64_t N, uint32_t bit, uint32_t nbits,
+                   const uint64_t *gstart, uint32_t *status, uint32_t *ticket, uint32_t ntiles, uint32_t *err,
+                   const uint64_t *dN, const KeySource *src, uint32_t grid, hipStream_t s) {
+    if (from_ids && bit < src->sbits) fail(JAS_EDEVICE, "sort from IDs: a digit below the ID bits");
+    if constexpr (sizeof(K) == 8) {
+        if (from_ids) {
+            k_radix_onesweep<K, Rounds, Table, true><<<grid, kOsNT, 0, s>>>(
+                reinterpret_cast<const K *>(src->ids), out, N, bit, nbits, gstart, status, ticket, ntiles, err, dN,
+                *src);
+            return;
+        }
+    }
+    if (from_ids) fail(JAS_EDEVICE, "sort from IDs: 64-bit keys only");
+    k_radix_onesweep<K, Rounds, Table><<<grid, kOsNT, 0, s>>>(in, out, N, bit, nbits, gstart, status, ticket, ntiles,
+                                                             err, dN, KeySource{});
+}
+
+// With src the keys are formed from CSR sets by the first pass (keys.p is
+// not read); otherwise keys holds them.
 template <class K, int Rounds, bool Table>
 bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit, uint32_t hi_bit, uint32_t width,
                    const unsigned long long *ghist, uint32_t *err, hipStream_t s, Budget *b, Arena *ar,
-                   const char *name) {
+                   const char *name, const KeySource *src = nullptr) {
     if (N <= 1 || hi_bit <= lo_bit) return true;
     if (width < 1 || width > 8) return false;
     const uint32_t npass = (hi_bit - lo_bit + width - 1) / width;
@@ -452,7 +536,7 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
     JAS_HIP(hipMemcpyAsync(hm, maxima.p, sizeof(uint64_t) * npass, hipMemcpyDeviceToHost, s));
     JAS_HIP(hipStreamSynchronize(s));
     for (uint32_t q = 0; q < npass; ++q)
-        if (hm[q] >= (uint64_t)kValMask) return false;
+        if (hm[q] >= std::min<uint64_t>(kValMask, scatter_count_limit())) return false;
     const uint64_t ntiles = onesweep::num_tiles(N, (uint32_t)kOsNT * Rounds);
     if (ntiles > 0xFFFFFFFFull) return false;
     // persistent blocks: two per CU (256 CUs) fit, never more than there are tiles
@@ -471,6 +555,16 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
         fail(JAS_EDEVICE, "single-pass scatter: buffer sizes do not cover its indexing");
     for (uint32_t q = 0; q < npass; ++q)
         if (hm[q] > kValMask) fail(JAS_EDEVICE, "single-pass scatter: a digit total exceeds the status count");
+    KeySource ks;
+    DevBuf<uint32_t> tinfo;
+    if (src) {
+        ks = *src;
+        temp_buf(tinfo, 2 * ntiles, s, b, ar, "tile samples");
+        ks.tinfo = tinfo.p;
+        ks.tinfo_words = tinfo.n;
+        tile_samples(ks, N, (uint32_t)kOsNT * Rounds, nullptr, s);
+        src = &ks;
+    }
     for (uint32_t q = 0; q < npass; ++q) {
         const uint32_t bit = lo_bit + width * q;
         const uint32_t nbits = min(width, hi_bit - bit);
@@ -483,8 +577,8 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
         check_launch("look-back reset");
         {
             JAS_TIMED(name, s);
-            k_radix_onesweep<K, Rounds, Table><<<grid, kOsNT, 0, s>>>(keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix, status.p,
-                                                  ticket.p, (uint32_t)ntiles, err, nullptr);
+            onesweep_pass<K, Rounds, Table>(src && q == 0, keys.p, alt.p, N, bit, nbits, gstart.p + q * kRadix,
+                                            status.p, ticket.p, (uint32_t)ntiles, err, nullptr, src, grid, s);
         }
         check_launch("radix scatter (look-back)");
         swap_bufs(keys, alt);
@@ -499,7 +593,7 @@ bool onesweep_sort(DevBuf<K> &keys, DevBuf<K> &alt, uint64_t N, uint32_t lo_bit,
 template <class K, int Rounds, bool Table>
 void onesweep_sort_planned(K *&keys, K *&alt, const uint64_t *dN, uint64_t Ncap, uint32_t lo_bit, uint32_t hi_bit,
                            uint32_t width, const unsigned long long *ghist, uint32_t *err, const OnesweepBufs &b,
-                           hipStream_t s, const char *name) {
+                           hipStream_t s, const char *name, const KeySource *src = nullptr) {
     if (Ncap <= 1 || hi_bit <= lo_bit) return;
     const uint32_t npass = (hi_bit - lo_bit + width - 1) / width;
     if (npass > kMaxPasses || width < 1 || width > 8) fail(JAS_EUNSUPPORTED, "planned sort: bad digit plan");
@@ -511,6 +605,7 @@ void onesweep_sort_planned(K *&keys, K *&alt, const uint64_t *dN, uint64_t Ncap,
         k_digit_starts<<<1, kNT, 0, s>>>(ghist, npass, b.gstart, b.maxima, err);
     }
     check_launch("digit starts");
+    if (src) tile_samples(*src, Ncap, (uint32_t)kOsNT * Rounds, dN, s);
     const uint32_t grid = (uint32_t)std::min<uint64_t>(ntiles, 256 * 2);
     for (uint32_t q = 0; q < npass; ++q) {
         const uint32_t bit = lo_bit + width * q;
@@ -524,9 +619,8 @@ void onesweep_sort_planned(K *&keys, K *&alt, const uint64_t *dN, uint64_t Ncap,
         check_launch("look-back reset");
         {
             JAS_TIMED(name, s);
-            k_radix_onesweep<K, Rounds, Table><<<grid, kOsNT, 0, s>>>(keys, alt, Ncap, bit, nbits,
-                                                                       b.gstart + q * kRadix, b.status, b.ticket,
-                                                                       (uint32_t)ntiles, err, dN);
+            onesweep_pass<K, Rounds, Table>(src && q == 0, keys, alt, Ncap, bit, nbits, b.gstart + q * kRadix,
+                                            b.status, b.ticket, (uint32_t)ntiles, err, dN, src, grid, s);
         }
         check_launch("radix scatter (planned)");
         std::swap(keys, alt);
@@ -542,9 +636,9 @@ uint64_t onesweep_status_words(uint64_t N, bool u32) {
 
 void radix_sort_onesweep_planned(uint64_t *&keys, uint64_t *&alt, const uint64_t *dN, uint64_t Ncap,
                                  uint32_t lo_bit, uint32_t hi_bit, uint32_t width, const unsigned long long *ghist,
-                                 uint32_t *err, const OnesweepBufs &b, hipStream_t s) {
+                                 uint32_t *err, const OnesweepBufs &b, hipStream_t s, const KeySource *src) {
     onesweep_sort_planned<uint64_t, 16, false>(keys, alt, dN, Ncap, lo_bit, hi_bit, width, ghist, err, b, s,
-                                               "radix_onesweep");
+                                               "radix_onesweep", src);
 }
 
 void radix_sort_onesweep_u32_planned(uint32_t *&keys, uint32_t *&alt, const uint64_t *dN, uint64_t Ncap,
@@ -560,11 +654,13 @@ void radix_sort_onesweep_u32_planned(uint32_t *&keys, uint32_t *&alt, const uint
 constexpr int kU64Rounds = 16;
 constexpr bool kU64Table = false;
 
+uint64_t onesweep_tile_keys_u64() { return (uint64_t)kOsNT * kU64Rounds; }
+
 bool radix_sort_onesweep(DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, uint64_t N, uint32_t lo_bit,
                          uint32_t hi_bit, uint32_t width, const unsigned long long *ghist, uint32_t *err,
-                         hipStream_t s, Budget *b, Arena *ar) {
+                         hipStream_t s, Budget *b, Arena *ar, const KeySource *src) {
     return onesweep_sort<uint64_t, kU64Rounds, kU64Table>(keys, alt, N, lo_bit, hi_bit, width, ghist, err, s, b, ar,
-                                                          "radix_onesweep");
+                                                          "radix_onesweep", src);
 }
 
 bool radix_sort_onesweep_u32(DevBuf<uint32_t> &keys, DevBuf<uint32_t> &alt, uint64_t N, uint32_t lo_bit,

@@ -230,6 +230,33 @@ def max_range_len(ids, off, U, stride):
     return int(np.max(np.diff(starts)))
 
 
+@pytest.mark.parametrize("declined", [False, True])
+def test_first_sort_pass_forms_the_keys(monkeypatch, declined):
+    """With a global sort the digits are counted from the IDs alone and the
+    sort's first pass forms the keys (id << s | sample) itself, the sample of
+    each tile found once; when the single-pass sort declines (a digit total
+    above its look-back counts, forced here by a lowered test limit), the keys
+    are formed by a kernel of their own and sorted by reduce-then-scan
+    passes.  Both give the oracle's result."""
+    spec = synth.scaled(synth.workload("paperlike"), n=300, size_scale=0.004, pool_scale=0.004)
+    ids, off = synth.generate(spec)
+    # a few empty sets and many short ones, so that tiles hold several samples
+    sets = [ids[int(off[i]):int(off[i + 1])] for i in range(spec.n)]
+    sets[1] = sets[7] = np.zeros(0, np.uint64)
+    sets[20:120] = [s[:37] for s in sets[20:120]]
+    ids, off = csr(sets)
+    if declined:
+        monkeypatch.setenv("JAS_TEST_SCATTER_LIMIT", "100")
+    ref = oracle.all_pairs(ids, off)
+    res, st, names = encode_timed(ids, off, spec.universe_bits)
+    assert_matches(res, ref)
+    assert "count_digits" in names
+    if declined:
+        assert "build_keys" in names and "radix_scatter" in names and "radix_onesweep" not in names
+    else:
+        assert "build_keys" not in names and "radix_onesweep" in names
+
+
 @pytest.mark.parametrize("U,per_cluster,tries", [(36, 26, 1), (36, 36, 2), (28, 36, 1)])
 def test_longer_ranges_when_a_bucket_is_large(U, per_cluster, tries):
     """Clusters of IDs make buckets of 90 * per_cluster keys.  With 26 per
