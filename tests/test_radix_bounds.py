@@ -49,3 +49,35 @@ def test_paperlike_size_in_bounds(emul, giveup):
     assert "tiles 204657" in out and "fails 0" in out
     if giveup:
         assert "giveups 0 " not in out
+
+
+@pytest.mark.parametrize("sizes", ["large", "small", "empty_runs"])
+def test_sample_of_an_entry_from_its_tile(sizes):
+    """The first scatter pass forms key id << s | sample: the sample of entry t
+    in a tile [t0, t1) is the sample s0 of the tile's first entry plus the
+    number of sample starts off[k], s0 < k <= s1 (s1 = the sample of the
+    tile's last entry), at or before t, each compared as a position in the
+    tile (off[k] - t0 < 8192).  Checked for every entry against the plain
+    definition (the last sample whose start is <= t) on offsets with large
+    sets, small sets and runs of empty sets."""
+    import numpy as np
+
+    rng = np.random.default_rng({"large": 1, "small": 2, "empty_runs": 3}[sizes])
+    if sizes == "large":
+        lens = rng.integers(5000, 40000, 60)
+    elif sizes == "small":
+        lens = rng.integers(1, 40, 3000)
+    else:
+        lens = rng.integers(0, 200, 2000) * (rng.random(2000) < 0.3)
+        lens[:5] = 0
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    N, tk = int(off[-1]), 8192
+    want = np.searchsorted(off, np.arange(N), side="right") - 1  # last s with off[s] <= t
+    for t0 in range(0, N, tk):
+        t1 = min(N, t0 + tk)
+        s0, s1 = int(want[t0]), int(want[t1 - 1])
+        starts = off[s0 + 1:s1 + 1] - t0
+        assert np.all((starts > 0) & (starts < tk))
+        li = np.arange(t1 - t0)
+        got = s0 + (li[:, None] >= starts[None, :]).sum(axis=1)
+        assert np.array_equal(got, want[t0:t1]), t0
