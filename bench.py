@@ -100,11 +100,14 @@ def algorithmic(kernel: str, stats: dict, n: int, N: int, passes: int):
 
 
 def kernel_label(name: str) -> str:
-    """The timing label of a HIP kernel's name as rocprofv3 prints it."""
-    base = name.split("::")[-1].split("(")[0]
-    tmpl = base.split("<", 1)[1] if "<" in base else ""
-    base = base.split("<")[0]
-    base = base[2:] if base.startswith("k_") else base
+    """The timing label of a HIP kernel's name as rocprofv3 prints it
+    (namespaces, template arguments and the parameter list around it)."""
+    import re
+
+    m = re.search(r"(?:^|::)(k_\w+)(?:<([^()]*)>)?(?:\(|$)", name)
+    if m is None:
+        return name.split("(")[0].split("::")[-1]
+    base, tmpl = m.group(1)[2:], m.group(2) or ""
     if base == "radix_onesweep" and tmpl.startswith("unsigned int"):
         return "pair_sort"  # the same kernel on 32-bit pair words
     if base in ("gram_fp4_wide",):
