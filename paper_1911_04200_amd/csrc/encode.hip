@@ -41,6 +41,7 @@ constexpr uint64_t kChunk = 65536;         // elements per classify block
 constexpr int32_t kHistMax = 16384;        // LDS column histogram up to this n
 constexpr uint32_t kPackCols = 8192;       // LDS words per pack pass, at most
 constexpr uint32_t kPackLoads = 8;         // sample loads in flight per lane in k_pack
+constexpr uint32_t kPackFlat = 4096;       // k_pack: word rows with at most this many entries spread them over the block
 
 enum { ST_PAIRS = 0, ST_ROWS, ST_NNZW, ST_F, ST_LISTPAIRS, ST_N };
 static_assert(ST_N == ST_N_ && ST_ROWS == ST_ROWS_ && ST_NNZW == ST_NNZW_ && ST_F == ST_F_ &&
@@ -81,6 +82,16 @@ __device__ __forceinline__ void build_keys_chunk(const uint64_t *__restrict__ id
         s_hi = find_sample(off, s_lo, n - 1, b1 - 1);
     }
     __syncthreads();
+    // A wave whose entries share a digit above the lowest (sets of ascending,
+    // dense IDs) adds them with one atomic instead of 64 on one LDS word.  Each
+    // wave decides once, from the top digit of its first 64 entries, whether
+    // to look for such runs (IDs in no particular order never share it).
+    bool agg = false;
+    if (npass > 1) {
+        const uint64_t t = b0 + tid;
+        const uint32_t d = t < b1 ? (uint32_t)(ids[t] >> (idlo + width * (npass - 1))) & dmask : 0u;
+        agg = __ballot(t < b1 && d == (uint32_t)__builtin_amdgcn_readfirstlane(d)) == __ballot(t < b1);
+    }
     uint32_t bad = 0;
     int32_t lo = kWrite ? s_lo : 0;
     for (uint64_t t = b0 + tid; t < b1; t += kNT) {
@@ -90,7 +101,21 @@ __device__ __forceinline__ void build_keys_chunk(const uint64_t *__restrict__ id
             lo = find_sample(off, lo, s_hi, t);  // t only grows, so the search range only shrinks
             keys[t] = (id << sbits) | (uint64_t)lo;
         }
-        for (uint32_t q = 0; q < npass; ++q) atomicAdd(&gh[q][(uint32_t)(id >> (idlo + width * q)) & dmask], 1u);
+        if (agg) {  // wave-uniform
+            const uint64_t active = __ballot(true);
+            for (uint32_t q = 0; q < npass; ++q) {
+                const uint32_t d = (uint32_t)(id >> (idlo + width * q)) & dmask;
+                if (q > 0 && __ballot(d == (uint32_t)__builtin_amdgcn_readfirstlane(d)) == active) {
+                    if (lane_id() == (uint32_t)__builtin_ctzll(active))
+                        atomicAdd(&gh[q][d], (uint32_t)__popcll(active));
+                } else {
+                    atomicAdd(&gh[q][d], 1u);
+                }
+            }
+        } else {
+            for (uint32_t q = 0; q < npass; ++q)
+                atomicAdd(&gh[q][(uint32_t)(id >> (idlo + width * q)) & dmask], 1u);
+        }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(err, 1u);
     __syncthreads();
@@ -453,7 +478,9 @@ __global__ __launch_bounds__(kLNT) __attribute__((amdgpu_waves_per_eu(local_cls_
     if (L > 0) {
         const uint64_t bf = bucket_of(K[s0], bsh), bl = bucket_of(K[s1 - 1], bsh);
         kbase = (bf << lowbits) << sbits;  // bf > 0 only when lowbits < U <= 63
-        nb = lowbits + dev_ceil_log2(bl - bf + 1);
+        // with no ID bits below the buckets (every ID bit sorted globally)
+        // the range is sorted already: a bucket is one ID, its keys in sample order
+        nb = lowbits == 0 ? 0u : lowbits + dev_ceil_log2(bl - bf + 1);
     }
     {
         // every load of the range in flight at once, then the LDS stores
@@ -888,6 +915,7 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
     extern __shared__ unsigned long long lw[];
     __shared__ uint64_t rstart[kWave + 1];  // exclusive prefix of the rows' degrees
     __shared__ uint64_t rbase[kWave];       // first pair of each row in S
+    __shared__ uint8_t prow[kPackFlat];  // up to kPackFlat entries: the row of each entry
     __shared__ uint32_t zsh[2];  // nonzero words of the row (b = 32: of each half)
     const uint32_t tid = threadIdx.x, lane = lane_id();
     if (plan_aborted(dsz)) return;
@@ -932,9 +960,9 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
             for (uint32_t i = tid; i < cn; i += kNT) lw[i] = 0;
             __syncthreads();
             const uint64_t P = rstart[kWave];
-            if (P >= (uint64_t)kWave * kWave) {
-                // long rows (64 samples or more on average): the lanes of a
-                // wave walk one row at a time
+            if (P > kPackFlat) {
+                // long rows (more than kPackFlat entries in all): the lanes of
+                // a wave walk one row at a time
                 // (kPackLoads loads in flight per lane before their ORs; a
                 // sample of ~0u lies past every chunk)
                 const uint32_t wv = tid / kWave;
@@ -953,20 +981,21 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
                     }
                 }
             } else {
-                // short rows: one thread per entry, its row found by binary
-                // search; kPackLoads entries per thread in flight
+                // up to kPackFlat entries: one thread per entry, its row read from prow
+                // (filled by the waves a row at a time, once per word row);
+                // kPackLoads entries per thread in flight
+                if (c0 == 0) {
+                    for (uint32_t t = tid / kWave; t < kWave; t += kNT / kWave)
+                        for (uint32_t e = (uint32_t)rstart[t] + lane; e < (uint32_t)rstart[t + 1]; e += kWave)
+                            prow[e] = (uint8_t)t;
+                    __syncthreads();
+                }
                 for (uint64_t p0 = tid; p0 < P; p0 += (uint64_t)kNT * kPackLoads) {
                     uint32_t v[kPackLoads], row[kPackLoads];
 #pragma unroll
                     for (uint32_t u = 0; u < kPackLoads; ++u) {
                         const uint64_t p = p0 + (uint64_t)u * kNT;
-                        // row of entry p: largest t with rstart[t] <= p
-                        uint32_t lo = 0, hi = kWave - 1;
-                        while (lo < hi) {
-                            const uint32_t mid = (lo + hi + 1) >> 1;
-                            if (rstart[mid] <= p) lo = mid;
-                            else hi = mid - 1;
-                        }
+                        const uint32_t lo = p < P ? prow[p] : 0u;
                         row[u] = lo;
                         v[u] = p < P ? S[rbase[lo] + (p - rstart[lo])] : ~0u;
                     }
@@ -1408,7 +1437,11 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         uint32_t *errL = reinterpret_cast<uint32_t *>(flags.p);
         uint64_t herr = 8, nlc = 0;
         uint32_t cap = kLocalCapKeys;
-        for (const uint64_t stride : kLocalStrides) {
+        // with every ID bit sorted globally the ranges need no LDS passes, and
+        // longer ranges (fewer blocks) pay: 4096 is tried first
+        const uint64_t strides[] = {kLocalWideStride, kLocalStrides[0], kLocalStrides[1]};
+        for (const uint64_t stride : strides) {
+            if (stride == kLocalWideStride && lowbits != 0) continue;
             nlc = div_up(N, stride);
             {
                 JAS_TIMED("fill_u64", s);

@@ -330,6 +330,7 @@ constexpr uint32_t kLocalShortCap = 4096;  // ranges no longer than this run fou
 // Range strides the encoder tries in turn until no range exceeds
 // kLocalCapKeys; shorter ones leave room for larger buckets.
 constexpr uint64_t kLocalStrides[2] = {3072, 2048};
+constexpr uint64_t kLocalWideStride = 4096;  // tried first when the ranges need no LDS sort passes
 SortPlan sort_plan(uint64_t N, uint32_t U);
 
 // Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;

@@ -257,6 +257,28 @@ def test_first_sort_pass_forms_the_keys(monkeypatch, declined):
         assert "build_keys" not in names and "radix_onesweep" in names
 
 
+def test_every_id_bit_sorted_globally():
+    """A small universe and many entries (U = 8, 90,000 entries with repeats):
+    the global sort covers every ID bit, so each bucket is one ID with its
+    keys in sample order and the ranges (from 4096-key strides) are finished
+    in LDS with no sort passes."""
+    rng = np.random.default_rng(21)
+    sets = [rng.integers(0, 256, 300, dtype=np.uint64) for _ in range(300)]
+    sets[4] = np.zeros(0, np.uint64)
+    ids, off = csr(sets)
+    assert -(-ids.size // 512) > 128  # ceil(log2(N / 512)) >= U
+    ref = oracle.all_pairs(ids, off)
+    cabi.jas_timing_report()
+    cabi.jas_timing_enable(True)
+    try:
+        res, st = gpu_all_pairs(ids, off, 8)
+    finally:
+        rep = cabi.jas_timing_report()
+        cabi.jas_timing_enable(False)
+    assert_matches(res, ref)
+    assert rep["range_starts"][0] == 1 and "local_cls" in rep and "host:classify_fallback" not in rep
+
+
 @pytest.mark.parametrize("U,per_cluster,tries", [(36, 26, 1), (36, 36, 2), (28, 36, 1)])
 def test_longer_ranges_when_a_bucket_is_large(U, per_cluster, tries):
     """Clusters of IDs make buckets of 90 * per_cluster keys.  With 26 per
