@@ -1679,6 +1679,67 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         check_launch("row split");
     }
 
+    // --- row lists, first part -------------------------------------------------
+    // Up to kSampleMajorMaxN samples: the rows' pairs, sorted by their smaller
+    // sample, straight from the shared pairs.  Otherwise (or if that sort
+    // cannot run) the rows as a CSR of samples, summed pair by pair.  The
+    // pairs are emitted and sorted on a side stream while the packed rows are
+    // packed on s (the two read the same rows and write different arrays); s
+    // waits for the side stream before anything of the pair path is freed or
+    // read.
+    db->n_list = QL;
+    bool pairs_done = false;
+    const bool pair_form = QL > 0 && n <= kSampleMajorMaxN;
+    DevBuf<uint64_t> npo;
+    DevBuf<uint32_t> pk, palt, perr;
+    DevBuf<unsigned long long> pgh;
+    uint64_t P = 0;
+    uint32_t psb = 0, pwidth = 0;
+    hipStream_t s2 = nullptr;
+    StreamJoin join;  // after the buffers: on an error s waits for s2 before they are freed
+    if (pair_form) {
+        // pairs per group of 64 list rows (one wave of the emission), scanned
+        const uint64_t nw = div_up(QL, (uint64_t)kWave);
+        DevBuf<uint64_t> np, tmp2;
+        np.alloc(nw, s, tb, true, "row group pair counts");
+        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
+            {
+                JAS_TIMED("list_npairs", st_);
+                k_list_wave_pairs<<<b, 256, 0, st_>>>(Lrow.p, rdegp, QL, np.p, nullptr);
+            }
+        });
+        check_launch("row pair counts");
+        npo.alloc(nw + 1, s, tb, true, "row group pair offsets");
+        tmp2.alloc(scan_tmp_elems(nw), s, tb, true, "scan scratch");
+        scan_excl_u64(np.p, npo.p, nw, tmp2.p, s);
+        P = to_host_u64(npo.p + nw, s);
+        np.release();
+        tmp2.release();
+        psb = std::max<uint32_t>(1, ceil_log2_u64((uint64_t)n));
+        const uint32_t npass = (psb + 7) / 8;
+        pwidth = (psb + npass - 1) / npass;
+        if (npass > kPairPasses) fail(JAS_EUNSUPPORTED, "row-list pairs: too many sample bits");
+        pk.alloc(P + 2, s, &db->budget, false, "row-list pairs");
+        palt.alloc(P + 2, s, tb, true, "row-list pairs (second buffer)");
+        pgh.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, tb, true, "pair digit totals");
+        perr.alloc(2, s, tb, true, "pair sort flag");
+        s2 = side_stream();
+        stream_after(s2, s);  // everything the pair path reads is on s so far
+        join.waiter = s;
+        join.on = s2;
+        {
+            JAS_TIMED("fill_u64", s2);
+            k_fill_u64<<<64, 256, 0, s2>>>((uint64_t *)pgh.p, (uint64_t)kGhistReplicas * kMaxPasses * 256, 0);
+            k_fill_u64<<<1, 64, 0, s2>>>((uint64_t *)perr.p, 1, 0);
+        }
+        {
+            JAS_TIMED("pair_emit", s2);
+            k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 8192), 256, 0, s2>>>(
+                Lrow.p, rptrp, rdegp, Sp, QL, npo.p, pk.p, npass, pwidth, pgh.p, nullptr);
+        }
+        check_launch("pair emit");
+    }
+
     // --- packed rows: batches, word rows, pack -------------------------------
     const uint64_t ldw = div_up((uint64_t)std::max<int32_t>(n, 1), 128) * 128;
     const uint32_t wb = db->word_bits;
@@ -1739,54 +1800,14 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
     }
     db->H = H;
 
-    // --- row lists -----------------------------------------------------------
-    // Up to kSampleMajorMaxN samples: the rows' pairs, sorted by their smaller
-    // sample, straight from the shared pairs.  Otherwise (or if that sort
-    // cannot run) the rows as a CSR of samples, summed pair by pair.
-    db->n_list = QL;
-    bool pairs_done = false;
-    if (QL > 0 && n <= kSampleMajorMaxN) {
-        // pairs per group of 64 list rows (one wave of the emission), scanned
-        const uint64_t nw = div_up(QL, (uint64_t)kWave);
-        DevBuf<uint64_t> np, npo, tmp2;
-        np.alloc(nw, s, tb, true, "row group pair counts");
-        launch_1d(QL, s, [&](uint32_t b, hipStream_t st_) {
-            {
-                JAS_TIMED("list_npairs", st_);
-                k_list_wave_pairs<<<b, 256, 0, st_>>>(Lrow.p, rdegp, QL, np.p, nullptr);
-            }
-        });
-        check_launch("row pair counts");
-        npo.alloc(nw + 1, s, tb, true, "row group pair offsets");
-        tmp2.alloc(scan_tmp_elems(nw), s, tb, true, "scan scratch");
-        scan_excl_u64(np.p, npo.p, nw, tmp2.p, s);
-        const uint64_t P = to_host_u64(npo.p + nw, s);
-        np.release();
-        tmp2.release();
-        const uint32_t sb = std::max<uint32_t>(1, ceil_log2_u64((uint64_t)n));
-        const uint32_t npass = (sb + 7) / 8, width = (sb + npass - 1) / npass;
-        if (npass > kPairPasses) fail(JAS_EUNSUPPORTED, "row-list pairs: too many sample bits");
-        DevBuf<uint32_t> pk, palt, perr;
-        DevBuf<unsigned long long> gh;
-        pk.alloc(P + 2, s, &db->budget, false, "row-list pairs");
-        palt.alloc(P + 2, s, tb, true, "row-list pairs (second buffer)");
-        gh.alloc((uint64_t)kGhistReplicas * kMaxPasses * 256, s, tb, true, "pair digit totals");
-        perr.alloc(2, s, tb, true, "pair sort flag");
-        {
-            JAS_TIMED("fill_u64", s);
-            k_fill_u64<<<64, 256, 0, s>>>((uint64_t *)gh.p, (uint64_t)kGhistReplicas * kMaxPasses * 256, 0);
-            k_fill_u64<<<1, 64, 0, s>>>((uint64_t *)perr.p, 1, 0);
-        }
-        {
-            JAS_TIMED("pair_emit", s);
-            k_pair_emit<<<(uint32_t)std::min<uint64_t>(div_up(QL, 256), 8192), 256, 0, s>>>(
-                Lrow.p, rptrp, rdegp, Sp, QL, npo.p, pk.p, npass, width, gh.p, nullptr);
-        }
-        check_launch("pair emit");
-        const bool ok = radix_sort_onesweep_u32(pk, palt, P, 16, 16 + sb, width, gh.p, perr.p, s, tb);
+    // --- row lists, second part: the pair sort (side stream), then s waits --
+    if (pair_form) {
+        const bool ok = radix_sort_onesweep_u32(pk, palt, P, 16, 16 + psb, pwidth, pgh.p, perr.p, s2, tb);
         uint32_t herr = 0;
-        JAS_HIP(hipMemcpyAsync(&herr, perr.p, 4, hipMemcpyDeviceToHost, s));
-        JAS_HIP(hipStreamSynchronize(s));
+        JAS_HIP(hipMemcpyAsync(&herr, perr.p, 4, hipMemcpyDeviceToHost, s2));
+        JAS_HIP(hipStreamSynchronize(s2));
+        stream_after(s, s2);
+        join.waiter = nullptr;
         if (ok && herr == 0) {
             db->n_lpairs = P;
             db->pairs = std::move(pk);

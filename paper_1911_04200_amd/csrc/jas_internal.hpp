@@ -198,6 +198,23 @@ inline void set_tile_stats(jas_encode_stats &o, uint64_t n) {
     o.word_pairs_W = o.dense_tiles * 128 * 128;
 }
 
+// A stream of the library's own on the current device (default priority, one
+// per device for the process), for work that overlaps the caller's stream
+// inside one call.
+hipStream_t side_stream();
+// Makes `waiter` wait for the work enqueued on `on` so far.
+void stream_after(hipStream_t waiter, hipStream_t on);
+// While armed (waiter set), makes waiter wait for on when it goes out of
+// scope: declared after the buffers the work on `on` uses, so that on an
+// error the buffers' stream-ordered release comes after that work.
+struct StreamJoin {
+    hipStream_t waiter = nullptr, on = nullptr;
+    StreamJoin() = default;
+    StreamJoin(const StreamJoin &) = delete;
+    StreamJoin &operator=(const StreamJoin &) = delete;
+    ~StreamJoin();
+};
+
 struct EncodeTrace {
     bool onesweep = false;    // the global sort ran as single-pass scatters
     bool local = false;       // ranges finished in LDS (no global classification)

@@ -110,6 +110,42 @@ void cache_free(void *p, bool synced) {
     g_free.emplace(b.bytes, b);
 }
 
+hipStream_t side_stream() {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;  // one per device, kept for the process
+    int dev = 0;
+    JAS_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    JAS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+    streams[dev] = st;
+    return st;
+}
+
+void stream_after(hipStream_t waiter, hipStream_t on) {
+    hipEvent_t ev = nullptr;
+    JAS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    const hipError_t e1 = hipEventRecord(ev, on);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(waiter, ev, 0) : e1;
+    (void)hipEventDestroy(ev);
+    if (e2 != hipSuccess) {
+        // cannot order the streams by an event: wait for the work itself
+        (void)hipGetLastError();
+        JAS_HIP(hipStreamSynchronize(on));
+    }
+}
+
+StreamJoin::~StreamJoin() {
+    if (!waiter) return;
+    try {
+        stream_after(waiter, on);
+    } catch (...) {
+        (void)hipStreamSynchronize(on);
+    }
+}
+
 void cache_trim() {
     std::lock_guard<std::mutex> lk(g_mu);
     release_all_locked();
