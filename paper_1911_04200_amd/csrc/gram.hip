@@ -744,25 +744,49 @@ __global__ void k_card_check(const int64_t *__restrict__ card, uint32_t n, int64
 
 __global__ void k_zero_flag(uint32_t *flag) { *flag = 0; }
 
-__global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ card, uint32_t n, int upper,
+// Full layout: row i of blocks over its n entries; the lower triangle is
+// mirrored from the upper.
+__global__ void k_finalize(int32_t *__restrict__ B, const int64_t *__restrict__ card, uint32_t n,
                            uint32_t jblocks, int64_t *__restrict__ den, double *__restrict__ J) {
     const uint32_t i = blockIdx.x / jblocks;
     const uint32_t j = (blockIdx.x % jblocks) * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    if (upper && j < i) return;
     uint64_t pos;
     int64_t b;
     if (i == j) {
-        pos = out_index(i, i, n, upper);
+        pos = out_index(i, i, n, false);
         b = card[i];
         B[pos] = (int32_t)b;
     } else if (i < j) {
-        pos = out_index(i, j, n, upper);
+        pos = out_index(i, j, n, false);
         b = B[pos];
     } else {
         pos = (uint64_t)i * n + j;
         b = B[(uint64_t)j * n + i];
         B[pos] = (int32_t)b;
+    }
+    const int64_t c = card[i] + card[j] - b;
+    if (den) den[pos] = c;
+    if (J) J[pos] = c == 0 ? 1.0 : (double)b / (double)c;
+}
+
+// Packed upper layout: rows i and n-1-i share a row of blocks over their
+// n - i and i + 1 entries (n + 1 in all), so no thread of the grid is idle.
+__global__ void k_finalize_upper(int32_t *__restrict__ B, const int64_t *__restrict__ card, uint32_t n,
+                                 uint32_t jblocks, int64_t *__restrict__ den, double *__restrict__ J) {
+    const uint32_t i0 = blockIdx.x / jblocks, i1 = n - 1 - i0;
+    const uint32_t t = (blockIdx.x % jblocks) * blockDim.x + threadIdx.x;
+    const uint32_t len0 = n - i0;  // entries of row i0
+    if (t >= (i0 == i1 ? len0 : n + 1)) return;
+    const uint32_t i = t < len0 ? i0 : i1;
+    const uint32_t j = t < len0 ? i0 + t : i1 + (t - len0);
+    const uint64_t pos = out_index(i, j, n, true);
+    int64_t b;
+    if (i == j) {
+        b = card[i];
+        B[pos] = (int32_t)b;
+    } else {
+        b = B[pos];
     }
     const int64_t c = card[i] + card[j] - b;
     if (den) den[pos] = c;
@@ -873,12 +897,19 @@ int32_t gram_variants() { return kNumVariants; }
 
 void finalize(uint32_t n, bool upper, hipStream_t s, int32_t *B, const int64_t *card, int64_t *den, double *J) {
     if (n == 0) return;
-    const uint32_t jb = (uint32_t)div_up(n, 256);
-    const uint64_t fb = (uint64_t)n * jb;
-    if (fb > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "n too large for finalize grid");
-    {
+    if (upper) {
+        // pairs of rows (i, n-1-i), the middle row alone when n is odd
+        const uint32_t jb = (uint32_t)div_up((uint64_t)n + 1, 256);
+        const uint64_t fb = div_up((uint64_t)n, 2) * jb;
+        if (fb > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "n too large for finalize grid");
         JAS_TIMED("finalize", s);
-        k_finalize<<<(uint32_t)fb, 256, 0, s>>>(B, card, n, upper, jb, den, J);
+        k_finalize_upper<<<(uint32_t)fb, 256, 0, s>>>(B, card, n, jb, den, J);
+    } else {
+        const uint32_t jb = (uint32_t)div_up(n, 256);
+        const uint64_t fb = (uint64_t)n * jb;
+        if (fb > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "n too large for finalize grid");
+        JAS_TIMED("finalize", s);
+        k_finalize<<<(uint32_t)fb, 256, 0, s>>>(B, card, n, jb, den, J);
     }
     check_launch("finalize");
 }
