@@ -631,8 +631,10 @@ __global__ __launch_bounds__(256) void k_pair_count(const uint32_t *__restrict__
                                                      uint32_t n, int32_t *__restrict__ B, int upper,
                                                      const uint64_t *__restrict__ dsz) {
     extern __shared__ uint32_t lds[];
-    uint32_t *cnt = lds;                                         // n counters
-    uint16_t *touched = reinterpret_cast<uint16_t *>(lds + n);  // n entries (n < 2^16)
+    uint32_t *cnt = lds;  // n counters
+    // the counters a short run touched (n < 2^16): a short run has fewer than
+    // n/8 words, so at most n/8 entries
+    uint16_t *touched = reinterpret_cast<uint16_t *>(lds + n);
     __shared__ uint32_t ntouched;
     __shared__ uint64_t seg_end;
     if (dsz) P = min(P, dsz[PZ_P]);  // a plan's db: P is the capacity, the count is on the device
@@ -1002,7 +1004,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         const uint64_t chunk = std::max<uint64_t>(kPairChunk, div_up(db->n_lpairs, kPairBlocks));
         const uint64_t blocks = div_up(db->n_lpairs, chunk);
         if (blocks > 0xFFFFFFFFull) fail(JAS_EUNSUPPORTED, "row lists too long");
-        const size_t lds = (size_t)n * (sizeof(uint32_t) + sizeof(uint16_t));
+        const size_t lds = (size_t)n * sizeof(uint32_t) + ((size_t)n / 8 + 1) * sizeof(uint16_t);
         {
             JAS_TIMED("pair_count", s);
             k_pair_count<<<(uint32_t)blocks, 256, lds, s>>>(db->pairs.p, db->n_lpairs, chunk, n, B, upper, db->dsz);
