@@ -627,7 +627,8 @@ __global__ void k_list_pairs(const uint64_t *__restrict__ lp, const uint32_t *__
 constexpr uint64_t kPairChunk = 16384;
 constexpr uint64_t kPairBlocks = 4096;
 
-__global__ __launch_bounds__(256) void k_pair_count(const uint32_t *__restrict__ pairs, uint64_t P, uint64_t chunk,
+constexpr int kPairCountNT = 512;  // threads per pair-count block (one LDS row of counters each)
+__global__ __launch_bounds__(kPairCountNT) void k_pair_count(const uint32_t *__restrict__ pairs, uint64_t P, uint64_t chunk,
                                                      uint32_t n, int32_t *__restrict__ B, int upper,
                                                      const uint64_t *__restrict__ dsz) {
     extern __shared__ uint32_t lds[];
@@ -1007,7 +1008,7 @@ void gram(const jas_db *db, uint32_t flags, hipStream_t s, int32_t *B, int64_t *
         const size_t lds = (size_t)n * sizeof(uint32_t) + ((size_t)n / 8 + 1) * sizeof(uint16_t);
         {
             JAS_TIMED("pair_count", s);
-            k_pair_count<<<(uint32_t)blocks, 256, lds, s>>>(db->pairs.p, db->n_lpairs, chunk, n, B, upper, db->dsz);
+            k_pair_count<<<(uint32_t)blocks, kPairCountNT, lds, s>>>(db->pairs.p, db->n_lpairs, chunk, n, B, upper, db->dsz);
         }
         check_launch("row-list pairs");
     } else if (db->n_list > 0) {
