@@ -844,7 +844,8 @@ __global__ __launch_bounds__(kNT) void k_row_split(const uint32_t *__restrict__ 
     }
 }
 
-// Batches of packed rows.
+// Batches of packed rows.  Drow maps packed row q to its shared row; null
+// when every shared row is packed (q itself), here and in k_pack.
 // (planned: flags for q < QD, zeros up to the capacity QDcap = the host QD)
 __global__ void k_batch_flag(const uint64_t *Drow, const uint64_t *row_id, uint64_t QD, uint32_t bbits,
                              uint32_t *bs, const uint64_t *__restrict__ dsz) {
@@ -855,8 +856,8 @@ __global__ void k_batch_flag(const uint64_t *Drow, const uint64_t *row_id, uint6
             bs[q] = 0;
             continue;
         }
-        const uint64_t b = row_id[Drow[q]] >> bbits;
-        bs[q] = (q == 0) || b != (row_id[Drow[q - 1]] >> bbits);
+        const uint64_t b = row_id[Drow ? Drow[q] : q] >> bbits;
+        bs[q] = (q == 0) || b != (row_id[Drow ? Drow[q - 1] : q - 1] >> bbits);
     }
 }
 
@@ -945,7 +946,7 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
             }
             uint64_t base = 0, deg = 0;
             if (qi < q1) {
-                const uint64_t r = Drow[qi];
+                const uint64_t r = Drow ? Drow[qi] : qi;
                 base = row_ptr[r];
                 deg = row_deg[r];
             }
@@ -1033,10 +1034,12 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
     }
 }
 
-// Row lists: CSR of the rows of degree 2..dmin-1.
+// Row lists: CSR of the rows of degree 2..dmin-1.  Lrow maps list row j to
+// its shared row; null when every shared row is a list row (j itself), here
+// and in k_list_wave_pairs and k_pair_emit.
 __global__ void k_list_deg(const uint64_t *Lrow, const uint32_t *row_deg, uint64_t QL, uint64_t *deg) {
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t r = Lrow[j];
+        const uint64_t r = Lrow ? Lrow[j] : j;
         deg[j] = row_deg[r];
     }
 }
@@ -1044,7 +1047,7 @@ __global__ void k_list_deg(const uint64_t *Lrow, const uint32_t *row_deg, uint64
 __global__ void k_list_gather(const uint64_t *Lrow, const uint64_t *row_ptr, const uint32_t *row_deg, const uint32_t *S,
                               const uint64_t *lptr, uint64_t QL, uint32_t *lsmp) {
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < QL; j += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t r = Lrow[j];
+        const uint64_t r = Lrow ? Lrow[j] : j;
         const uint64_t a0 = row_ptr[r], d = row_deg[r], o = lptr[j];
         for (uint64_t k = 0; k < d; ++k) lsmp[o + k] = S[a0 + k];
     }
@@ -1068,7 +1071,7 @@ __global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint32_t *row_deg,
         const uint64_t j = g * kWave + lane;
         uint64_t np = 0;
         if (j < QL) {
-            const uint64_t r = Lrow[j];
+            const uint64_t r = Lrow ? Lrow[j] : j;
             const uint64_t d = row_deg[r];
             np = d * (d - 1) / 2;
         }
@@ -1190,7 +1193,7 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
         const uint32_t last = (uint32_t)(min(r0 + kWave, QL) - 1 - r0);  // lane of the wave's last row
         uint64_t e0 = 0, e1 = 0;
         if (r < QL) {
-            const uint64_t rr = Lrow[r];
+            const uint64_t rr = Lrow ? Lrow[r] : r;
             e0 = row_ptr[rr];
             e1 = e0 + row_deg[rr];
         }
@@ -1670,13 +1673,17 @@ void encode_sorted(jas_db *db, DevBuf<uint64_t> &keys, DevBuf<uint64_t> &alt, ui
         scan_excl_u32(tcnt.p, toff.p, nt, tmp.p, s);
         QD = to_host_u64(toff.p + nt, s);
         QL = R - QD;
-        Drow.alloc(QD, s, tb, true, "packed rows");
-        Lrow.alloc(QL, s, tb, true, "list rows");
-        {
-            JAS_TIMED("row_split", s);
-            k_row_split<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, toff.p, Drow.p, Lrow.p, nullptr);
+        // when every shared row is of one form the split is the identity: the
+        // kernels take a null Drow / Lrow as row q = q
+        if (QD > 0 && QL > 0) {
+            Drow.alloc(QD, s, tb, true, "packed rows");
+            Lrow.alloc(QL, s, tb, true, "list rows");
+            {
+                JAS_TIMED("row_split", s);
+                k_row_split<<<(uint32_t)nt, kNT, 0, s>>>(rdegp, R, db->dmin, toff.p, Drow.p, Lrow.p, nullptr);
+            }
+            check_launch("row split");
         }
-        check_launch("row split");
     }
 
     // --- row lists, first part -------------------------------------------------
