@@ -820,6 +820,9 @@ __global__ __launch_bounds__(kNT) void k_row_split(const uint32_t *__restrict__ 
                                                     uint64_t *__restrict__ Lrow, const uint64_t *__restrict__ dsz) {
     __shared__ uint64_t sh[kWaves];
     if (plan_aborted(dsz)) return;
+    // planned: with every shared row of one form the maps are the identity
+    // (the kernels that read them check the same sizes)
+    if (dsz && (dsz[PZ_QD] == 0 || dsz[PZ_QL] == 0)) return;
     if (dsz) R = dsz[PZ_R];
     const uint64_t r0 = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)threadIdx.x * kSplitPer;
     uint32_t flags = 0, nd = 0;
@@ -844,6 +847,15 @@ __global__ __launch_bounds__(kNT) void k_row_split(const uint32_t *__restrict__ 
     }
 }
 
+// Whether the packed-row map Drow / the list-row map Lrow is read: a null map,
+// or (planned) every shared row of that form, is the identity.
+__device__ __forceinline__ bool packed_map_used(const uint64_t *Drow, const uint64_t *dsz) {
+    return Drow && !(dsz && dsz[PZ_QL] == 0);
+}
+__device__ __forceinline__ bool list_map_used(const uint64_t *Lrow, const uint64_t *dsz) {
+    return Lrow && !(dsz && dsz[PZ_QD] == 0);
+}
+
 // Batches of packed rows.  Drow maps packed row q to its shared row; null
 // when every shared row is packed (q itself), here and in k_pack.
 // (planned: flags for q < QD, zeros up to the capacity QDcap = the host QD)
@@ -851,6 +863,7 @@ __global__ void k_batch_flag(const uint64_t *Drow, const uint64_t *row_id, uint6
                              uint32_t *bs, const uint64_t *__restrict__ dsz) {
     if (plan_aborted(dsz)) return;
     const uint64_t qd = dsz ? dsz[PZ_QD] : QD;
+    if (!packed_map_used(Drow, dsz)) Drow = nullptr;
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < QD; q += (uint64_t)gridDim.x * blockDim.x) {
         if (q >= qd) {
             bs[q] = 0;
@@ -923,6 +936,7 @@ __global__ __launch_bounds__(kNT) void k_pack(uint64_t *__restrict__ W, uint64_t
     // planned: H is the capacity; rows from the actual count on are written as
     // zeros (they add nothing to the Gram product)
     const uint64_t Hv = dsz ? dsz[PZ_H] : H;
+    if (!packed_map_used(Drow, dsz)) Drow = nullptr;
     if (dsz) Hw = dsz[PZ_HW];
     unsigned long long nnz_acc = 0, f_acc = 0;  // this block's totals (thread 0)
     for (uint64_t w = blockIdx.x; w < H; w += gridDim.x) {
@@ -1065,6 +1079,7 @@ __global__ void k_list_wave_pairs(const uint64_t *Lrow, const uint32_t *row_deg,
     // planned: QL is the capacity; groups past the actual rows count nothing
     const uint64_t nw = (QL + kWave - 1) / kWave;
     if (dsz) QL = dsz[PZ_QL];
+    if (!list_map_used(Lrow, dsz)) Lrow = nullptr;
     const uint32_t lane = lane_id();
     for (uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; g < nw;
          g += ((uint64_t)gridDim.x * blockDim.x) / kWave) {
@@ -1172,6 +1187,7 @@ __global__ __launch_bounds__(256) void k_pair_emit(const uint64_t *__restrict__ 
     __shared__ uint32_t gh[kPairPasses][256];
     if (plan_aborted(dsz)) return;
     if (dsz) QL = dsz[PZ_QL];
+    if (!list_map_used(Lrow, dsz)) Lrow = nullptr;
     // per wave: the output stage, or (for waves whose pairs do not fit it)
     // the rows' first output words, degrees and first entries
     __shared__ uint64_t stgb[256 / kWave][kEmitStage / 2];
