@@ -245,7 +245,7 @@ jas_status jas_encode(const uint64_t *ids, const uint64_t *offsets, int32_t n, c
         // range in LDS by encode_sorted).  Both buffers get two spare entries:
         // after the sort the free one holds the shared pairs and row pointers.
         DevBuf<uint64_t> keys, alt;
-        const SortPlan plan = sort_plan(N, U);
+        const SortPlan plan = sort_plan(N, U, sbits);
         if (N > 0) {
             DevBuf<uint32_t> err;
             keys.alloc(N + 2, s, &tb, true, "sort keys");

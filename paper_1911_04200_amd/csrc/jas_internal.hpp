@@ -336,11 +336,15 @@ uint64_t radix_work_bytes(uint64_t N);
 // sorted globally (npass passes of `width` bits); that makes every bucket of
 // equal top bits contiguous, with about kBucketKeys keys per bucket for
 // uniformly spread IDs, and the encoder finishes each run of whole buckets in
-// LDS.
+// LDS.  Buckets of about 2 kBucketKeys keys (one sorted bit fewer) are taken
+// when a range's keys then still fit 32 bits in LDS: the ID bits below the
+// buckets, a few bits for the buckets a range spans (kSpanBits) and the
+// sample bits.
 struct SortPlan {
     uint32_t top_bits = 0, npass = 0, width = 8;
 };
 constexpr uint64_t kBucketKeys = 512;
+constexpr uint32_t kSpanBits = 4;
 constexpr int32_t kSampleMajorMaxN = 10240;  // LDS row of per-sample counters (6 bytes each); < 2^16
 constexpr uint32_t kLocalCapKeys = 6144;   // most keys one LDS range can hold
 constexpr uint32_t kLocalShortCap = 4096;  // ranges no longer than this run four blocks per CU (else three)
@@ -348,7 +352,7 @@ constexpr uint32_t kLocalShortCap = 4096;  // ranges no longer than this run fou
 // kLocalCapKeys; shorter ones leave room for larger buckets.
 constexpr uint64_t kLocalStrides[2] = {3072, 2048};
 constexpr uint64_t kLocalWideStride = 4096;  // tried first when the ranges need no LDS sort passes
-SortPlan sort_plan(uint64_t N, uint32_t U);
+SortPlan sort_plan(uint64_t N, uint32_t U, uint32_t sbits);
 
 // Keys (id << sbits) | sample from CSR sets; err[0] |= 1 for an ID >= 2^U;
 // ghist: totals of every digit of the plan's passes (kGhistReplicas copies).

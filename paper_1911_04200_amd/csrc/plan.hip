@@ -130,7 +130,7 @@ jas_status jas_plan_create(const uint64_t *ids, const uint64_t *offsets, int32_t
         p.batch_bits = bb;
         p.word_bits = wb;
         p.dmin = dmin;
-        p.sort = sort_plan(tr.N, U);
+        p.sort = sort_plan(tr.N, U, sbits);
         p.stride = tr.stride ? tr.stride : kLocalStrides[0];
         p.lcap = tr.lcap ? tr.lcap : kLocalShortCap;
         p.wide = tr.wide;

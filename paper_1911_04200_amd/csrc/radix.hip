@@ -427,10 +427,12 @@ __global__ void k_tile_samples(const uint64_t *__restrict__ off, int32_t n, uint
 
 }  // namespace
 
-SortPlan sort_plan(uint64_t N, uint32_t U) {
+SortPlan sort_plan(uint64_t N, uint32_t U, uint32_t sbits) {
     SortPlan p;
     if (N <= kLocalCapKeys) return p;  // one LDS range holds everything
     p.top_bits = std::min<uint32_t>(U, ceil_log2_u64(div_up(N, kBucketKeys)));
+    const uint32_t fewer = std::min<uint32_t>(U, ceil_log2_u64(div_up(N, 2 * kBucketKeys)));
+    if (fewer > 0 && (U - fewer) + kSpanBits + sbits <= 32) p.top_bits = fewer;
     p.npass = (p.top_bits + 7) / 8;
     p.width = p.npass ? (p.top_bits + p.npass - 1) / p.npass : 8;
     return p;

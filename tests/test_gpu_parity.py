@@ -222,7 +222,12 @@ def max_range_len(ids, off, U, stride):
     n = off.size - 1
     N = ids.size
     sbits = max(1, int(np.ceil(np.log2(n))))
+    # the encoder's choice of sorted top bits: buckets of about 512 keys, or
+    # about 1024 when a range's keys still fit 32 bits (4 bits for its span)
     tb = min(U, int(np.ceil(np.log2(-(-N // 512)))))
+    fewer = min(U, int(np.ceil(np.log2(-(-N // 1024)))))
+    if fewer > 0 and (U - fewer) + 4 + sbits <= 32:
+        tb = fewer
     bucket = np.sort(ids >> np.uint64(U - tb), kind="stable")
     edges = np.flatnonzero(np.diff(bucket)) + 1
     edges = np.concatenate([[0], edges, [N]])
@@ -279,14 +284,15 @@ def test_every_id_bit_sorted_globally():
     assert rep["range_starts"][0] == 1 and "local_cls" in rep and "host:classify_fallback" not in rep
 
 
-@pytest.mark.parametrize("U,per_cluster,tries", [(36, 26, 1), (36, 36, 2), (28, 36, 1)])
+@pytest.mark.parametrize("U,per_cluster,tries", [(36, 26, 1), (36, 36, 2), (28, 36, 2)])
 def test_longer_ranges_when_a_bucket_is_large(U, per_cluster, tries):
     """Clusters of IDs make buckets of 90 * per_cluster keys.  With 26 per
     cluster (~2300 keys) some 3072-key-stride range exceeds the 4096 keys the
     four-blocks-per-CU kernel holds, so the kernel for 6144-key ranges runs;
-    with 36 (~3200 keys) and U = 36 some range exceeds even 6144 keys at that
-    stride and the encoder tries 2048.  Either way the ranges are finished in
-    LDS, with keys held in 64 bits there for U = 36 and in 32 for U = 28."""
+    with 36 (~3200 keys) some range exceeds even 6144 keys at that stride and
+    the encoder tries 2048.  Either way the ranges are finished in LDS, with
+    keys held in 64 bits there for U = 36 and in 32 for U = 28 (where the
+    encoder sorts one top bit fewer, as the 32-bit keys still fit)."""
     rng = np.random.default_rng(11)
     n = 90
     sets = []
