@@ -262,6 +262,36 @@ def test_first_sort_pass_forms_the_keys(monkeypatch, declined):
         assert "build_keys" not in names and "radix_onesweep" in names
 
 
+@pytest.mark.parametrize("N", [6145, 8192, 8193, 16384, 16385, 24577])
+def test_scatter_tile_edges(N):
+    """Entry counts around the single-pass scatter's 8192-entry tiles (the
+    global sort runs from 6145 entries on), with set boundaries exactly on,
+    just before and just after tile boundaries and empty sets there, so that
+    the first pass's per-tile samples (first and last entry of each tile, the
+    starts inside it) meet every case."""
+    rng = np.random.default_rng(N)
+    U = 30
+    cuts = sorted({0, N} | {c for t in range(8192, N, 8192) for c in (t - 1, t, t + 1) if 0 < c < N}
+                  | {int(x) for x in rng.integers(1, N, 6)})
+    sizes = [b - a for a, b in zip(cuts, cuts[1:])]
+    sets = []
+    for k, sz in enumerate(sizes):
+        sets.append(rng.integers(0, 1 << U, sz, dtype=np.uint64))
+        if k % 3 == 1:
+            sets.append(np.zeros(0, np.uint64))  # an empty set at this boundary
+    # shared IDs, so that rows of several samples exist
+    pool = rng.integers(0, 1 << U, 64, dtype=np.uint64)
+    for st in sets:
+        if st.size:
+            st[: min(st.size, 5)] = rng.choice(pool, min(st.size, 5))
+    ids, off = csr(sets)
+    assert ids.size == N
+    ref = oracle.all_pairs(ids, off)
+    res, st, names = encode_timed(ids, off, U)
+    assert_matches(res, ref)
+    assert "radix_onesweep" in names and "count_digits" in names
+
+
 def test_every_id_bit_sorted_globally():
     """A small universe and many entries (U = 8, 90,000 entries with repeats):
     the global sort covers every ID bit, so each bucket is one ID with its
