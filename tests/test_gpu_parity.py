@@ -262,6 +262,43 @@ def test_first_sort_pass_forms_the_keys(monkeypatch, declined):
         assert "build_keys" not in names and "radix_onesweep" in names
 
 
+def test_concurrent_encodes_on_two_streams():
+    """Two host threads encode different collections on their own streams at
+    once (each encode puts its row-list pairs on the library's side stream
+    while it packs on its own stream); both results are the oracle's."""
+    import threading
+
+    cases = []
+    for k, name in enumerate(("paperlike", "precision")):
+        spec = synth.scaled(synth.workload(name), **SCALED[name])
+        ids, off = synth.generate(spec)
+        cases.append((spec, ids, off, oracle.all_pairs(ids, off)))
+    results, errors = [None, None], []
+
+    def work(k):
+        try:
+            spec, ids, off, _ = cases[k]
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for _ in range(3):
+                    db, _ = jas.encode(dev(ids), dev(off), universe_bits=spec.universe_bits, dense_min_degree=6)
+                    out = jas.gram(db)
+                    st.synchronize()
+                    results[k] = {key: v.cpu().numpy() for key, v in out.items()}
+                    db.close()
+        except Exception as e:  # reported by the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        assert_matches(results[k], cases[k][3])
+
+
 @pytest.mark.parametrize("N", [6145, 8192, 8193, 16384, 16385, 24577])
 def test_scatter_tile_edges(N):
     """Entry counts around the single-pass scatter's 8192-entry tiles (the
